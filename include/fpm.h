@@ -1,0 +1,236 @@
+/*
+ * fpm.h - C ABI of libfpm, the MI355X (gfx950) hot path of Batch-FPM
+ * (random batch-update Fourier ptychography, arXiv 2408.13782).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Sizes.  N = n_lr is the low-resolution (LR) image side, s = upsample,
+ *   M = s*N the high-resolution (HR) side. Supported N: 64, 128, 256, 512.
+ *
+ * Spectrum O.  complex [M][M] row-major (row = k_y, column = k_x), centred
+ *   (zero frequency at [M/2][M/2]) and orthonormally scaled:
+ *   O = fftshift(fft2(o)) / M for the HR object o (Sec. 2.1, Eq. 1).
+ *
+ * Pupil P.  complex [N][N], centred like O. Its support is the disk
+ *   |u| <= NA/lambda (in spectral pixels); entries off the support are
+ *   ignored on input and never written by gradients.
+ *
+ * LED windows.  The plan owns the LED table: int32 [n_led][2] spectral
+ *   offsets (row, col) s_b = round(k_b / dk). LED b reads the N x N window
+ *   of O whose top-left corner is (M/2 - N/2) + s_b (this is O(k - k_m) of
+ *   Eq. 2 with k_m the illumination propagation direction).
+ *
+ * Images.  Measured amplitudes A = sqrt(I), float [n_led][N][N] natural
+ *   order, indexed by LED id. Batches are int32 device arrays of LED ids.
+ *
+ * Loss (Eq. 5, amplitude form, summed over the batch as in Eq. 13):
+ *   L = sum_b sum_r (sqrt(gamma_b) |psi_b(r)| - A_b(r))^2,
+ *   psi_b = (N^2/M) ifft2(ifftshift(C_b * P)), C_b = window of O.
+ * Gradients are real gradients written as complex numbers,
+ *   g = dL/dRe + i dL/dIm, accumulated (+=) into caller buffers.
+ *
+ * Memory.  Every pointer argument except `desc`, `shifts_host` and the
+ *   output `plan` handle is DEVICE memory on the current HIP device, owned by
+ *   the caller. The plan owns only its scratch (sized at creation from N, M
+ *   and max_batch). No entry point allocates after plan creation.
+ *
+ * Streams.  `stream` is a hipStream_t passed as void* (NULL = default
+ *   stream). Calls enqueue kernels and return without synchronising;
+ *   results are ready when the stream reaches them. Calls on one plan must
+ *   not overlap on different streams (they share the plan's scratch).
+ *
+ * Errors.  Every call returns FPM_OK (0) or a negative code; arguments are
+ *   validated on the host before any launch, so a failed call has enqueued
+ *   nothing. fpm_strerror() names the code; fpm_last_error() gives a
+ *   human-readable message for the last failure on the calling thread.
+ */
+#ifndef FPM_H
+#define FPM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FPM_OK = 0,
+  FPM_EINVAL = -1,        /* bad size, null required pointer, B > max_batch ... */
+  FPM_ENOMEM = -2,        /* device allocation failed at plan creation */
+  FPM_EHIP = -3,          /* a HIP runtime call failed */
+  FPM_EUNSUPPORTED = -4   /* N or M outside the compiled set */
+};
+
+typedef struct fpm_plan fpm_plan;
+
+/* Interleaved complex float (8 bytes, same layout as float2 / std::complex<float>). */
+typedef struct { float re, im; } fpm_c32;
+
+/* Optics and sizes of one reconstruction problem (Sec. 2.1, Sec. 3). */
+typedef struct {
+  int32_t n_lr;          /* N */
+  int32_t upsample;      /* s, M = s N (M <= 4096) */
+  int32_t n_led;         /* rows of the LED table */
+  int32_t max_batch;     /* largest B any call on this plan will pass */
+  double wavelength_um;  /* lambda */
+  double na;             /* objective numerical aperture */
+  double mag;            /* objective magnification */
+  double pixel_um;       /* camera pixel pitch; object-plane pitch = pixel/mag */
+} fpm_desc;
+
+/* Read-only facts about a plan, filled by fpm_plan_info(). */
+typedef struct {
+  int32_t n_lr, m_hr, n_led, max_batch;
+  int32_t support_px;      /* |S|: pixels of the pupil disk */
+  int32_t support_rows;    /* rows of the pupil grid that meet the disk */
+  int32_t adam_tiles;      /* 32 x 32 HR tiles covering the union of windows */
+  double pupil_radius_px;  /* NA / lambda / dk */
+  double dk;               /* spectral pitch, 1/um */
+} fpm_info;
+
+/*
+ * Create a plan. `shifts_host` is HOST memory, int32 [n_led][2] (row, col)
+ * spectral offsets; it is copied. Every window must lie inside the HR grid
+ * (FPM_EINVAL otherwise). The plan records the current HIP device.
+ */
+int fpm_plan_create(const fpm_desc* desc, const int32_t* shifts_host, fpm_plan** plan);
+int fpm_plan_destroy(fpm_plan* plan);
+int fpm_plan_info(const fpm_plan* plan, fpm_info* info);
+const char* fpm_strerror(int code);
+const char* fpm_last_error(void);
+
+/* Square LED grid below the sample and its errors (Sec. 2.1; Sec. 2.2). */
+typedef struct {
+  int32_t n_side;       /* LEDs per side; ids run row-major */
+  double pitch_mm;      /* LED spacing */
+  double height_mm;     /* LED plane to sample distance */
+  double shift_x_mm, shift_y_mm;   /* lateral offset of the whole array */
+  double rot_rad;       /* in-plane rotation of the array */
+  double dh_mm;         /* height error */
+  double roi_x_mm, roi_y_mm;       /* sample point (field-of-view position) */
+} fpm_led_grid;
+
+/*
+ * LED geometry -> spectral offsets (Sec. 2.1, k_m = sin(theta)/lambda), in
+ * FP64 on the host. LED (column i, row j) offsets from the grid centre sits
+ * at x = p(i cos r - j sin r) + dx, y = p(i sin r + j cos r) + dy, height
+ * H = h + dh; with d the LED-to-sample distance, k = ((x - x_s), (y - y_s)) / (lambda d)
+ * and the offset in spectral pixels is s = k / dk, dk = 1 / (N pixel/mag).
+ * All outputs are HOST arrays [n_side^2][2] in (row, col) order, each nullable:
+ * k_out in 1/um, s_out fractional pixels, nearest_out = floor(s + 1/2).
+ */
+int fpm_led_shifts(const fpm_desc* desc, const fpm_led_grid* grid, double* k_out,
+                   double* s_out, int32_t* nearest_out);
+
+/*
+ * Pupil with aberrations and defocus (Eq. 3 with H folded into P):
+ *   P(u) = mask(u) exp(i (sum_{j<n_zern} c_j Z_j(u) + z kappa(u))),
+ *   kappa(u) = 2 pi (sqrt(1/lambda^2 - |k|^2) - 1/lambda), k = u dk,
+ * Z_j the OSA/ANSI Zernike terms (unit RMS on the disk, rho = |u| / R).
+ * coeffs: float [n_zern] (n_zern <= 15) or NULL (all zero);
+ * z_um: float [1] or NULL (zero). P_out: complex [N][N], zero off the disk.
+ */
+int fpm_pupil(fpm_plan* plan, const float* coeffs, int32_t n_zern, const float* z_um,
+              fpm_c32* P_out, void* stream);
+
+/*
+ * Forward model (Eq. 3): for each LED id leds[b], b < B,
+ *   amp_out[b]   = sqrt(gamma[led]) |psi_b|      float [B][N][N]
+ *   field_out[b] = psi_b                          complex [B][N][N] (nullable)
+ * gamma: float [n_led] or NULL (all ones).
+ */
+int fpm_forward(fpm_plan* plan, const fpm_c32* O, const fpm_c32* P, const int32_t* leds,
+                int32_t B, const float* gamma, float* amp_out, fpm_c32* field_out,
+                void* stream);
+
+/*
+ * Loss and adjoint of one random batch (Eqs. 5 and 13):
+ *   gO[w_b + u] += conj(P(u)) g_Phi_b(u)     (atomic scatter-add, complex [M][M])
+ *   gP[u]       += conj(C_b(u)) g_Phi_b(u)   (nullable, complex [N][N], disk only)
+ *   loss[0]     += L                         (nullable, double, device)
+ * with g_Phi_b = (1/M) fftshift(fft2(2 sqrt(gamma) e psi/|psi|)),
+ * e = sqrt(gamma)|psi| - A (psi/|psi| taken as 0 where psi = 0).
+ * meas_amp: float [n_led][N][N]. The summation order of the atomics is not
+ * fixed, so results agree with a sequential sum to rounding only.
+ */
+int fpm_backward(fpm_plan* plan, const fpm_c32* O, const fpm_c32* P, const int32_t* leds,
+                 int32_t B, const float* gamma, const float* meas_amp, fpm_c32* gO,
+                 fpm_c32* gP, double* loss, void* stream);
+
+/*
+ * Projection of a pupil gradient onto its phase parameters:
+ *   g_theta(u) = Im(gP(u) conj(P(u))),
+ *   g_par[j] += sum_u g_theta(u) Z_j(u)  (j < 15),  g_par[15] += sum_u g_theta(u) kappa(u)
+ * in FP64. g_par: double [16]. gP is read only.
+ */
+int fpm_pupil_grad(fpm_plan* plan, const fpm_c32* gP, const fpm_c32* P, double* g_par,
+                   void* stream);
+
+/* Adam hyper-parameters and learning rates (torch.optim.Adam semantics). */
+typedef struct {
+  float lr_object, lr_zernike, lr_z;
+  float beta1, beta2, eps;
+  int32_t learn_zernike;   /* update coeffs[1..14]; the piston coeffs[0] is a global
+                              phase with zero gradient and is held fixed */
+  int32_t learn_z;         /* update z_um */
+} fpm_hparams;
+
+/*
+ * Device-resident optimiser state of one reconstruction (all caller-owned):
+ * O, m_O, v_O, g_O: complex [M][M] (m, v per real component; g_O must be zero
+ * before the first step and is left zero by every step);
+ * P: complex [N][N] pupil (input if the pupil is fixed, rebuilt otherwise);
+ * coeffs/m_c/v_c: float [15]; z_um/m_z/v_z: float [1] (may be NULL when not
+ * learned); g_par: double [16] accumulator, zero on entry, left zero;
+ * loss: double [1] or NULL (+= the batch loss).
+ * `t` is the number of Adam steps already taken; fpm_step increments it.
+ */
+typedef struct {
+  fpm_c32* O; fpm_c32* m_O; fpm_c32* v_O; fpm_c32* g_O;
+  fpm_c32* P;
+  float* coeffs; float* m_c; float* v_c;
+  float* z_um; float* m_z; float* v_z;
+  double* g_par;
+  double* loss;
+  int32_t t;
+} fpm_state;
+
+/*
+ * One random-batch update (Eq. 13): rebuild P from (coeffs, z) when either
+ * is learned, loss and gradients of the batch, pupil-parameter projection,
+ * then Adam on the object (over the union of LED windows; elsewhere the
+ * gradient is identically zero and Adam leaves O unchanged) and on the
+ * learned pupil parameters.
+ */
+int fpm_step(fpm_plan* plan, fpm_state* state, const fpm_hparams* hp, const int32_t* leds,
+             int32_t B, const float* gamma, const float* meas_amp, void* stream);
+
+/*
+ * HR object <-> spectrum (Sec. 2.1, Eq. 1) with the orthonormal scaling:
+ *   direction +1: O = fftshift(fft2(o)) / M;   direction -1: o = ifft2(ifftshift(O)) * M.
+ * in, out: complex [M][M]; in == out is allowed.
+ */
+int fpm_hr_transform(fpm_plan* plan, const fpm_c32* in, fpm_c32* out, int32_t direction,
+                     void* stream);
+
+/*
+ * Initial value (Sec. 2.3): spectrum of the bilinearly upsampled amplitude
+ * image `centre_amp` (float [N][N], pixel-centre aligned, clamped borders),
+ * zero phase. O_out: complex [M][M].
+ */
+int fpm_init_spectrum(fpm_plan* plan, const float* centre_amp, fpm_c32* O_out, void* stream);
+
+/*
+ * Digital refocusing (Abstract; Sec. 3.3): for each of nz distances z_um[i]
+ * (device float [nz]), out[i] = ifft2(ifftshift(O H(z_i))) * M with
+ * H = exp(i z kappa(k)) over the HR spectrum, 0 where |k| > 1/lambda.
+ * out: complex [nz][M][M].
+ */
+int fpm_refocus(fpm_plan* plan, const fpm_c32* O, const float* z_um, int32_t nz, fpm_c32* out,
+                void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FPM_H */

@@ -499,9 +499,13 @@ def step(state: SolveState, cfg: SolveConfig, mask, zern, kappa, shifts, leds, m
     if cfg.learn_pupil or cfg.learn_z:
         g_c, g_z, _ = pupil_param_grads(gr.g_P, P, zern, kappa)
         if cfg.learn_pupil:
-            state.coeffs, state.m_c, state.v_c = adam_update(
-                state.coeffs, g_c, state.m_c, state.v_c, t, cfg.lr_zernike,
-                cfg.beta1, cfg.beta2, cfg.eps)
+            # The piston term (j = 0) is a global phase: its gradient is identically
+            # zero, so it is held at its value rather than driven by rounding noise.
+            c, mc, vc = adam_update(state.coeffs[1:], g_c[1:], state.m_c[1:], state.v_c[1:],
+                                    t, cfg.lr_zernike, cfg.beta1, cfg.beta2, cfg.eps)
+            state.coeffs = np.concatenate([state.coeffs[:1], c])
+            state.m_c = np.concatenate([state.m_c[:1], mc])
+            state.v_c = np.concatenate([state.v_c[:1], vc])
         if cfg.learn_z:
             zz, mz, vz = adam_update(np.array([state.z_um]), np.array([g_z]),
                                      np.array([state.m_z]), np.array([state.v_z]), t,

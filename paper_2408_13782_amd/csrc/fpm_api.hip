@@ -1,0 +1,520 @@
+// fpm_api.hip - host side of libfpm: plans, argument validation, launches.
+// The C ABI is declared in include/fpm.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fpm.h"
+#include "fpm_aux.hpp"
+#include "fpm_kernels.hpp"
+
+using namespace fpm;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define FPM_HIP(call)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (call);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(FPM_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));    \
+  } while (0)
+
+#define FPM_REQUIRE(cond, msg) \
+  do {                         \
+    if (!(cond)) return fail(FPM_EINVAL, msg); \
+  } while (0)
+
+bool lr_supported(int n) { return n == 64 || n == 128 || n == 256 || n == 512; }
+bool hr_supported(int m) { return m == 256 || m == 512 || m == 1024 || m == 2048; }
+
+std::vector<float2> twiddles(int n) {
+  std::vector<float2> tw(n);
+  for (int m = 0; m < n; ++m) {
+    const double a = -2.0 * M_PI * (double)m / (double)n;
+    tw[m] = make_float2((float)std::cos(a), (float)std::sin(a));
+  }
+  return tw;
+}
+
+template <class T>
+int upload(T** dst, const T* src, size_t count) {
+  if (hipMalloc((void**)dst, count * sizeof(T)) != hipSuccess) {
+    *dst = nullptr;
+    return fail(FPM_ENOMEM, "hipMalloc failed");
+  }
+  if (src) FPM_HIP(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
+  return FPM_OK;
+}
+
+}  // namespace
+
+struct fpm_plan {
+  int device = 0;
+  int N = 0, s = 0, M = 0, n_led = 0, max_batch = 0;
+  double lambda = 0, na = 0, mag = 0, pixel = 0, dk = 0, radius = 0;
+  int ky_lo = 0, ky_hi = -1, nrows = 0, support_px = 0;
+  int n_tiles = 0;
+  bool hr_ok = false;
+  std::vector<int2> shifts_h;
+  int2* rowext = nullptr;     // [N] (first, last) disk column of each pupil row
+  int2* shifts = nullptr;     // [n_led]
+  float2* twN = nullptr;      // [N]
+  float2* twM = nullptr;      // [M] when the HR transforms are available
+  float2* X = nullptr;        // [max_batch][N][N] row/column scratch
+  float2* gP = nullptr;       // [N][N] pupil-gradient accumulator for fpm_step
+  int2* tiles = nullptr;      // [n_tiles] 32 x 32 HR tiles covered by some window
+};
+
+namespace {
+
+void plan_free(fpm_plan* p) {
+  (void)hipFree(p->rowext);
+  (void)hipFree(p->shifts);
+  (void)hipFree(p->twN);
+  (void)hipFree(p->twM);
+  (void)hipFree(p->X);
+  (void)hipFree(p->gP);
+  (void)hipFree(p->tiles);
+  delete p;
+}
+
+int check_device(const fpm_plan* p) {
+  int dev = -1;
+  FPM_HIP(hipGetDevice(&dev));
+  if (dev != p->device) return fail(FPM_EINVAL, "current HIP device differs from the plan's device");
+  return FPM_OK;
+}
+
+PupilGeom pupil_geom(const fpm_plan* p) {
+  PupilGeom g;
+  g.n = p->N;
+  g.inv_r = 1.0 / p->radius;
+  g.dk2 = p->dk * p->dk;
+  g.inv_l = 1.0 / p->lambda;
+  return g;
+}
+
+int check_batch(const fpm_plan* p, const int32_t* leds, int32_t B) {
+  FPM_REQUIRE(B >= 0, "batch size must be >= 0");
+  FPM_REQUIRE(B <= p->max_batch, "batch size exceeds the plan's max_batch");
+  FPM_REQUIRE(B == 0 || leds != nullptr, "leds must not be NULL");
+  return FPM_OK;
+}
+
+// Loss and gradient launches shared by fpm_backward and fpm_step.
+template <int N>
+int launch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t* leds, int B,
+                    const float* gamma, const float* A, float2* gO, float2* gP, double* loss,
+                    hipStream_t st) {
+  constexpr int Lr = kRowThreads / Plan1D<N>::T;
+  constexpr int Lc = ColLines<N>::value;
+  const int slots = (B + kXcds - 1) / kXcds * kXcds;
+  const int row_chunks = (p->nrows + Lr - 1) / Lr;
+  const int col_groups = N / Lc;
+  rows_forward<N><<<slots * row_chunks, kRowThreads, 0, st>>>(
+      O, p->M, P, p->rowext, p->ky_lo, p->nrows, p->shifts, leds, B, p->n_led, row_chunks, p->X,
+      p->twN);
+  cols<N, false><<<slots * col_groups, Lc * Plan1D<N>::T, 0, st>>>(
+      p->X, A, gamma, leds, B, p->n_led, p->ky_lo, p->ky_hi, col_groups, loss, nullptr, nullptr, p->twN,
+      1.0f / p->M);
+  rows_backward<N><<<slots * row_chunks, kRowThreads, 0, st>>>(
+      p->X, O, p->M, P, p->rowext, p->ky_lo, p->nrows, p->shifts, leds, B, p->n_led, row_chunks, gO, gP,
+      p->twN);
+  FPM_HIP(hipGetLastError());
+  return FPM_OK;
+}
+
+template <int N>
+int launch_forward(fpm_plan* p, const float2* O, const float2* P, const int32_t* leds, int B,
+                   const float* gamma, float* amp, float2* field, hipStream_t st) {
+  constexpr int Lr = kRowThreads / Plan1D<N>::T;
+  constexpr int Lc = ColLines<N>::value;
+  const int slots = (B + kXcds - 1) / kXcds * kXcds;
+  const int row_chunks = (p->nrows + Lr - 1) / Lr;
+  const int col_groups = N / Lc;
+  rows_forward<N><<<slots * row_chunks, kRowThreads, 0, st>>>(
+      O, p->M, P, p->rowext, p->ky_lo, p->nrows, p->shifts, leds, B, p->n_led, row_chunks, p->X,
+      p->twN);
+  cols<N, true><<<slots * col_groups, Lc * Plan1D<N>::T, 0, st>>>(
+      p->X, nullptr, gamma, leds, B, p->n_led, p->ky_lo, p->ky_hi, col_groups, nullptr, amp, field,
+      p->twN, 1.0f / p->M);
+  FPM_HIP(hipGetLastError());
+  return FPM_OK;
+}
+
+int dispatch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t* leds, int B,
+                      const float* gamma, const float* A, float2* gO, float2* gP, double* loss,
+                      hipStream_t st) {
+  switch (p->N) {
+    case 64: return launch_backward<64>(p, O, P, leds, B, gamma, A, gO, gP, loss, st);
+    case 128: return launch_backward<128>(p, O, P, leds, B, gamma, A, gO, gP, loss, st);
+    case 256: return launch_backward<256>(p, O, P, leds, B, gamma, A, gO, gP, loss, st);
+    case 512: return launch_backward<512>(p, O, P, leds, B, gamma, A, gO, gP, loss, st);
+  }
+  return fail(FPM_EUNSUPPORTED, "unsupported N");
+}
+
+template <int M>
+int launch_hr(fpm_plan* p, HrArgs a, int row_mode, int dir, hipStream_t st) {
+  constexpr int Lr = HrRowLines<M>::value;
+  constexpr int Lc = HrColLines<M>::value;
+  constexpr int T = Plan1D<M>::T;
+  switch (row_mode) {
+    case kRowFwd: hr_rows<M, kRowFwd><<<M / Lr, Lr * T, 0, st>>>(a, p->twM); break;
+    case kRowInv: hr_rows<M, kRowInv><<<M / Lr, Lr * T, 0, st>>>(a, p->twM); break;
+    case kRowInit: hr_rows<M, kRowInit><<<M / Lr, Lr * T, 0, st>>>(a, p->twM); break;
+    case kRowRefocus: hr_rows<M, kRowRefocus><<<M / Lr, Lr * T, 0, st>>>(a, p->twM); break;
+  }
+  if (dir < 0)
+    hr_cols<M, -1><<<M / Lc, Lc * T, 0, st>>>(a.out, p->twM);
+  else
+    hr_cols<M, +1><<<M / Lc, Lc * T, 0, st>>>(a.out, p->twM);
+  FPM_HIP(hipGetLastError());
+  return FPM_OK;
+}
+
+int dispatch_hr(fpm_plan* p, HrArgs a, int row_mode, int dir, hipStream_t st) {
+  switch (p->M) {
+    case 256: return launch_hr<256>(p, a, row_mode, dir, st);
+    case 512: return launch_hr<512>(p, a, row_mode, dir, st);
+    case 1024: return launch_hr<1024>(p, a, row_mode, dir, st);
+    case 2048: return launch_hr<2048>(p, a, row_mode, dir, st);
+  }
+  return fail(FPM_EUNSUPPORTED, "HR transforms support M in {256, 512, 1024, 2048}");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* fpm_strerror(int code) {
+  switch (code) {
+    case FPM_OK: return "ok";
+    case FPM_EINVAL: return "invalid argument";
+    case FPM_ENOMEM: return "out of device memory";
+    case FPM_EHIP: return "HIP runtime error";
+    case FPM_EUNSUPPORTED: return "unsupported size";
+  }
+  return "unknown error";
+}
+
+const char* fpm_last_error(void) { return g_last_error.c_str(); }
+
+int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** out) {
+  FPM_REQUIRE(d && shifts_host && out, "desc, shifts_host and plan must not be NULL");
+  *out = nullptr;
+  if (!lr_supported(d->n_lr)) return fail(FPM_EUNSUPPORTED, "n_lr must be 64, 128, 256 or 512");
+  FPM_REQUIRE(d->upsample >= 1 && (int64_t)d->upsample * d->n_lr <= 4096, "upsample out of range");
+  FPM_REQUIRE(d->n_led >= 1 && d->max_batch >= 1, "n_led and max_batch must be >= 1");
+  FPM_REQUIRE(d->wavelength_um > 0 && d->na > 0 && d->mag > 0 && d->pixel_um > 0,
+              "optics must be positive");
+  fpm_plan* p = new fpm_plan();
+  FPM_HIP(hipGetDevice(&p->device));
+  p->N = d->n_lr;
+  p->s = d->upsample;
+  p->M = d->n_lr * d->upsample;
+  p->n_led = d->n_led;
+  p->max_batch = d->max_batch;
+  p->lambda = d->wavelength_um;
+  p->na = d->na;
+  p->mag = d->mag;
+  p->pixel = d->pixel_um;
+  const double dx = d->pixel_um / d->mag;
+  p->dk = 1.0 / (p->N * dx);
+  p->radius = d->na / d->wavelength_um / p->dk;
+  if (!(p->radius < p->N / 2 - 1)) {
+    delete p;
+    return fail(FPM_EINVAL, "pupil disk does not fit the N x N pupil grid");
+  }
+  // pupil disk: |u|^2 <= R^2, per-row column extents
+  std::vector<int2> ext(p->N);
+  const double r2 = p->radius * p->radius;
+  for (int ky = 0; ky < p->N; ++ky) {
+    const double uy = ky - p->N / 2;
+    int lo = p->N, hi = -1;
+    for (int kx = 0; kx < p->N; ++kx) {
+      const double ux = kx - p->N / 2;
+      if (uy * uy + ux * ux <= r2) {
+        lo = std::min(lo, kx);
+        hi = std::max(hi, kx);
+        ++p->support_px;
+      }
+    }
+    ext[ky] = make_int2(lo, hi);
+    if (hi >= lo) {
+      if (p->nrows == 0) p->ky_lo = ky;
+      p->ky_hi = ky;
+      ++p->nrows;
+    }
+  }
+  // LED windows must lie inside the HR grid
+  p->shifts_h.resize(p->n_led);
+  const int base = p->M / 2 - p->N / 2;
+  for (int i = 0; i < p->n_led; ++i) {
+    const int sr = shifts_host[2 * i], sc = shifts_host[2 * i + 1];
+    if (base + sr < 0 || base + sr + p->N > p->M || base + sc < 0 || base + sc + p->N > p->M) {
+      delete p;
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "LED %d: window (%d, %d) leaves the %d x %d HR grid", i, sr,
+                    sc, p->M, p->M);
+      return fail(FPM_EINVAL, buf);
+    }
+    p->shifts_h[i] = make_int2(sr, sc);
+  }
+  // HR tiles touched by some window (Adam runs over these only)
+  const int nt = (p->M + 31) / 32;
+  std::vector<uint8_t> cover((size_t)nt * nt, 0);
+  for (int i = 0; i < p->n_led; ++i) {
+    const int2 s = p->shifts_h[i];
+    for (int ky = p->ky_lo; ky <= p->ky_hi; ++ky) {
+      const int row = base + s.x + ky;
+      const int c0 = base + s.y + ext[ky].x, c1 = base + s.y + ext[ky].y;
+      for (int tc = c0 / 32; tc <= c1 / 32; ++tc) cover[(size_t)(row / 32) * nt + tc] = 1;
+    }
+  }
+  std::vector<int2> tiles;
+  for (int tr = 0; tr < nt; ++tr)
+    for (int tc = 0; tc < nt; ++tc)
+      if (cover[(size_t)tr * nt + tc]) tiles.push_back(make_int2(tr, tc));
+  p->n_tiles = (int)tiles.size();
+  p->hr_ok = hr_supported(p->M);
+
+  int rc = FPM_OK;
+  const auto twn = twiddles(p->N);
+  if ((rc = upload(&p->rowext, ext.data(), ext.size())) ||
+      (rc = upload(&p->shifts, p->shifts_h.data(), p->shifts_h.size())) ||
+      (rc = upload(&p->twN, twn.data(), twn.size())) ||
+      (rc = upload<float2>(&p->X, nullptr, (size_t)p->max_batch * p->N * p->N)) ||
+      (rc = upload<float2>(&p->gP, nullptr, (size_t)p->N * p->N)) ||
+      (rc = upload(&p->tiles, tiles.data(), std::max<size_t>(tiles.size(), 1)))) {
+    plan_free(p);
+    return rc;
+  }
+  if (p->hr_ok) {
+    const auto twm = twiddles(p->M);
+    if ((rc = upload(&p->twM, twm.data(), twm.size()))) {
+      plan_free(p);
+      return rc;
+    }
+  }
+  if (hipMemset(p->gP, 0, (size_t)p->N * p->N * sizeof(float2)) != hipSuccess) {
+    plan_free(p);
+    return fail(FPM_EHIP, "hipMemset failed");
+  }
+  *out = p;
+  return FPM_OK;
+}
+
+int fpm_plan_destroy(fpm_plan* p) {
+  if (!p) return FPM_OK;
+  plan_free(p);
+  return FPM_OK;
+}
+
+int fpm_plan_info(const fpm_plan* p, fpm_info* info) {
+  FPM_REQUIRE(p && info, "plan and info must not be NULL");
+  info->n_lr = p->N;
+  info->m_hr = p->M;
+  info->n_led = p->n_led;
+  info->max_batch = p->max_batch;
+  info->support_px = p->support_px;
+  info->support_rows = p->nrows;
+  info->adam_tiles = p->n_tiles;
+  info->pupil_radius_px = p->radius;
+  info->dk = p->dk;
+  return FPM_OK;
+}
+
+int fpm_led_shifts(const fpm_desc* d, const fpm_led_grid* g, double* k_out, double* s_out,
+                   int32_t* nearest_out) {
+  FPM_REQUIRE(d && g, "desc and grid must not be NULL");
+  FPM_REQUIRE(g->n_side >= 1 && d->n_lr >= 1, "n_side and n_lr must be >= 1");
+  FPM_REQUIRE(d->wavelength_um > 0 && d->mag > 0 && d->pixel_um > 0, "optics must be positive");
+  const double dk = 1.0 / (d->n_lr * (d->pixel_um / d->mag));
+  const double c = (g->n_side - 1) / 2.0;
+  const double cr = std::cos(g->rot_rad), sr = std::sin(g->rot_rad);
+  for (int row = 0; row < g->n_side; ++row) {
+    for (int col = 0; col < g->n_side; ++col) {
+      const double i = col - c, j = row - c;
+      const double x = g->pitch_mm * (i * cr - j * sr) + g->shift_x_mm - g->roi_x_mm;
+      const double y = g->pitch_mm * (i * sr + j * cr) + g->shift_y_mm - g->roi_y_mm;
+      const double h = g->height_mm + g->dh_mm;
+      const double dist = std::sqrt(x * x + y * y + h * h);
+      const double ky = y / dist / d->wavelength_um, kx = x / dist / d->wavelength_um;
+      const int led = row * g->n_side + col;
+      if (k_out) { k_out[2 * led] = ky; k_out[2 * led + 1] = kx; }
+      if (s_out) { s_out[2 * led] = ky / dk; s_out[2 * led + 1] = kx / dk; }
+      if (nearest_out) {
+        nearest_out[2 * led] = (int32_t)std::floor(ky / dk + 0.5);
+        nearest_out[2 * led + 1] = (int32_t)std::floor(kx / dk + 0.5);
+      }
+    }
+  }
+  return FPM_OK;
+}
+
+int fpm_pupil(fpm_plan* p, const float* coeffs, int32_t n_zern, const float* z_um,
+              fpm_c32* P_out, void* stream) {
+  FPM_REQUIRE(p && P_out, "plan and P_out must not be NULL");
+  FPM_REQUIRE(n_zern >= 0 && n_zern <= kZern, "n_zern must be in [0, 15]");
+  if (int rc = check_device(p)) return rc;
+  const int nn = p->N * p->N;
+  pupil_build<<<(nn + 255) / 256, 256, 0, (hipStream_t)stream>>>(
+      pupil_geom(p), p->rowext, coeffs, n_zern, z_um, reinterpret_cast<float2*>(P_out));
+  FPM_HIP(hipGetLastError());
+  return FPM_OK;
+}
+
+int fpm_forward(fpm_plan* p, const fpm_c32* O, const fpm_c32* P, const int32_t* leds, int32_t B,
+                const float* gamma, float* amp_out, fpm_c32* field_out, void* stream) {
+  FPM_REQUIRE(p && O && P && amp_out, "plan, O, P and amp_out must not be NULL");
+  if (int rc = check_batch(p, leds, B)) return rc;
+  if (int rc = check_device(p)) return rc;
+  if (B == 0) return FPM_OK;
+  const auto* o = reinterpret_cast<const float2*>(O);
+  const auto* pp = reinterpret_cast<const float2*>(P);
+  auto* f = reinterpret_cast<float2*>(field_out);
+  hipStream_t st = (hipStream_t)stream;
+  switch (p->N) {
+    case 64: return launch_forward<64>(p, o, pp, leds, B, gamma, amp_out, f, st);
+    case 128: return launch_forward<128>(p, o, pp, leds, B, gamma, amp_out, f, st);
+    case 256: return launch_forward<256>(p, o, pp, leds, B, gamma, amp_out, f, st);
+    case 512: return launch_forward<512>(p, o, pp, leds, B, gamma, amp_out, f, st);
+  }
+  return fail(FPM_EUNSUPPORTED, "unsupported N");
+}
+
+int fpm_backward(fpm_plan* p, const fpm_c32* O, const fpm_c32* P, const int32_t* leds, int32_t B,
+                 const float* gamma, const float* meas_amp, fpm_c32* gO, fpm_c32* gP,
+                 double* loss, void* stream) {
+  FPM_REQUIRE(p && O && P && meas_amp && gO, "plan, O, P, meas_amp and gO must not be NULL");
+  if (int rc = check_batch(p, leds, B)) return rc;
+  if (int rc = check_device(p)) return rc;
+  if (B == 0) return FPM_OK;
+  return dispatch_backward(p, reinterpret_cast<const float2*>(O), reinterpret_cast<const float2*>(P),
+                           leds, B, gamma, meas_amp, reinterpret_cast<float2*>(gO),
+                           reinterpret_cast<float2*>(gP), loss, (hipStream_t)stream);
+}
+
+int fpm_pupil_grad(fpm_plan* p, const fpm_c32* gP, const fpm_c32* P, double* g_par,
+                   void* stream) {
+  FPM_REQUIRE(p && gP && P && g_par, "plan, gP, P and g_par must not be NULL");
+  if (int rc = check_device(p)) return rc;
+  const int nn = p->N * p->N;
+  pupil_grad<<<(nn + 255) / 256, 256, 0, (hipStream_t)stream>>>(
+      pupil_geom(p), p->rowext, const_cast<float2*>(reinterpret_cast<const float2*>(gP)),
+      reinterpret_cast<const float2*>(P), g_par, 0);
+  FPM_HIP(hipGetLastError());
+  return FPM_OK;
+}
+
+int fpm_step(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_t* leds, int32_t B,
+             const float* gamma, const float* meas_amp, void* stream) {
+  FPM_REQUIRE(p && s && hp, "plan, state and hparams must not be NULL");
+  FPM_REQUIRE(s->O && s->m_O && s->v_O && s->g_O && s->P && meas_amp,
+              "state O, m_O, v_O, g_O, P and meas_amp must not be NULL");
+  FPM_REQUIRE(B >= 1, "fpm_step needs a non-empty batch");
+  if (int rc = check_batch(p, leds, B)) return rc;
+  if (int rc = check_device(p)) return rc;
+  const bool learn_c = hp->learn_zernike != 0, learn_z = hp->learn_z != 0;
+  const bool learn_p = learn_c || learn_z;
+  if (learn_c) FPM_REQUIRE(s->coeffs && s->m_c && s->v_c, "Zernike state must not be NULL");
+  if (learn_z) FPM_REQUIRE(s->z_um && s->m_z && s->v_z, "defocus state must not be NULL");
+  if (learn_p) FPM_REQUIRE(s->g_par, "g_par must not be NULL when the pupil is learned");
+  FPM_REQUIRE(s->t >= 0, "t must be >= 0");
+  hipStream_t st = (hipStream_t)stream;
+  float2* P = reinterpret_cast<float2*>(s->P);
+  const int nn = p->N * p->N;
+  if (learn_p) {
+    pupil_build<<<(nn + 255) / 256, 256, 0, st>>>(pupil_geom(p), p->rowext, s->coeffs,
+                                                  s->coeffs ? kZern : 0, s->z_um, P);
+  }
+  if (int rc = dispatch_backward(p, reinterpret_cast<const float2*>(s->O), P, leds, B, gamma,
+                                 meas_amp, reinterpret_cast<float2*>(s->g_O),
+                                 learn_p ? p->gP : nullptr, s->loss, st))
+    return rc;
+  if (learn_p) {
+    pupil_grad<<<(nn + 255) / 256, 256, 0, st>>>(pupil_geom(p), p->rowext, p->gP, P, s->g_par, 1);
+  }
+  const int t = s->t + 1;
+  const double b1 = hp->beta1, b2 = hp->beta2;
+  const double bc1 = 1.0 - std::pow(b1, t), bc2 = 1.0 - std::pow(b2, t);
+  AdamCoef c;
+  c.b1 = hp->beta1;
+  c.b2 = hp->beta2;
+  c.eps = hp->eps;
+  c.step_size = (float)(hp->lr_object / bc1);
+  c.sqrt_bc2 = (float)std::sqrt(bc2);
+  adam_object<<<p->n_tiles, 256, 0, st>>>(p->tiles, p->M, reinterpret_cast<float*>(s->O),
+                                          reinterpret_cast<float*>(s->m_O),
+                                          reinterpret_cast<float*>(s->v_O),
+                                          reinterpret_cast<float*>(s->g_O), c);
+  if (learn_p) {
+    AdamScalarArgs a;
+    a.coeffs = s->coeffs; a.m_c = s->m_c; a.v_c = s->v_c; a.learn_c = learn_c;
+    a.z = s->z_um; a.m_z = s->m_z; a.v_z = s->v_z; a.learn_z = learn_z;
+    a.lr_c = hp->lr_zernike; a.lr_z = hp->lr_z;
+    a.b1 = b1; a.b2 = b2; a.eps = hp->eps; a.bc1 = bc1; a.sqrt_bc2 = std::sqrt(bc2);
+    adam_scalars<<<1, 64, 0, st>>>(a, s->g_par);
+  }
+  FPM_HIP(hipGetLastError());
+  s->t = t;
+  return FPM_OK;
+}
+
+int fpm_hr_transform(fpm_plan* p, const fpm_c32* in, fpm_c32* out, int32_t direction,
+                     void* stream) {
+  FPM_REQUIRE(p && in && out, "plan, in and out must not be NULL");
+  FPM_REQUIRE(direction == 1 || direction == -1, "direction must be +1 or -1");
+  if (!p->hr_ok) return fail(FPM_EUNSUPPORTED, "HR transforms support M in {256, 512, 1024, 2048}");
+  if (int rc = check_device(p)) return rc;
+  HrArgs a{};
+  a.in = reinterpret_cast<const float2*>(in);
+  a.out = reinterpret_cast<float2*>(out);
+  return dispatch_hr(p, a, direction > 0 ? kRowFwd : kRowInv, direction > 0 ? -1 : +1,
+                     (hipStream_t)stream);
+}
+
+int fpm_init_spectrum(fpm_plan* p, const float* centre_amp, fpm_c32* O_out, void* stream) {
+  FPM_REQUIRE(p && centre_amp && O_out, "plan, centre_amp and O_out must not be NULL");
+  if (!p->hr_ok) return fail(FPM_EUNSUPPORTED, "HR transforms support M in {256, 512, 1024, 2048}");
+  if (int rc = check_device(p)) return rc;
+  HrArgs a{};
+  a.img = centre_amp;
+  a.n = p->N;
+  a.s = p->s;
+  a.out = reinterpret_cast<float2*>(O_out);
+  return dispatch_hr(p, a, kRowInit, -1, (hipStream_t)stream);
+}
+
+int fpm_refocus(fpm_plan* p, const fpm_c32* O, const float* z_um, int32_t nz, fpm_c32* out,
+                void* stream) {
+  FPM_REQUIRE(p && O && out && (nz == 0 || z_um), "plan, O, z_um and out must not be NULL");
+  FPM_REQUIRE(nz >= 0, "nz must be >= 0");
+  if (!p->hr_ok) return fail(FPM_EUNSUPPORTED, "HR transforms support M in {256, 512, 1024, 2048}");
+  if (int rc = check_device(p)) return rc;
+  if (nz == 0) return FPM_OK;
+  for (int i = 0; i < nz; ++i) {
+    HrArgs a{};
+    a.in = reinterpret_cast<const float2*>(O);
+    a.out = reinterpret_cast<float2*>(out) + (size_t)i * p->M * p->M;
+    a.z_um = z_um + i;
+    a.dk2 = p->dk * p->dk;
+    a.inv_l = 1.0 / p->lambda;
+    if (int rc = dispatch_hr(p, a, kRowRefocus, +1, (hipStream_t)stream)) return rc;
+  }
+  return FPM_OK;
+}
+
+}  // extern "C"

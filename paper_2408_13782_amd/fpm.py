@@ -1,0 +1,282 @@
+"""Python binding of libfpm (include/fpm.h): argument marshalling only.
+
+Every computation of the hot path runs in the HIP library; torch provides
+device memory and the current stream. Loading fails loudly when the library
+has not been built: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfpm.so")
+
+FPM_OK = 0
+N_ZERN = 15
+N_PAR = 16
+
+
+class FpmError(RuntimeError):
+    pass
+
+
+class _Desc(C.Structure):
+    _fields_ = [("n_lr", C.c_int32), ("upsample", C.c_int32), ("n_led", C.c_int32),
+                ("max_batch", C.c_int32), ("wavelength_um", C.c_double), ("na", C.c_double),
+                ("mag", C.c_double), ("pixel_um", C.c_double)]
+
+
+class _Info(C.Structure):
+    _fields_ = [("n_lr", C.c_int32), ("m_hr", C.c_int32), ("n_led", C.c_int32),
+                ("max_batch", C.c_int32), ("support_px", C.c_int32),
+                ("support_rows", C.c_int32), ("adam_tiles", C.c_int32),
+                ("pupil_radius_px", C.c_double), ("dk", C.c_double)]
+
+
+class _Grid(C.Structure):
+    _fields_ = [("n_side", C.c_int32), ("pitch_mm", C.c_double), ("height_mm", C.c_double),
+                ("shift_x_mm", C.c_double), ("shift_y_mm", C.c_double), ("rot_rad", C.c_double),
+                ("dh_mm", C.c_double), ("roi_x_mm", C.c_double), ("roi_y_mm", C.c_double)]
+
+
+class _HParams(C.Structure):
+    _fields_ = [("lr_object", C.c_float), ("lr_zernike", C.c_float), ("lr_z", C.c_float),
+                ("beta1", C.c_float), ("beta2", C.c_float), ("eps", C.c_float),
+                ("learn_zernike", C.c_int32), ("learn_z", C.c_int32)]
+
+
+class _State(C.Structure):
+    _fields_ = [("O", C.c_void_p), ("m_O", C.c_void_p), ("v_O", C.c_void_p), ("g_O", C.c_void_p),
+                ("P", C.c_void_p), ("coeffs", C.c_void_p), ("m_c", C.c_void_p),
+                ("v_c", C.c_void_p), ("z_um", C.c_void_p), ("m_z", C.c_void_p),
+                ("v_z", C.c_void_p), ("g_par", C.c_void_p), ("loss", C.c_void_p),
+                ("t", C.c_int32)]
+
+
+EXPORTS = {
+    "fpm_plan_create": [C.POINTER(_Desc), C.c_void_p, C.POINTER(C.c_void_p)],
+    "fpm_plan_destroy": [C.c_void_p],
+    "fpm_plan_info": [C.c_void_p, C.POINTER(_Info)],
+    "fpm_strerror": [C.c_int],
+    "fpm_last_error": [],
+    "fpm_led_shifts": [C.POINTER(_Desc), C.POINTER(_Grid), C.c_void_p, C.c_void_p, C.c_void_p],
+    "fpm_pupil": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
+    "fpm_forward": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                    C.c_void_p, C.c_void_p, C.c_void_p],
+    "fpm_backward": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "fpm_pupil_grad": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "fpm_step": [C.c_void_p, C.POINTER(_State), C.POINTER(_HParams), C.c_void_p, C.c_int32,
+                 C.c_void_p, C.c_void_p, C.c_void_p],
+    "fpm_hr_transform": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
+    "fpm_init_spectrum": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "fpm_refocus": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libfpm.so and declare its signatures; raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise FpmError(f"{path} not found: build it with `python -m paper_2408_13782_amd.build` "
+                       "(the HIP library is required; there is no CPU fallback)")
+    lib = C.CDLL(path)
+    for name, argtypes in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = argtypes
+        fn.restype = C.c_char_p if name in ("fpm_strerror", "fpm_last_error") else C.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != FPM_OK:
+        lib = load()
+        raise FpmError(f"{lib.fpm_strerror(rc).decode()} ({rc}): {lib.fpm_last_error().decode()}")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(device=None):
+    import torch
+    return C.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _desc(n_lr, upsample, n_led, max_batch, wavelength_um, na, mag, pixel_um) -> _Desc:
+    return _Desc(n_lr, upsample, n_led, max_batch, wavelength_um, na, mag, pixel_um)
+
+
+def led_shifts(n_lr: int, wavelength_um: float, mag: float, pixel_um: float, n_side: int,
+               pitch_mm: float, height_mm: float, shift_x_mm=0.0, shift_y_mm=0.0, rot_rad=0.0,
+               dh_mm=0.0, roi_x_mm=0.0, roi_y_mm=0.0):
+    """(k [n_led,2] 1/um, s [n_led,2] fractional px, nearest [n_led,2] int32), (row, col)."""
+    lib = load()
+    n_led = n_side * n_side
+    d = _desc(n_lr, 1, n_led, 1, wavelength_um, 0.1, mag, pixel_um)
+    g = _Grid(n_side, pitch_mm, height_mm, shift_x_mm, shift_y_mm, rot_rad, dh_mm, roi_x_mm,
+              roi_y_mm)
+    k = np.zeros((n_led, 2), np.float64)
+    s = np.zeros((n_led, 2), np.float64)
+    nearest = np.zeros((n_led, 2), np.int32)
+    _check(lib.fpm_led_shifts(C.byref(d), C.byref(g), k.ctypes.data, s.ctypes.data,
+                              nearest.ctypes.data))
+    return k, s, nearest
+
+
+@dataclass
+class HParams:
+    lr_object: float = 1e-2
+    lr_zernike: float = 1e-2
+    lr_z: float = 0.1
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    learn_zernike: bool = False
+    learn_z: bool = False
+
+    def c(self) -> _HParams:
+        return _HParams(self.lr_object, self.lr_zernike, self.lr_z, self.beta1, self.beta2,
+                        self.eps, int(self.learn_zernike), int(self.learn_z))
+
+
+class State:
+    """Device-resident reconstruction state (spectrum, pupil parameters, Adam moments)."""
+
+    def __init__(self, plan: "Plan", O0, coeffs0=None, z0: float = 0.0, P0=None):
+        import torch
+        dev = O0.device
+        M, N = plan.M, plan.N
+        assert O0.shape == (M, M) and O0.dtype == torch.complex64 and O0.is_cuda
+        self.O = O0.clone().contiguous()
+        self.m_O = torch.zeros((M, M), dtype=torch.complex64, device=dev)
+        self.v_O = torch.zeros((M, M), dtype=torch.complex64, device=dev)
+        self.g_O = torch.zeros((M, M), dtype=torch.complex64, device=dev)
+        self.coeffs = torch.zeros(N_ZERN, dtype=torch.float32, device=dev)
+        if coeffs0 is not None:
+            self.coeffs.copy_(torch.as_tensor(np.asarray(coeffs0, np.float32)))
+        self.m_c = torch.zeros(N_ZERN, dtype=torch.float32, device=dev)
+        self.v_c = torch.zeros(N_ZERN, dtype=torch.float32, device=dev)
+        self.z_um = torch.full((1,), float(z0), dtype=torch.float32, device=dev)
+        self.m_z = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.v_z = torch.zeros(1, dtype=torch.float32, device=dev)
+        self.g_par = torch.zeros(N_PAR, dtype=torch.float64, device=dev)
+        self.loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        if P0 is not None:
+            self.P = P0.clone().contiguous()
+        else:
+            self.P = plan.pupil(self.coeffs, self.z_um)
+        self.t = 0
+        self._c = _State()
+
+    def c(self) -> _State:
+        s = self._c
+        s.O, s.m_O, s.v_O, s.g_O = (self.O.data_ptr(), self.m_O.data_ptr(), self.v_O.data_ptr(),
+                                    self.g_O.data_ptr())
+        s.P = self.P.data_ptr()
+        s.coeffs, s.m_c, s.v_c = self.coeffs.data_ptr(), self.m_c.data_ptr(), self.v_c.data_ptr()
+        s.z_um, s.m_z, s.v_z = self.z_um.data_ptr(), self.m_z.data_ptr(), self.v_z.data_ptr()
+        s.g_par = self.g_par.data_ptr()
+        s.loss = self.loss.data_ptr()
+        s.t = self.t
+        return s
+
+
+class Plan:
+    """One reconstruction problem's sizes, optics and LED table, with its scratch."""
+
+    def __init__(self, n_lr: int, upsample: int, shifts, max_batch: int, wavelength_um: float,
+                 na: float, mag: float, pixel_um: float):
+        lib = load()
+        shifts = np.ascontiguousarray(np.asarray(shifts, np.int32).reshape(-1, 2))
+        self.N, self.s, self.M = int(n_lr), int(upsample), int(n_lr) * int(upsample)
+        self.n_led = shifts.shape[0]
+        self.max_batch = int(max_batch)
+        self.shifts = shifts
+        d = _desc(self.N, self.s, self.n_led, self.max_batch, wavelength_um, na, mag, pixel_um)
+        h = C.c_void_p()
+        _check(lib.fpm_plan_create(C.byref(d), shifts.ctypes.data, C.byref(h)))
+        self._h = h
+        info = _Info()
+        _check(lib.fpm_plan_info(h, C.byref(info)))
+        self.info = info
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            self._lib.fpm_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- entry points -------------------------------------------------------
+
+    def pupil(self, coeffs=None, z_um=None, out=None):
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        if out is None:
+            out = torch.empty((self.N, self.N), dtype=torch.complex64, device=dev)
+        n = 0 if coeffs is None else int(coeffs.numel())
+        _check(self._lib.fpm_pupil(self._h, _ptr(coeffs), n, _ptr(z_um), _ptr(out), _stream()))
+        return out
+
+    def forward(self, O, P, leds, gamma=None, with_field=False):
+        import torch
+        B = int(leds.numel())
+        amp = torch.empty((B, self.N, self.N), dtype=torch.float32, device=O.device)
+        field = (torch.empty((B, self.N, self.N), dtype=torch.complex64, device=O.device)
+                 if with_field else None)
+        _check(self._lib.fpm_forward(self._h, _ptr(O), _ptr(P), _ptr(leds), B, _ptr(gamma),
+                                     _ptr(amp), _ptr(field), _stream()))
+        return (amp, field) if with_field else amp
+
+    def backward(self, O, P, leds, meas_amp, gO, gP=None, loss=None, gamma=None):
+        B = int(leds.numel())
+        _check(self._lib.fpm_backward(self._h, _ptr(O), _ptr(P), _ptr(leds), B, _ptr(gamma),
+                                      _ptr(meas_amp), _ptr(gO), _ptr(gP), _ptr(loss), _stream()))
+
+    def pupil_grad(self, gP, P, g_par):
+        _check(self._lib.fpm_pupil_grad(self._h, _ptr(gP), _ptr(P), _ptr(g_par), _stream()))
+
+    def step(self, state: State, hp: HParams, leds, meas_amp, gamma=None):
+        cs = state.c()
+        hc = hp.c()
+        B = int(leds.numel())
+        _check(self._lib.fpm_step(self._h, C.byref(cs), C.byref(hc), _ptr(leds), B, _ptr(gamma),
+                                  _ptr(meas_amp), _stream()))
+        state.t = cs.t
+
+    def hr_transform(self, x, direction: int, out=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(x)
+        _check(self._lib.fpm_hr_transform(self._h, _ptr(x), _ptr(out), int(direction), _stream()))
+        return out
+
+    def init_spectrum(self, centre_amp, out=None):
+        import torch
+        if out is None:
+            out = torch.empty((self.M, self.M), dtype=torch.complex64, device=centre_amp.device)
+        _check(self._lib.fpm_init_spectrum(self._h, _ptr(centre_amp), _ptr(out), _stream()))
+        return out
+
+    def refocus(self, O, z_um, out=None):
+        import torch
+        nz = int(z_um.numel())
+        if out is None:
+            out = torch.empty((nz, self.M, self.M), dtype=torch.complex64, device=O.device)
+        _check(self._lib.fpm_refocus(self._h, _ptr(O), _ptr(z_um), nz, _ptr(out), _stream()))
+        return out

@@ -1,0 +1,358 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle.
+
+Same seeded inputs on both sides (float32 / complex64 on the GPU, upcast for
+the oracle). Tolerances: gradients and fields within a relative L2 of 2e-5
+(the per-step gradient bar of this build; an N x N complex64 FFT pair has a
+relative error near 1e-6); pupil-parameter gradients within 2e-5 of the sum
+of their summands' magnitudes (the sums cancel); reconstructions after a full
+solve within 1e-3 relative error; integer decisions bit-exact.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fpm_oracle as fo
+from paper_2408_13782_amd import fpm, inputs, problem
+
+from cases import oracle_problem, optics_of, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GRAD_TOL = 2e-5
+OBJ_TOL = 1e-3
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    fpm.load()
+    return torch.device("cuda:0")
+
+
+def T(x, dev):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(dev)
+
+
+def H(t):
+    return t.detach().cpu().numpy()
+
+
+def make_plan(w, shifts, max_batch):
+    return fpm.Plan(w.n_lr, w.upsample, shifts, max_batch, w.wavelength_um, w.na, w.mag,
+                    w.pixel_um)
+
+
+def oracle_shifts(w):
+    opt = optics_of(w)
+    return fo.nearest_shifts(fo.led_shifts(opt, fo.led_wavevectors(opt, w.n_side, w.pitch_mm,
+                                                                   w.height_mm)))
+
+
+# ---------------------------------------------------------------------------
+# building blocks
+
+
+@pytest.mark.parametrize("n_lr", [64, 256, 512])
+def test_hr_transforms_match_oracle(dev, n_lr):
+    w = inputs.workload("small", n_lr=n_lr)
+    say(f"hr_transform M={w.m_hr}")
+    plan = make_plan(w, oracle_shifts(w) * 0, 1)
+    o = inputs.random_complex((w.m_hr, w.m_hr), seed=3)
+    O = plan.hr_transform(T(o, dev), +1)
+    torch.cuda.synchronize()
+    want = fo.spectrum(o.astype(np.complex128))
+    assert rel_l2(H(O), want) <= GRAD_TOL
+    back = plan.hr_transform(O, -1)
+    torch.cuda.synchronize()
+    assert rel_l2(H(back), o) <= GRAD_TOL
+    # in place
+    x = T(o, dev)
+    plan.hr_transform(x, +1, out=x)
+    torch.cuda.synchronize()
+    assert rel_l2(H(x), want) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("n_lr", [64, 256])
+def test_initial_spectrum_matches_oracle(dev, n_lr):
+    w = inputs.workload("small", n_lr=n_lr)
+    say(f"init_spectrum N={n_lr}")
+    plan = make_plan(w, oracle_shifts(w) * 0, 1)
+    img = inputs.random_real((n_lr, n_lr), seed=5, lo=0.2, hi=1.0)
+    O0 = plan.init_spectrum(T(img, dev))
+    torch.cuda.synchronize()
+    assert rel_l2(H(O0), fo.initial_spectrum(img.astype(np.float64), w.upsample)) <= GRAD_TOL
+
+
+@pytest.mark.parametrize("n_lr", [64, 128, 256, 512])
+def test_pupil_matches_oracle(dev, n_lr):
+    w = inputs.workload("small", n_lr=n_lr)
+    say(f"pupil N={n_lr}")
+    opt = optics_of(w)
+    plan = make_plan(w, oracle_shifts(w) * 0, 1)
+    c = (inputs.random_real((15,), seed=n_lr, lo=-0.6, hi=0.6)).astype(np.float32)
+    z = np.array([-7.25], np.float32)
+    P = H(plan.pupil(T(c, dev), T(z, dev)))
+    mask = fo.pupil_mask(opt)
+    want = fo.pupil(mask, fo.zernike_basis(opt), c.astype(np.float64), float(z[0]),
+                    fo.defocus_phase_per_um(opt))
+    assert plan.info.support_px == int(mask.sum())
+    np.testing.assert_array_equal(P != 0, mask.astype(bool))
+    assert np.abs(P - want).max() <= 2e-6
+    P0 = H(plan.pupil())
+    np.testing.assert_array_equal(P0, mask.astype(np.complex64))
+
+
+# ---------------------------------------------------------------------------
+# forward model and adjoint
+
+
+@pytest.mark.parametrize("n_lr,B", [(64, 8), (64, 11), (128, 5), (256, 16), (512, 3)])
+def test_forward_matches_oracle(dev, n_lr, B):
+    w = inputs.workload("small", n_lr=n_lr, n_side=9 if n_lr <= 128 else 7)
+    say(f"forward N={n_lr} B={B}")
+    shifts = oracle_shifts(w)
+    plan = make_plan(w, shifts, 16)
+    opt = optics_of(w)
+    amp, ph = inputs.truth_object(w.m_hr, seed=n_lr)
+    O = fo.spectrum(fo.transmission(amp, ph)).astype(np.complex64)
+    c = inputs.random_real((15,), seed=1, lo=-0.3, hi=0.3).astype(np.float64)
+    P = fo.pupil(fo.pupil_mask(opt), fo.zernike_basis(opt), c, 2.0,
+                 fo.defocus_phase_per_um(opt)).astype(np.complex64)
+    gamma = inputs.random_real((w.n_led,), seed=2, lo=0.7, hi=1.3)
+    leds = inputs.random_indices(w.n_led, B, seed=B)
+    a, f = plan.forward(T(O, dev), T(P, dev), T(leds, dev), T(gamma, dev), with_field=True)
+    torch.cuda.synchronize()
+    want_a = fo.forward_amplitudes(O.astype(np.complex128), P.astype(np.complex128), shifts,
+                                   leds, gamma.astype(np.float64))
+    want_f = np.stack([fo.lr_field(O.astype(np.complex128), P.astype(np.complex128), shifts[l])
+                       for l in leds])
+    assert rel_l2(H(a), want_a) <= GRAD_TOL
+    assert rel_l2(H(f), want_f) <= GRAD_TOL
+
+
+def _backward_case(dev, w, O, P, leds, A, gamma, with_gP=True):
+    shifts = oracle_shifts(w)
+    plan = make_plan(w, shifts, max(16, len(leds)))
+    gO = torch.zeros((w.m_hr, w.m_hr), dtype=torch.complex64, device=dev)
+    gP = torch.zeros((w.n_lr, w.n_lr), dtype=torch.complex64, device=dev) if with_gP else None
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    plan.backward(T(O, dev), T(P, dev), T(leds, dev), T(A, dev), gO, gP, loss,
+                  None if gamma is None else T(gamma, dev))
+    torch.cuda.synchronize()
+    ref = fo.loss_and_grads(O.astype(np.complex128), P.astype(np.complex128), shifts, leds,
+                            A.astype(np.float64), None if gamma is None else gamma.astype(np.float64))
+    return plan, H(gO), None if gP is None else H(gP), float(H(loss)[0]), ref
+
+
+@pytest.mark.parametrize("name,B", [("small", 8), ("small", 3), ("paper", 16), ("paper", 13)])
+def test_backward_matches_oracle_at_initial_state(dev, name, B):
+    w = inputs.workload(name)
+    say(f"backward {name} B={B}")
+    pr = oracle_problem(w, seed=0)
+    P = fo.pupil(pr.mask, pr.zern, np.zeros(15), 0.0, pr.kappa).astype(np.complex64)
+    leds = inputs.random_indices(w.n_led, B, seed=11 + B)
+    plan, gO, gP, loss, ref = _backward_case(dev, w, pr.O0, P, leds, pr.A, None)
+    assert rel_l2(gO, ref.g_O) <= GRAD_TOL
+    m = pr.mask.astype(bool)
+    assert rel_l2(gP[m], ref.g_P[m]) <= GRAD_TOL
+    assert np.all(gP[~m] == 0)
+    assert abs(loss - ref.loss) <= 1e-5 * ref.loss
+    # gradient is exactly zero outside the union of this batch's windows
+    touched = np.zeros(gO.shape, bool)
+    for l in leds:
+        rows, cols = fo.window_indices(w.m_hr, w.n_lr, pr.shifts[l])
+        touched[np.ix_(rows, cols)] |= m
+    assert np.all(gO[~touched] == 0)
+
+
+def test_backward_with_aberrations_and_gamma(dev):
+    w = inputs.workload("small", n_side=9)
+    say("backward aberrated pupil, gamma")
+    opt = optics_of(w)
+    amp, ph = inputs.truth_object(w.m_hr, seed=4)
+    O = (fo.spectrum(fo.transmission(amp, ph)) * 0.9).astype(np.complex64)
+    c = inputs.random_real((15,), seed=9, lo=-0.5, hi=0.5).astype(np.float64)
+    P = fo.pupil(fo.pupil_mask(opt), fo.zernike_basis(opt), c, -3.0,
+                 fo.defocus_phase_per_um(opt)).astype(np.complex64)
+    A = inputs.random_real((w.n_led, w.n_lr, w.n_lr), seed=6, lo=0.0, hi=1.2)
+    gamma = inputs.random_real((w.n_led,), seed=7, lo=0.6, hi=1.4)
+    leds = inputs.random_indices(w.n_led, 16, seed=1)
+    plan, gO, gP, loss, ref = _backward_case(dev, w, O, P, leds, A, gamma)
+    m = fo.pupil_mask(opt).astype(bool)
+    assert rel_l2(gO, ref.g_O) <= GRAD_TOL
+    assert rel_l2(gP[m], ref.g_P[m]) <= GRAD_TOL
+    assert abs(loss - ref.loss) <= 1e-5 * ref.loss
+
+
+def test_pupil_grad_projection_matches_oracle(dev):
+    w = inputs.workload("paper")
+    say("pupil_grad paper")
+    opt = optics_of(w)
+    plan = make_plan(w, oracle_shifts(w), 1)
+    mask = fo.pupil_mask(opt)
+    zern, kappa = fo.zernike_basis(opt), fo.defocus_phase_per_um(opt)
+    c = inputs.random_real((15,), seed=3, lo=-0.4, hi=0.4).astype(np.float64)
+    P = fo.pupil(mask, zern, c, 1.5, kappa).astype(np.complex64)
+    gP = (inputs.random_complex((w.n_lr, w.n_lr), seed=4) * mask).astype(np.complex64)
+    g_par = torch.zeros(16, dtype=torch.float64, device=dev)
+    plan.pupil_grad(T(gP, dev), T(P, dev), g_par)
+    torch.cuda.synchronize()
+    g_c, g_z, g_theta = fo.pupil_param_grads(gP.astype(np.complex128), P.astype(np.complex128),
+                                             zern, kappa)
+    got = H(g_par)
+    for j in range(15):
+        assert abs(got[j] - g_c[j]) <= GRAD_TOL * np.sum(np.abs(g_theta * zern[j]))
+    assert abs(got[15] - g_z) <= GRAD_TOL * np.sum(np.abs(g_theta * kappa))
+
+
+# ---------------------------------------------------------------------------
+# optimiser steps and full solves
+
+
+def _gpu_state(plan, O0, dev, coeffs=None, z=0.0):
+    return fpm.State(plan, T(O0, dev), coeffs, z)
+
+
+def test_single_step_matches_oracle(dev):
+    w = inputs.workload("small")
+    say("one step small")
+    pr = oracle_problem(w, seed=0)
+    plan = make_plan(w, pr.shifts, w.batch)
+    st = _gpu_state(plan, pr.O0, dev)
+    hp = problem.hparams(w)
+    leds = inputs.random_indices(w.n_led, w.batch, seed=21)
+    plan.step(st, hp, T(leds, dev), T(pr.A, dev))
+    torch.cuda.synchronize()
+    ost = fo.init_state(pr.O0)
+    cfg = fo.SolveConfig(lr_object=w.lr_object)
+    loss = fo.step(ost, cfg, pr.mask, pr.zern, pr.kappa, pr.shifts, leds, pr.A.astype(np.float64))
+    assert st.t == 1
+    assert rel_l2(H(st.O), ost.O) <= 1e-6
+    assert abs(float(H(st.loss)[0]) - loss) <= 1e-5 * loss
+    assert np.all(H(st.g_O) == 0)          # the step leaves the gradient buffer cleared
+
+
+def test_step_with_zernike_learning_matches_oracle(dev):
+    w = inputs.workload("paper")
+    say("two steps paper (object + Zernike)")
+    pr = oracle_problem(w, seed=0)
+    plan = make_plan(w, pr.shifts, w.batch)
+    st = _gpu_state(plan, pr.O0, dev)
+    hp = problem.hparams(w)
+    ost = fo.init_state(pr.O0)
+    cfg = fo.SolveConfig(lr_object=w.lr_object, lr_zernike=w.lr_zernike, learn_pupil=True)
+    A64 = pr.A.astype(np.float64)
+    for i in range(2):
+        leds = inputs.random_indices(w.n_led, w.batch, seed=30 + i)
+        plan.step(st, hp, T(leds, dev), T(pr.A, dev))
+        fo.step(ost, cfg, pr.mask, pr.zern, pr.kappa, pr.shifts, leds, A64)
+    torch.cuda.synchronize()
+    assert rel_l2(H(st.O), ost.O) <= 1e-5
+    np.testing.assert_allclose(H(st.coeffs), ost.coeffs, atol=2e-5 * w.lr_zernike * 2 + 1e-7)
+    assert np.all(H(st.g_par) == 0)
+
+
+def _gradient_at_gpu_state(dev, plan, pr, st, leds, P):
+    gO = torch.zeros_like(st.O)
+    plan.backward(st.O, P, T(leds, dev), T(pr.A, dev), gO)
+    torch.cuda.synchronize()
+    ref = fo.loss_and_grads(H(st.O).astype(np.complex128), H(P).astype(np.complex128),
+                            pr.shifts, leds, pr.A.astype(np.float64))
+    return rel_l2(H(gO), ref.g_O)
+
+
+def test_small_solve_matches_oracle(dev):
+    """Full small workload: 7x7 LEDs, 64^2 -> 256^2, B = 8, 20 epochs (140 steps)."""
+    w = inputs.workload("small")
+    say("full solve small (140 steps)")
+    pr = oracle_problem(w, seed=0)
+    perms = inputs.led_permutations(w.n_led, w.epochs, seed=0)
+    sched = fo.batches_from_permutations(perms, w.batch)
+    plan = make_plan(w, pr.shifts, w.batch)
+    st = _gpu_state(plan, pr.O0, dev)
+    hp = problem.hparams(w)
+    P = plan.pupil()
+    views = problem.upload_schedule(problem.schedule(perms, w.batch), dev)
+    A = T(pr.A, dev)
+    mid_err = None
+    for i, leds in enumerate(views):
+        if i == 70:   # per-step gradient at the GPU's own state, mid-trajectory
+            mid_err = _gradient_at_gpu_state(dev, plan, pr, st, sched[i], P)
+        plan.step(st, hp, leds, A)
+    torch.cuda.synchronize()
+    ost = fo.init_state(pr.O0)
+    cfg = fo.SolveConfig(lr_object=w.lr_object)
+    losses = fo.solve(ost, cfg, pr.mask, pr.zern, pr.kappa, pr.shifts, sched,
+                      pr.A.astype(np.float64))
+    err = rel_l2(H(st.O), ost.O)
+    say(f"final object rel err {err:.3e}; mid-trajectory gradient rel err {mid_err:.3e}")
+    assert mid_err <= GRAD_TOL
+    assert err <= OBJ_TOL
+    assert abs(float(H(st.loss)[0]) - sum(losses)) <= 1e-4 * sum(losses)
+    # the reconstruction improves on the initial value
+    psnr0 = fo.psnr(np.abs(fo.object_from_spectrum(pr.O0)), np.abs(fo.object_from_spectrum(pr.O_true)))
+    psnr1 = fo.psnr(np.abs(fo.object_from_spectrum(H(st.O))), np.abs(fo.object_from_spectrum(pr.O_true)))
+    assert psnr1 > psnr0
+
+
+# ---------------------------------------------------------------------------
+# refocusing
+
+
+@pytest.mark.parametrize("n_lr", [64, 256])
+def test_refocus_matches_oracle(dev, n_lr):
+    w = inputs.workload("small", n_lr=n_lr)
+    say(f"refocus M={w.m_hr}")
+    plan = make_plan(w, oracle_shifts(w) * 0, 1)
+    amp, ph = inputs.truth_object(w.m_hr, seed=8)
+    O = fo.spectrum(fo.transmission(amp, ph)).astype(np.complex64)
+    z = np.array([-40.0, -13.3, 0.0, 27.5], np.float32)
+    out = H(plan.refocus(T(O, dev), T(z, dev)))
+    want = fo.refocus(O.astype(np.complex128), z.astype(np.float64), optics_of(w))
+    for i in range(len(z)):
+        assert rel_l2(out[i], want[i]) <= GRAD_TOL
+
+
+# ---------------------------------------------------------------------------
+# edge cases and errors
+
+
+def test_edge_cases(dev):
+    w = inputs.workload("small")
+    say("edge cases")
+    pr = oracle_problem(w, seed=0)
+    plan = make_plan(w, pr.shifts, 8)
+    O = T(pr.O0, dev)
+    P = plan.pupil()
+    A = T(pr.A, dev)
+    gO = torch.zeros_like(O)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    # empty batch: nothing happens
+    plan.backward(O, P, torch.zeros(0, dtype=torch.int32, device=dev), A, gO, None, loss)
+    torch.cuda.synchronize()
+    assert float(H(loss)[0]) == 0.0 and not torch.any(gO != 0)
+    # an out-of-range LED id contributes nothing; the valid ones are unaffected
+    leds = np.array([3, 999, 17, -1], np.int32)
+    plan.backward(O, P, T(leds, dev), A, gO, None, loss)
+    torch.cuda.synchronize()
+    ref = fo.loss_and_grads(pr.O0.astype(np.complex128), H(P).astype(np.complex128), pr.shifts,
+                            [3, 17], pr.A.astype(np.float64))
+    assert rel_l2(H(gO), ref.g_O) <= GRAD_TOL
+    # batch larger than the plan allows
+    with pytest.raises(fpm.FpmError):
+        plan.backward(O, P, torch.zeros(9, dtype=torch.int32, device=dev), A, gO)
+    # a window leaving the HR grid is refused at plan creation
+    bad = pr.shifts.copy()
+    bad[0] = (w.m_hr, 0)
+    with pytest.raises(fpm.FpmError):
+        make_plan(w, bad, 8)
+    with pytest.raises(fpm.FpmError):
+        fpm.Plan(96, 4, pr.shifts, 8, w.wavelength_um, w.na, w.mag, w.pixel_um)

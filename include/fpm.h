@@ -181,7 +181,8 @@ typedef struct {
  * before the first step and is left zero by every step);
  * P: complex [N][N] pupil (input if the pupil is fixed, rebuilt otherwise);
  * coeffs/m_c/v_c: float [15]; z_um/m_z/v_z: float [1] (may be NULL when not
- * learned); g_par: double [16] accumulator, zero on entry, left zero;
+ * learned); g_par: double [16] or NULL: when the pupil is learned, += the
+ * gradients with respect to coeffs[0..14] and z of each step (diagnostics);
  * loss: double [1] or NULL (+= the batch loss).
  * `t` is the number of Adam steps already taken; fpm_step increments it.
  */
@@ -197,13 +198,25 @@ typedef struct {
 
 /*
  * One random-batch update (Eq. 13): rebuild P from (coeffs, z) when either
- * is learned, loss and gradients of the batch, pupil-parameter projection,
- * then Adam on the object (over the union of LED windows; elsewhere the
- * gradient is identically zero and Adam leaves O unchanged) and on the
- * learned pupil parameters.
+ * is learned (written to state->P), loss and gradients of the batch,
+ * pupil-parameter projection, Adam on the learned pupil parameters, then
+ * Adam on the object (over the union of LED windows; elsewhere the gradient
+ * is identically zero and Adam leaves O unchanged). The loss and the
+ * pupil-parameter gradients are reduced in a fixed order (deterministic);
+ * the object gradient is accumulated with atomics.
  */
 int fpm_step(fpm_plan* plan, fpm_state* state, const fpm_hparams* hp, const int32_t* leds,
              int32_t B, const float* gamma, const float* meas_amp, void* stream);
+
+/*
+ * n_steps consecutive updates (a whole solve or a slice of one) in one call:
+ * step i uses the batch_sizes[i] LED ids that follow those of step i-1 in
+ * `leds` (device, int32, concatenated); batch_sizes is HOST memory
+ * [n_steps], each in [1, max_batch]. Same effect as n_steps fpm_step calls.
+ */
+int fpm_run(fpm_plan* plan, fpm_state* state, const fpm_hparams* hp, const int32_t* leds,
+            const int32_t* batch_sizes, int32_t n_steps, const float* gamma,
+            const float* meas_amp, void* stream);
 
 /*
  * HR object <-> spectrum (Sec. 2.1, Eq. 1) with the orthonormal scaling:
@@ -228,6 +241,18 @@ int fpm_init_spectrum(fpm_plan* plan, const float* centre_amp, fpm_c32* O_out, v
  */
 int fpm_refocus(fpm_plan* plan, const fpm_c32* O, const float* z_um, int32_t nz, fpm_c32* out,
                 void* stream);
+
+/*
+ * Per-kernel timing (diagnostics for profiling and roofline reports).
+ * While enabled, every kernel the plan launches is bracketed by a pair of
+ * HIP events recorded on the launch's stream (at most 65536 pairs are kept).
+ * fpm_timing_collect() waits for the recorded events, writes for each kernel
+ * kind k < *n_kinds (at most max_kinds): names[k] (static string), total_ms[k]
+ * and counts[k], then clears the record. All arrays are HOST memory.
+ */
+int fpm_timing_enable(fpm_plan* plan, int32_t enable);
+int fpm_timing_collect(fpm_plan* plan, int32_t max_kinds, const char** names, double* total_ms,
+                       int32_t* counts, int32_t* n_kinds);
 
 #ifdef __cplusplus
 }

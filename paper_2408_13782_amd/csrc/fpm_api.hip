@@ -57,6 +57,20 @@ int upload(T** dst, const T* src, size_t count) {
   return FPM_OK;
 }
 
+enum Kind {
+  kPupilBuild, kRowsForward, kCols, kRowsBackward, kPupilGrad, kAdamObject, kAdamScalars,
+  kHrRows, kHrCols, kKinds
+};
+const char* const kKindNames[kKinds] = {"pupil_build", "rows_forward", "cols", "rows_backward",
+                                        "pupil_grad", "adam_object", "adam_scalars", "hr_rows",
+                                        "hr_cols"};
+constexpr size_t kMaxTimed = 65536;
+
+struct TimedLaunch {
+  int kind;
+  hipEvent_t start, stop;
+};
+
 }  // namespace
 
 struct fpm_plan {
@@ -74,11 +88,56 @@ struct fpm_plan {
   float2* X = nullptr;        // [max_batch][N][N] row/column scratch
   float2* gP = nullptr;       // [N][N] pupil-gradient accumulator for fpm_step
   int2* tiles = nullptr;      // [n_tiles] 32 x 32 HR tiles covered by some window
+  double* part = nullptr;     // per-workgroup partial sums of the grid reductions
+  unsigned* counters = nullptr;  // completion counters, one per reducing kernel
+  bool timing = false;
+  std::vector<TimedLaunch> timed;
+  std::vector<hipEvent_t> event_pool;
 };
 
 namespace {
 
+hipEvent_t pool_event(fpm_plan* p) {
+  if (!p->event_pool.empty()) {
+    hipEvent_t e = p->event_pool.back();
+    p->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Brackets one launch with events when the plan's timing is on.
+struct Timed {
+  fpm_plan* p;
+  int kind;
+  hipStream_t st;
+  hipEvent_t start = nullptr;
+  Timed(fpm_plan* plan, int k, hipStream_t s) : p(plan), kind(k), st(s) {
+    if (p->timing && p->timed.size() < kMaxTimed) {
+      start = pool_event(p);
+      if (start && hipEventRecord(start, st) != hipSuccess) start = nullptr;
+    }
+  }
+  ~Timed() {
+    if (!start) return;
+    hipEvent_t stop = pool_event(p);
+    if (stop && hipEventRecord(stop, st) == hipSuccess) {
+      p->timed.push_back({kind, start, stop});
+    } else {
+      p->event_pool.push_back(start);
+      if (stop) p->event_pool.push_back(stop);
+    }
+  }
+};
+
 void plan_free(fpm_plan* p) {
+  for (auto& t : p->timed) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  for (auto e : p->event_pool) (void)hipEventDestroy(e);
   (void)hipFree(p->rowext);
   (void)hipFree(p->shifts);
   (void)hipFree(p->twN);
@@ -86,6 +145,8 @@ void plan_free(fpm_plan* p) {
   (void)hipFree(p->X);
   (void)hipFree(p->gP);
   (void)hipFree(p->tiles);
+  (void)hipFree(p->part);
+  (void)hipFree(p->counters);
   delete p;
 }
 
@@ -112,25 +173,90 @@ int check_batch(const fpm_plan* p, const int32_t* leds, int32_t B) {
   return FPM_OK;
 }
 
-// Loss and gradient launches shared by fpm_backward and fpm_step.
+enum { kCounterCols = 0, kCounterRows = 1, kCounterPupil = 2, kCounters = 3 };
+
+Batch batch_of(const fpm_plan* p, const int32_t* leds, int B) {
+  Batch b;
+  b.shifts = p->shifts;
+  b.leds = leds;
+  b.B = B;
+  b.n_led = p->n_led;
+  b.M = p->M;
+  return b;
+}
+
+Disk disk_of(const fpm_plan* p) {
+  Disk d;
+  d.rowext = p->rowext;
+  d.ky_lo = p->ky_lo;
+  d.ky_hi = p->ky_hi;
+  d.nrows = p->nrows;
+  return d;
+}
+
+Reduction reduction_of(const fpm_plan* p, int which) {
+  Reduction r;
+  r.part = p->part;
+  r.counter = p->counters + which;
+  return r;
+}
+
+// What a loss-and-gradient pass produces besides g_O.
+struct BackwardOut {
+  bool live_pupil = false;    // rebuild P from pp into P (slot 0 writes it)
+  PupilParams pp{};
+  int mode = kGradO;          // rows_backward mode
+  float2* gP = nullptr;       // kGradOP
+  double* g_par = nullptr;    // kGradOZern: += parameter gradients (nullable)
+  ScalarAdam adam{};          // kGradOZern: Adam on the pupil parameters
+  double* loss = nullptr;
+};
+
 template <int N>
-int launch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t* leds, int B,
-                    const float* gamma, const float* A, float2* gO, float2* gP, double* loss,
+int launch_backward(fpm_plan* p, const float2* O, float2* P, const int32_t* leds, int B,
+                    const float* gamma, const float* A, float2* gO, const BackwardOut& o,
                     hipStream_t st) {
   constexpr int Lr = kRowThreads / Plan1D<N>::T;
   constexpr int Lc = ColLines<N>::value;
   const int slots = (B + kXcds - 1) / kXcds * kXcds;
   const int row_chunks = (p->nrows + Lr - 1) / Lr;
   const int col_groups = N / Lc;
-  rows_forward<N><<<slots * row_chunks, kRowThreads, 0, st>>>(
-      O, p->M, P, p->rowext, p->ky_lo, p->nrows, p->shifts, leds, B, p->n_led, row_chunks, p->X,
-      p->twN);
-  cols<N, false><<<slots * col_groups, Lc * Plan1D<N>::T, 0, st>>>(
-      p->X, A, gamma, leds, B, p->n_led, p->ky_lo, p->ky_hi, col_groups, loss, nullptr, nullptr, p->twN,
-      1.0f / p->M);
-  rows_backward<N><<<slots * row_chunks, kRowThreads, 0, st>>>(
-      p->X, O, p->M, P, p->rowext, p->ky_lo, p->nrows, p->shifts, leds, B, p->n_led, row_chunks, gO, gP,
-      p->twN);
+  const Batch bt = batch_of(p, leds, B);
+  const Disk dk = disk_of(p);
+  const PupilGeom pg = pupil_geom(p);
+  {
+    Timed tm(p, kRowsForward, st);
+    if (o.live_pupil)
+      rows_forward<N, true><<<slots * row_chunks, kRowThreads, 0, st>>>(
+          O, P, bt, dk, pg, o.pp, P, row_chunks, p->X, p->twN);
+    else
+      rows_forward<N, false><<<slots * row_chunks, kRowThreads, 0, st>>>(
+          O, P, bt, dk, pg, o.pp, nullptr, row_chunks, p->X, p->twN);
+  }
+  {
+    Timed tm(p, kCols, st);
+    cols<N, false><<<slots * col_groups, Lc * Plan1D<N>::T, 0, st>>>(
+        p->X, A, gamma, bt, dk, col_groups, reduction_of(p, kCounterCols), o.loss, nullptr,
+        nullptr, p->twN, 1.0f / p->M);
+  }
+  {
+    Timed tm(p, kRowsBackward, st);
+    const Reduction red = reduction_of(p, kCounterRows);
+    switch (o.mode) {
+      case kGradO:
+        rows_backward<N, kGradO><<<slots * row_chunks, kRowThreads, 0, st>>>(
+            p->X, O, P, bt, dk, pg, row_chunks, gO, nullptr, red, nullptr, o.adam, p->twN);
+        break;
+      case kGradOP:
+        rows_backward<N, kGradOP><<<slots * row_chunks, kRowThreads, 0, st>>>(
+            p->X, O, P, bt, dk, pg, row_chunks, gO, o.gP, red, nullptr, o.adam, p->twN);
+        break;
+      default:
+        rows_backward<N, kGradOZern><<<slots * row_chunks, kRowThreads, 0, st>>>(
+            p->X, O, P, bt, dk, pg, row_chunks, gO, nullptr, red, o.g_par, o.adam, p->twN);
+        break;
+    }
+  }
   FPM_HIP(hipGetLastError());
   return FPM_OK;
 }
@@ -143,26 +269,49 @@ int launch_forward(fpm_plan* p, const float2* O, const float2* P, const int32_t*
   const int slots = (B + kXcds - 1) / kXcds * kXcds;
   const int row_chunks = (p->nrows + Lr - 1) / Lr;
   const int col_groups = N / Lc;
-  rows_forward<N><<<slots * row_chunks, kRowThreads, 0, st>>>(
-      O, p->M, P, p->rowext, p->ky_lo, p->nrows, p->shifts, leds, B, p->n_led, row_chunks, p->X,
-      p->twN);
-  cols<N, true><<<slots * col_groups, Lc * Plan1D<N>::T, 0, st>>>(
-      p->X, nullptr, gamma, leds, B, p->n_led, p->ky_lo, p->ky_hi, col_groups, nullptr, amp, field,
-      p->twN, 1.0f / p->M);
+  const Batch bt = batch_of(p, leds, B);
+  const Disk dk = disk_of(p);
+  {
+    Timed tm(p, kRowsForward, st);
+    rows_forward<N, false><<<slots * row_chunks, kRowThreads, 0, st>>>(
+        O, P, bt, dk, pupil_geom(p), PupilParams{}, nullptr, row_chunks, p->X, p->twN);
+  }
+  {
+    Timed tm(p, kCols, st);
+    cols<N, true><<<slots * col_groups, Lc * Plan1D<N>::T, 0, st>>>(
+        p->X, nullptr, gamma, bt, dk, col_groups, reduction_of(p, kCounterCols), nullptr, amp,
+        field, p->twN, 1.0f / p->M);
+  }
   FPM_HIP(hipGetLastError());
   return FPM_OK;
 }
 
-int dispatch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t* leds, int B,
-                      const float* gamma, const float* A, float2* gO, float2* gP, double* loss,
+int dispatch_backward(fpm_plan* p, const float2* O, float2* P, const int32_t* leds, int B,
+                      const float* gamma, const float* A, float2* gO, const BackwardOut& o,
                       hipStream_t st) {
   switch (p->N) {
-    case 64: return launch_backward<64>(p, O, P, leds, B, gamma, A, gO, gP, loss, st);
-    case 128: return launch_backward<128>(p, O, P, leds, B, gamma, A, gO, gP, loss, st);
-    case 256: return launch_backward<256>(p, O, P, leds, B, gamma, A, gO, gP, loss, st);
-    case 512: return launch_backward<512>(p, O, P, leds, B, gamma, A, gO, gP, loss, st);
+    case 64: return launch_backward<64>(p, O, P, leds, B, gamma, A, gO, o, st);
+    case 128: return launch_backward<128>(p, O, P, leds, B, gamma, A, gO, o, st);
+    case 256: return launch_backward<256>(p, O, P, leds, B, gamma, A, gO, o, st);
+    case 512: return launch_backward<512>(p, O, P, leds, B, gamma, A, gO, o, st);
   }
   return fail(FPM_EUNSUPPORTED, "unsupported N");
+}
+
+// Largest grid of any reducing kernel (sizes the partial-sum buffer).
+int max_reduce_grid(const fpm_plan* p) {
+  const int slots = (p->max_batch + kXcds - 1) / kXcds * kXcds;
+  int rows_l = 0, cols_l = 0;
+  switch (p->N) {
+    case 64: rows_l = kRowThreads / Plan1D<64>::T; cols_l = ColLines<64>::value; break;
+    case 128: rows_l = kRowThreads / Plan1D<128>::T; cols_l = ColLines<128>::value; break;
+    case 256: rows_l = kRowThreads / Plan1D<256>::T; cols_l = ColLines<256>::value; break;
+    case 512: rows_l = kRowThreads / Plan1D<512>::T; cols_l = ColLines<512>::value; break;
+  }
+  const int rows_grid = slots * ((p->nrows + rows_l - 1) / rows_l);
+  const int cols_grid = slots * (p->N / cols_l);
+  const int pupil_grid = (p->N * p->N + 255) / 256;
+  return std::max(rows_grid, std::max(cols_grid, pupil_grid));
 }
 
 template <int M>
@@ -170,12 +319,16 @@ int launch_hr(fpm_plan* p, HrArgs a, int row_mode, int dir, hipStream_t st) {
   constexpr int Lr = HrRowLines<M>::value;
   constexpr int Lc = HrColLines<M>::value;
   constexpr int T = Plan1D<M>::T;
+  {
+  Timed tm(p, kHrRows, st);
   switch (row_mode) {
     case kRowFwd: hr_rows<M, kRowFwd><<<M / Lr, Lr * T, 0, st>>>(a, p->twM); break;
     case kRowInv: hr_rows<M, kRowInv><<<M / Lr, Lr * T, 0, st>>>(a, p->twM); break;
     case kRowInit: hr_rows<M, kRowInit><<<M / Lr, Lr * T, 0, st>>>(a, p->twM); break;
     case kRowRefocus: hr_rows<M, kRowRefocus><<<M / Lr, Lr * T, 0, st>>>(a, p->twM); break;
   }
+  }
+  Timed tm(p, kHrCols, st);
   if (dir < 0)
     hr_cols<M, -1><<<M / Lc, Lc * T, 0, st>>>(a.out, p->twM);
   else
@@ -301,6 +454,16 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
     plan_free(p);
     return rc;
   }
+  const size_t n_part = (size_t)max_reduce_grid(p) * kPar;
+  if ((rc = upload<double>(&p->part, nullptr, n_part)) ||
+      (rc = upload<unsigned>(&p->counters, nullptr, kCounters))) {
+    plan_free(p);
+    return rc;
+  }
+  if (hipMemset(p->counters, 0, kCounters * sizeof(unsigned)) != hipSuccess) {
+    plan_free(p);
+    return fail(FPM_EHIP, "hipMemset failed");
+  }
   if (p->hr_ok) {
     const auto twm = twiddles(p->M);
     if ((rc = upload(&p->twM, twm.data(), twm.size()))) {
@@ -370,6 +533,7 @@ int fpm_pupil(fpm_plan* p, const float* coeffs, int32_t n_zern, const float* z_u
   FPM_REQUIRE(n_zern >= 0 && n_zern <= kZern, "n_zern must be in [0, 15]");
   if (int rc = check_device(p)) return rc;
   const int nn = p->N * p->N;
+  Timed tm(p, kPupilBuild, (hipStream_t)stream);
   pupil_build<<<(nn + 255) / 256, 256, 0, (hipStream_t)stream>>>(
       pupil_geom(p), p->rowext, coeffs, n_zern, z_um, reinterpret_cast<float2*>(P_out));
   FPM_HIP(hipGetLastError());
@@ -402,9 +566,14 @@ int fpm_backward(fpm_plan* p, const fpm_c32* O, const fpm_c32* P, const int32_t*
   if (int rc = check_batch(p, leds, B)) return rc;
   if (int rc = check_device(p)) return rc;
   if (B == 0) return FPM_OK;
-  return dispatch_backward(p, reinterpret_cast<const float2*>(O), reinterpret_cast<const float2*>(P),
-                           leds, B, gamma, meas_amp, reinterpret_cast<float2*>(gO),
-                           reinterpret_cast<float2*>(gP), loss, (hipStream_t)stream);
+  BackwardOut o;
+  o.mode = gP ? kGradOP : kGradO;
+  o.gP = reinterpret_cast<float2*>(gP);
+  o.loss = loss;
+  return dispatch_backward(p, reinterpret_cast<const float2*>(O),
+                           const_cast<float2*>(reinterpret_cast<const float2*>(P)), leds, B,
+                           gamma, meas_amp, reinterpret_cast<float2*>(gO), o,
+                           (hipStream_t)stream);
 }
 
 int fpm_pupil_grad(fpm_plan* p, const fpm_c32* gP, const fpm_c32* P, double* g_par,
@@ -412,64 +581,102 @@ int fpm_pupil_grad(fpm_plan* p, const fpm_c32* gP, const fpm_c32* P, double* g_p
   FPM_REQUIRE(p && gP && P && g_par, "plan, gP, P and g_par must not be NULL");
   if (int rc = check_device(p)) return rc;
   const int nn = p->N * p->N;
+  Timed tm(p, kPupilGrad, (hipStream_t)stream);
   pupil_grad<<<(nn + 255) / 256, 256, 0, (hipStream_t)stream>>>(
-      pupil_geom(p), p->rowext, const_cast<float2*>(reinterpret_cast<const float2*>(gP)),
-      reinterpret_cast<const float2*>(P), g_par, 0);
+      pupil_geom(p), p->rowext, reinterpret_cast<const float2*>(gP),
+      reinterpret_cast<const float2*>(P), reduction_of(p, kCounterPupil), g_par);
   FPM_HIP(hipGetLastError());
   return FPM_OK;
 }
 
-int fpm_step(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_t* leds, int32_t B,
-             const float* gamma, const float* meas_amp, void* stream) {
+}  // extern "C"
+
+namespace {
+
+int check_state(fpm_plan* p, const fpm_state* s, const fpm_hparams* hp, const float* meas_amp) {
   FPM_REQUIRE(p && s && hp, "plan, state and hparams must not be NULL");
   FPM_REQUIRE(s->O && s->m_O && s->v_O && s->g_O && s->P && meas_amp,
               "state O, m_O, v_O, g_O, P and meas_amp must not be NULL");
-  FPM_REQUIRE(B >= 1, "fpm_step needs a non-empty batch");
-  if (int rc = check_batch(p, leds, B)) return rc;
-  if (int rc = check_device(p)) return rc;
-  const bool learn_c = hp->learn_zernike != 0, learn_z = hp->learn_z != 0;
-  const bool learn_p = learn_c || learn_z;
-  if (learn_c) FPM_REQUIRE(s->coeffs && s->m_c && s->v_c, "Zernike state must not be NULL");
-  if (learn_z) FPM_REQUIRE(s->z_um && s->m_z && s->v_z, "defocus state must not be NULL");
-  if (learn_p) FPM_REQUIRE(s->g_par, "g_par must not be NULL when the pupil is learned");
+  if (hp->learn_zernike) FPM_REQUIRE(s->coeffs && s->m_c && s->v_c, "Zernike state must not be NULL");
+  if (hp->learn_z) FPM_REQUIRE(s->z_um && s->m_z && s->v_z, "defocus state must not be NULL");
   FPM_REQUIRE(s->t >= 0, "t must be >= 0");
-  hipStream_t st = (hipStream_t)stream;
-  float2* P = reinterpret_cast<float2*>(s->P);
-  const int nn = p->N * p->N;
-  if (learn_p) {
-    pupil_build<<<(nn + 255) / 256, 256, 0, st>>>(pupil_geom(p), p->rowext, s->coeffs,
-                                                  s->coeffs ? kZern : 0, s->z_um, P);
-  }
-  if (int rc = dispatch_backward(p, reinterpret_cast<const float2*>(s->O), P, leds, B, gamma,
-                                 meas_amp, reinterpret_cast<float2*>(s->g_O),
-                                 learn_p ? p->gP : nullptr, s->loss, st))
-    return rc;
-  if (learn_p) {
-    pupil_grad<<<(nn + 255) / 256, 256, 0, st>>>(pupil_geom(p), p->rowext, p->gP, P, s->g_par, 1);
-  }
+  return check_device(p);
+}
+
+// One update: loss and gradients (pupil rebuilt and its parameters updated
+// inside the row passes when learned), then Adam on the spectrum.
+int step_launches(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_t* leds, int B,
+                  const float* gamma, const float* meas_amp, hipStream_t st) {
+  const bool learn_c = hp->learn_zernike != 0, learn_z = hp->learn_z != 0;
   const int t = s->t + 1;
   const double b1 = hp->beta1, b2 = hp->beta2;
   const double bc1 = 1.0 - std::pow(b1, t), bc2 = 1.0 - std::pow(b2, t);
+  float2* P = reinterpret_cast<float2*>(s->P);
+  BackwardOut o;
+  o.loss = s->loss;
+  if (learn_c || learn_z) {
+    o.live_pupil = true;
+    o.pp.coeffs = s->coeffs;
+    o.pp.n_zern = s->coeffs ? kZern : 0;
+    o.pp.z_um = s->z_um;
+    o.mode = kGradOZern;
+    o.g_par = s->g_par;
+    ScalarAdam& a = o.adam;
+    a.coeffs = s->coeffs; a.m_c = s->m_c; a.v_c = s->v_c; a.learn_c = learn_c;
+    a.z = s->z_um; a.m_z = s->m_z; a.v_z = s->v_z; a.learn_z = learn_z;
+    a.lr_c = hp->lr_zernike; a.lr_z = hp->lr_z;
+    a.b1 = b1; a.b2 = b2; a.eps = hp->eps; a.bc1 = bc1; a.sqrt_bc2 = std::sqrt(bc2);
+  }
+  if (int rc = dispatch_backward(p, reinterpret_cast<const float2*>(s->O), P, leds, B, gamma,
+                                 meas_amp, reinterpret_cast<float2*>(s->g_O), o, st))
+    return rc;
   AdamCoef c;
   c.b1 = hp->beta1;
   c.b2 = hp->beta2;
   c.eps = hp->eps;
   c.step_size = (float)(hp->lr_object / bc1);
   c.sqrt_bc2 = (float)std::sqrt(bc2);
-  adam_object<<<p->n_tiles, 256, 0, st>>>(p->tiles, p->M, reinterpret_cast<float*>(s->O),
-                                          reinterpret_cast<float*>(s->m_O),
-                                          reinterpret_cast<float*>(s->v_O),
-                                          reinterpret_cast<float*>(s->g_O), c);
-  if (learn_p) {
-    AdamScalarArgs a;
-    a.coeffs = s->coeffs; a.m_c = s->m_c; a.v_c = s->v_c; a.learn_c = learn_c;
-    a.z = s->z_um; a.m_z = s->m_z; a.v_z = s->v_z; a.learn_z = learn_z;
-    a.lr_c = hp->lr_zernike; a.lr_z = hp->lr_z;
-    a.b1 = b1; a.b2 = b2; a.eps = hp->eps; a.bc1 = bc1; a.sqrt_bc2 = std::sqrt(bc2);
-    adam_scalars<<<1, 64, 0, st>>>(a, s->g_par);
+  {
+    Timed tm(p, kAdamObject, st);
+    adam_object<<<p->n_tiles, 256, 0, st>>>(p->tiles, p->M, reinterpret_cast<float*>(s->O),
+                                            reinterpret_cast<float*>(s->m_O),
+                                            reinterpret_cast<float*>(s->v_O),
+                                            reinterpret_cast<float*>(s->g_O), c);
   }
   FPM_HIP(hipGetLastError());
   s->t = t;
+  return FPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fpm_step(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_t* leds, int32_t B,
+             const float* gamma, const float* meas_amp, void* stream) {
+  if (int rc = check_state(p, s, hp, meas_amp)) return rc;
+  FPM_REQUIRE(B >= 1, "fpm_step needs a non-empty batch");
+  if (int rc = check_batch(p, leds, B)) return rc;
+  return step_launches(p, s, hp, leds, B, gamma, meas_amp, (hipStream_t)stream);
+}
+
+int fpm_run(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_t* leds,
+            const int32_t* batch_sizes, int32_t n_steps, const float* gamma,
+            const float* meas_amp, void* stream) {
+  if (int rc = check_state(p, s, hp, meas_amp)) return rc;
+  FPM_REQUIRE(n_steps >= 0, "n_steps must be >= 0");
+  FPM_REQUIRE(n_steps == 0 || (leds && batch_sizes), "leds and batch_sizes must not be NULL");
+  for (int i = 0; i < n_steps; ++i) {
+    FPM_REQUIRE(batch_sizes[i] >= 1 && batch_sizes[i] <= p->max_batch,
+                "every batch size must be in [1, max_batch]");
+  }
+  size_t off = 0;
+  for (int i = 0; i < n_steps; ++i) {
+    if (int rc = step_launches(p, s, hp, leds + off, batch_sizes[i], gamma, meas_amp,
+                               (hipStream_t)stream))
+      return rc;
+    off += batch_sizes[i];
+  }
   return FPM_OK;
 }
 
@@ -515,6 +722,39 @@ int fpm_refocus(fpm_plan* p, const fpm_c32* O, const float* z_um, int32_t nz, fp
     if (int rc = dispatch_hr(p, a, kRowRefocus, +1, (hipStream_t)stream)) return rc;
   }
   return FPM_OK;
+}
+
+int fpm_timing_enable(fpm_plan* p, int32_t enable) {
+  FPM_REQUIRE(p, "plan must not be NULL");
+  p->timing = enable != 0;
+  return FPM_OK;
+}
+
+int fpm_timing_collect(fpm_plan* p, int32_t max_kinds, const char** names, double* total_ms,
+                       int32_t* counts, int32_t* n_kinds) {
+  FPM_REQUIRE(p && names && total_ms && counts && n_kinds, "arguments must not be NULL");
+  const int n = std::min<int>(max_kinds, kKinds);
+  for (int k = 0; k < n; ++k) {
+    names[k] = kKindNames[k];
+    total_ms[k] = 0.0;
+    counts[k] = 0;
+  }
+  *n_kinds = n;
+  int rc = FPM_OK;
+  for (auto& t : p->timed) {
+    float ms = 0.f;
+    if (hipEventSynchronize(t.stop) != hipSuccess ||
+        hipEventElapsedTime(&ms, t.start, t.stop) != hipSuccess)
+      rc = fail(FPM_EHIP, "reading a timing event failed");
+    if (t.kind < n) {
+      total_ms[t.kind] += ms;
+      counts[t.kind] += 1;
+    }
+    p->event_pool.push_back(t.start);
+    p->event_pool.push_back(t.stop);
+  }
+  p->timed.clear();
+  return rc;
 }
 
 }  // extern "C"

@@ -6,50 +6,9 @@
 
 #include "fft_line.hpp"
 #include "fpm_kernels.hpp"
+#include "fpm_optics.hpp"
 
 namespace fpm {
-
-constexpr int kZern = 15;
-constexpr int kPar = 16;   // 15 Zernike coefficients + defocus
-
-// Optics constants handed to the pupil kernels.
-struct PupilGeom {
-  int n;            // N
-  double inv_r;     // 1 / pupil radius in spectral pixels
-  double dk2;       // dk^2
-  double inv_l;     // 1 / lambda
-};
-
-// OSA/ANSI Zernike terms j = 0..14, unit RMS on the unit disk, as Cartesian
-// polynomials of the normalised pupil coordinates (x along k_x, y along k_y).
-__device__ __forceinline__ void zernike15(double x, double y, double* z) {
-  const double s3 = 1.7320508075688772, s5 = 2.2360679774997897, s6 = 2.4494897427831781;
-  const double s8 = 2.8284271247461901, s10 = 3.1622776601683795;
-  const double x2 = x * x, y2 = y * y, r2 = x2 + y2, xy = x * y;
-  z[0] = 1.0;
-  z[1] = 2.0 * y;
-  z[2] = 2.0 * x;
-  z[3] = s6 * 2.0 * xy;
-  z[4] = s3 * (2.0 * r2 - 1.0);
-  z[5] = s6 * (x2 - y2);
-  z[6] = s8 * (3.0 * x2 - y2) * y;
-  z[7] = s8 * (3.0 * r2 - 2.0) * y;
-  z[8] = s8 * (3.0 * r2 - 2.0) * x;
-  z[9] = s8 * (x2 - 3.0 * y2) * x;
-  z[10] = s10 * 4.0 * xy * (x2 - y2);
-  z[11] = s10 * (4.0 * r2 - 3.0) * 2.0 * xy;
-  z[12] = s5 * (6.0 * r2 * r2 - 6.0 * r2 + 1.0);
-  z[13] = s10 * (4.0 * r2 - 3.0) * (x2 - y2);
-  z[14] = s10 * (x2 * x2 - 6.0 * x2 * y2 + y2 * y2);
-}
-
-// Defocus phase per um, kappa = 2 pi (sqrt(1/l^2 - k^2) - 1/l), written in the
-// cancellation-free form -2 pi k^2 / (sqrt(1/l^2 - k^2) + 1/l); 0 if evanescent.
-__device__ __forceinline__ double defocus_kappa(double k2, double inv_l) {
-  const double a = inv_l * inv_l - k2;
-  if (a < 0.0) return 0.0;
-  return -2.0 * 3.141592653589793 * k2 / (sqrt(a) + inv_l);
-}
 
 __global__ void __launch_bounds__(256)
 pupil_build(PupilGeom g, const int2* __restrict__ rowext, const float* __restrict__ coeffs,
@@ -76,12 +35,10 @@ pupil_build(PupilGeom g, const int2* __restrict__ rowext, const float* __restric
   P[idx] = make_float2((float)cs, (float)sn);
 }
 
-// g_par[j] += sum_u Im(gP conj P) Z_j, g_par[15] += sum_u Im(gP conj P) kappa.
-// With `clear`, gP is zeroed on the disk after it is read.
+// g_par[j] += sum_u Im(gP conj P) Z_j, g_par[15] += sum_u Im(gP conj P) kappa (FP64).
 __global__ void __launch_bounds__(256)
-pupil_grad(PupilGeom g, const int2* __restrict__ rowext, float2* __restrict__ gP,
-           const float2* __restrict__ P, double* __restrict__ g_par, int clear) {
-  __shared__ double part[4][kPar];
+pupil_grad(PupilGeom g, const int2* __restrict__ rowext, const float2* __restrict__ gP,
+           const float2* __restrict__ P, Reduction red, double* __restrict__ g_par) {
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int n = g.n;
   double acc[kPar];
@@ -100,23 +57,17 @@ pupil_grad(PupilGeom g, const int2* __restrict__ rowext, float2* __restrict__ gP
 #pragma unroll
       for (int j = 0; j < kZern; ++j) acc[j] = gth * z[j];
       acc[kZern] = gth * defocus_kappa((ux * ux + uy * uy) * g.dk2, g.inv_l);
-      if (clear) gP[idx] = make_float2(0.f, 0.f);
     }
   }
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  grid_reduce<kPar>(acc, red, [&](const double* tot, int lane) {
+    if (lane < kPar) {
+      double gj = 0.0;
 #pragma unroll
-  for (int j = 0; j < kPar; ++j) {
-    double v = acc[j];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if (lane == 0) part[wave][j] = v;
-  }
-  __syncthreads();
-  if (threadIdx.x < kPar) {
-    const double s = part[0][threadIdx.x] + part[1][threadIdx.x] + part[2][threadIdx.x] +
-                     part[3][threadIdx.x];
-    unsafeAtomicAdd(g_par + threadIdx.x, s);
-  }
+      for (int j = 0; j < kPar; ++j)
+        if (j == lane) gj = tot[j];
+      g_par[lane] += gj;
+    }
+  });
 }
 
 // Adam over 32 x 32 tiles of the HR spectrum (each thread: 8 consecutive floats);
@@ -155,37 +106,6 @@ adam_object(const int2* __restrict__ tiles, int M, float* __restrict__ O, float*
     *pv = v;
     *pg = make_float4(0.f, 0.f, 0.f, 0.f);
   }
-}
-
-// Adam on the pupil parameters (15 Zernike coefficients, defocus), FP64 inside;
-// clears the accumulated gradients.
-struct AdamScalarArgs {
-  float* coeffs; float* m_c; float* v_c; int learn_c;
-  float* z; float* m_z; float* v_z; int learn_z;
-  double lr_c, lr_z, b1, b2, eps, bc1, sqrt_bc2;
-};
-
-__global__ void adam_scalars(AdamScalarArgs a, double* __restrict__ g_par) {
-  const int j = threadIdx.x;
-  if (j >= kPar) return;
-  const double g = g_par[j];
-  g_par[j] = 0.0;
-  float *p, *m, *v;
-  double lr;
-  if (j < kZern) {
-    // piston (j = 0): a global phase with an identically zero gradient, held fixed
-    if (!a.learn_c || j == 0) return;
-    p = a.coeffs + j; m = a.m_c + j; v = a.v_c + j; lr = a.lr_c;
-  } else {
-    if (!a.learn_z) return;
-    p = a.z; m = a.m_z; v = a.v_z; lr = a.lr_z;
-  }
-  const double mm = a.b1 * (double)*m + (1.0 - a.b1) * g;
-  const double vv = a.b2 * (double)*v + (1.0 - a.b2) * g * g;
-  const double den = sqrt(vv) / a.sqrt_bc2 + a.eps;
-  *p = (float)((double)*p - (lr / a.bc1) * mm / den);
-  *m = (float)mm;
-  *v = (float)vv;
 }
 
 // ---------------------------------------------------------------------------

@@ -1,18 +1,26 @@
 // fpm_kernels.hpp - device kernels of the Batch-FPM hot path (gfx950).
 //
-// Per random batch of B LEDs, a loss-and-gradient pass is three launches
+// Per random batch of B LEDs, the loss and its adjoint are three launches
 // (the 2-D transforms of N x N images do not fit one CU's LDS for N >= 256,
 // so they are split into row and column passes that meet in an L2/MALL
 // resident scratch X[B][N][N]):
 //
-//   rows_forward   crop C_b = O[w_b + u] on the pupil disk, Phi = C_b P,
+//   rows_forward   crop C_b = O[w_b + u] on the pupil disk, Phi = C_b P
+//                  (P read, or rebuilt from its Zernike/defocus parameters),
 //                  ifftshift along k_x, inverse DFT of each disk row -> X
 //   cols           inverse DFT of each column (ifftshift along k_y) -> psi,
 //                  amplitude residual e = sqrt(gamma)|psi| - A, loss,
 //                  g_psi = 2 sqrt(gamma) e psi / |psi|, forward DFT of each
 //                  column, keep disk rows (fftshift) -> X (in place)
 //   rows_backward  forward DFT of each disk row, keep disk columns, scatter-add
-//                  conj(P) g_Phi into g_O and conj(C_b) g_Phi into g_P
+//                  conj(P) g_Phi into g_O; the pupil gradient either
+//                  scatter-added into g_P or projected on the spot onto the
+//                  Zernike/defocus parameters
+//
+// Scalar results (loss, parameter gradients) are reduced without contended
+// atomics: each workgroup writes a partial, and the last workgroup to finish
+// (found with one counter atomic) sums the partials in a fixed order, so the
+// sums are deterministic.
 //
 // Workgroups of one LED are placed on one XCD (workgroup id mod 8 selects
 // the XCD) so that the scratch written by one pass is read from the same
@@ -22,6 +30,7 @@
 #include <stdint.h>
 
 #include "fft_line.hpp"
+#include "fpm_optics.hpp"
 
 namespace fpm {
 
@@ -57,47 +66,121 @@ __device__ __forceinline__ void atomic_add_c(float2* p, float2 v) {
   unsafeAtomicAdd(f + 1, v.y);
 }
 
-// Sum a per-thread double over the workgroup and add it to *dst (one atomic per wave).
-__device__ __forceinline__ void wave_atomic_add(double v, double* dst) {
+// Batch description shared by the three passes.
+struct Batch {
+  const int2* shifts;   // [n_led] window offsets (row, col)
+  const int* leds;      // [B] LED ids
+  int B;
+  int n_led;
+  int M;
+};
+
+// Pupil disk: per-row column extents and the row range.
+struct Disk {
+  const int2* rowext;
+  int ky_lo, ky_hi, nrows;
+};
+
+// Per-workgroup partials and the completion counter of a last-workgroup reduction.
+struct Reduction {
+  double* part;
+  unsigned* counter;
+};
+
+// Sum K per-thread values over the workgroup into part[blockIdx.x * K + k], then
+// let the last workgroup to arrive call done(sums) with the grid-wide totals
+// (summed in workgroup order). Every workgroup of the grid must call this.
+template <int K, class V, class Done>
+__device__ __forceinline__ void grid_reduce(const V* vals, Reduction red, Done done) {
+  __shared__ double wsum[16][K];
+  __shared__ int is_last;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwaves = (blockDim.x + 63) >> 6;
 #pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-  if ((threadIdx.x & 63) == 0) unsafeAtomicAdd(dst, v);
+  for (int k = 0; k < K; ++k) {
+    double v = vals[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) wsum[wave][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int w = 0; w < nwaves; ++w) s += wsum[w][threadIdx.x];
+    red.part[(size_t)blockIdx.x * K + threadIdx.x] = s;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) is_last = atomicAdd(red.counter, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!is_last) return;
+  __threadfence();
+  if (threadIdx.x < 64) {
+    double tot[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) tot[k] = 0.0;
+    const volatile double* part = red.part;
+    for (unsigned i = lane; i < gridDim.x; i += 64) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) tot[k] += part[(size_t)i * K + k];
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) tot[k] += __shfl_xor(tot[k], off);
+    }
+    if (lane == 0) {
+      *red.counter = 0u;
+    }
+    done(tot, lane);
+  }
 }
 
 // ---------------------------------------------------------------------------
 // Row pass 1: crop, pupil, inverse DFT along k_x.
-template <int N>
+// kLivePupil: P is rebuilt from its parameters (and written by slot 0).
+template <int N, bool kLivePupil>
 __global__ void __launch_bounds__(kRowThreads)
-rows_forward(const float2* __restrict__ O, int M, const float2* __restrict__ P,
-             const int2* __restrict__ rowext, int ky0, int nrows,
-             const int2* __restrict__ shifts, const int* __restrict__ leds, int B, int n_led,
-             int chunks, float2* __restrict__ X, const float2* __restrict__ tw) {
+rows_forward(const float2* __restrict__ O, const float2* __restrict__ P_in, Batch bt, Disk dk,
+             PupilGeom pg, PupilParams pp, float2* __restrict__ P_out, int chunks,
+             float2* __restrict__ X, const float2* __restrict__ tw) {
   constexpr int T = Plan1D<N>::T;
   constexpr int E = N / T;
   constexpr int L = kRowThreads / T;
   __shared__ float2 lds[L * (N + 1)];
   int b, c;
-  if (!xcd_map(blockIdx.x, chunks, B, b, c)) return;
-  const int led = leds[b];
-  if ((unsigned)led >= (unsigned)n_led) return;   // invalid id: the image contributes nothing
+  if (!xcd_map(blockIdx.x, chunks, bt.B, b, c)) return;
   const int line = threadIdx.x / T;
   const int t = threadIdx.x % T;
   const int rr = c * L + line;
-  const bool active = rr < nrows;
-  const int ky = ky0 + (active ? rr : 0);
-  const int2 s = shifts[led];
-  const int base = M / 2 - N / 2;
-  const int2 ext = rowext[ky];
-  const float2* orow = O + (size_t)(base + s.x + ky) * M + (base + s.y);
-  const float2* prow = P + (size_t)ky * N;
+  const bool active = rr < dk.nrows;
+  const int ky = dk.ky_lo + (active ? rr : 0);
+  const int2 ext = dk.rowext[ky];
+  float2 p[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int kx = half_shift<N>(t + m * T);
+    const bool in = active && kx >= ext.x && kx <= ext.y;
+    if constexpr (kLivePupil) {
+      p[m] = in ? pupil_value(pg, pp, kx, ky) : make_float2(0.f, 0.f);
+      if (in && b == 0) P_out[(size_t)ky * N + kx] = p[m];
+    } else {
+      p[m] = in ? P_in[(size_t)ky * N + kx] : make_float2(0.f, 0.f);
+    }
+  }
+  const int led = bt.leds[b];
+  if ((unsigned)led >= (unsigned)bt.n_led) return;   // invalid id: the image contributes nothing
+  const int2 s = bt.shifts[led];
+  const int base = bt.M / 2 - N / 2;
+  const float2* orow = O + (size_t)(base + s.x + ky) * bt.M + (base + s.y);
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int kx = half_shift<N>(t + m * T);
-    v[m] = (active && kx >= ext.x && kx <= ext.y) ? cmul(orow[kx], prow[kx]) : make_float2(0.f, 0.f);
+    const bool in = active && kx >= ext.x && kx <= ext.y;
+    v[m] = in ? cmul(orow[kx], p[m]) : make_float2(0.f, 0.f);
   }
-  float2* my = lds + line * (N + 1);
-  Plan1D<N>::template run<+1>(v, t, my, [](int n) { return n; }, tw);
+  Plan1D<N>::template run<+1>(v, t, lds + line * (N + 1), [](int n) { return n; }, tw);
   if (active) {
     float2* xr = X + ((size_t)b * N + ky) * N;
 #pragma unroll
@@ -110,103 +193,173 @@ rows_forward(const float2* __restrict__ O, int M, const float2* __restrict__ P,
 template <int N, bool kForward>
 __global__ void __launch_bounds__(ColLines<N>::value * Plan1D<N>::T)
 cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restrict__ gamma,
-     const int* __restrict__ leds, int B, int n_led, int ky_lo, int ky_hi, int groups,
-     double* __restrict__ loss, float* __restrict__ amp_out, float2* __restrict__ field_out,
-     const float2* __restrict__ tw, float inv_m) {
+     Batch bt, Disk dk, int groups, Reduction red, double* __restrict__ loss,
+     float* __restrict__ amp_out, float2* __restrict__ field_out, const float2* __restrict__ tw,
+     float inv_m) {
   constexpr int T = Plan1D<N>::T;
   constexpr int E = N / T;
   constexpr int L = ColLines<N>::value;
   __shared__ float2 lds[N * (L + 1)];
   int b, g;
-  if (!xcd_map(blockIdx.x, groups, B, b, g)) return;
-  const int led = leds[b];
-  if ((unsigned)led >= (unsigned)n_led) return;
+  bool live = xcd_map(blockIdx.x, groups, bt.B, b, g);
+  const int led = live ? bt.leds[b] : -1;
+  live = live && (unsigned)led < (unsigned)bt.n_led;
   const int line = threadIdx.x % L;
   const int t = threadIdx.x / L;
   const int x = g * L + line;
-  float2* xb = X + (size_t)b * N * N;
-  float2 v[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int ky = half_shift<N>(t + m * T);
-    v[m] = (ky >= ky_lo && ky <= ky_hi) ? xb[(size_t)ky * N + x] : make_float2(0.f, 0.f);
-  }
-  auto lay = [line](int n) { return n * (L + 1) + line; };
-  Plan1D<N>::template run<+1>(v, t, lds, lay, tw);
-  const float sg = gamma ? sqrtf(gamma[led]) : 1.0f;
-  if constexpr (kForward) {
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int y = t + m * T;
-      const float2 psi = cscale(v[m], inv_m);
-      const size_t o = ((size_t)b * N + y) * N + x;
-      amp_out[o] = sg * sqrtf(psi.x * psi.x + psi.y * psi.y);
-      if (field_out) field_out[o] = psi;
-    }
-  } else {
-    const float* ab = A + (size_t)led * N * N;
-    float acc = 0.f;
-#pragma unroll
-    for (int m = 0; m < E; ++m) {
-      const int y = t + m * T;
-      const float2 psi = cscale(v[m], inv_m);
-      const float a = sqrtf(psi.x * psi.x + psi.y * psi.y);
-      const float e = sg * a - ab[(size_t)y * N + x];
-      acc += e * e;
-      const float f = a > 0.f ? 2.f * sg * e / a : 0.f;
-      v[m] = cscale(psi, f);
-    }
-    Plan1D<N>::template run<-1>(v, t, lds, lay, tw);
+  float acc = 0.f;
+  if (live) {
+    float2* xb = X + (size_t)b * N * N;
+    float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int ky = half_shift<N>(t + m * T);
-      if (ky >= ky_lo && ky <= ky_hi) xb[(size_t)ky * N + x] = cscale(v[m], inv_m);
+      v[m] = (ky >= dk.ky_lo && ky <= dk.ky_hi) ? xb[(size_t)ky * N + x] : make_float2(0.f, 0.f);
     }
-    if (loss) wave_atomic_add((double)acc, loss);
+    auto lay = [line](int n) { return n * (L + 1) + line; };
+    Plan1D<N>::template run<+1>(v, t, lds, lay, tw);
+    const float sg = gamma ? sqrtf(gamma[led]) : 1.0f;
+    if constexpr (kForward) {
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int y = t + m * T;
+        const float2 psi = cscale(v[m], inv_m);
+        const size_t o = ((size_t)b * N + y) * N + x;
+        amp_out[o] = sg * sqrtf(psi.x * psi.x + psi.y * psi.y);
+        if (field_out) field_out[o] = psi;
+      }
+    } else {
+      const float* ab = A + (size_t)led * N * N;
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int y = t + m * T;
+        const float2 psi = cscale(v[m], inv_m);
+        const float a = sqrtf(psi.x * psi.x + psi.y * psi.y);
+        const float e = sg * a - ab[(size_t)y * N + x];
+        acc += e * e;
+        const float f = a > 0.f ? 2.f * sg * e / a : 0.f;
+        v[m] = cscale(psi, f);
+      }
+      Plan1D<N>::template run<-1>(v, t, lds, lay, tw);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int ky = half_shift<N>(t + m * T);
+        if (ky >= dk.ky_lo && ky <= dk.ky_hi) xb[(size_t)ky * N + x] = cscale(v[m], inv_m);
+      }
+    }
+  }
+  if constexpr (!kForward) {
+    if (loss) {
+      grid_reduce<1>(&acc, red, [&](const double* tot, int lane) {
+        if (lane == 0) *loss += tot[0];
+      });
+    }
   }
 }
 
-// Row pass 2: forward DFT along x, conj-pupil, scatter-add into g_O and g_P.
-template <int N>
+// Adam on the pupil parameters (Zernike 1..14, defocus); FP64 arithmetic.
+struct ScalarAdam {
+  float* coeffs; float* m_c; float* v_c; int learn_c;
+  float* z; float* m_z; float* v_z; int learn_z;
+  double lr_c, lr_z, b1, b2, eps, bc1, sqrt_bc2;
+};
+
+__device__ __forceinline__ void scalar_adam(const ScalarAdam& a, int j, double g) {
+  float *p, *m, *v;
+  double lr;
+  if (j < kZern) {
+    // piston (j = 0): a global phase with an identically zero gradient, held fixed
+    if (!a.learn_c || j == 0) return;
+    p = a.coeffs + j; m = a.m_c + j; v = a.v_c + j; lr = a.lr_c;
+  } else {
+    if (!a.learn_z) return;
+    p = a.z; m = a.m_z; v = a.v_z; lr = a.lr_z;
+  }
+  const double mm = a.b1 * (double)*m + (1.0 - a.b1) * g;
+  const double vv = a.b2 * (double)*v + (1.0 - a.b2) * g * g;
+  const double den = sqrt(vv) / a.sqrt_bc2 + a.eps;
+  *p = (float)((double)*p - lr / a.bc1 * mm / den);
+  *m = (float)mm;
+  *v = (float)vv;
+}
+
+enum RowsBackwardMode { kGradO = 0, kGradOP = 1, kGradOZern = 2 };
+
+// Row pass 2: forward DFT along x, conj-pupil, scatter-add into g_O; the pupil
+// gradient is scatter-added into g_P (kGradOP) or projected onto the Zernike
+// and defocus parameters (kGradOZern; the last workgroup then adds the
+// totals to g_par and, when `adam.learn_c | adam.learn_z`, updates them).
+template <int N, int MODE>
 __global__ void __launch_bounds__(kRowThreads)
-rows_backward(const float2* __restrict__ X, const float2* __restrict__ O, int M,
-              const float2* __restrict__ P, const int2* __restrict__ rowext, int ky0, int nrows,
-              const int2* __restrict__ shifts, const int* __restrict__ leds, int B, int n_led,
-              int chunks, float2* __restrict__ gO, float2* __restrict__ gP,
-              const float2* __restrict__ tw) {
+rows_backward(const float2* __restrict__ X, const float2* __restrict__ O,
+              const float2* __restrict__ P, Batch bt, Disk dk, PupilGeom pg, int chunks,
+              float2* __restrict__ gO, float2* __restrict__ gP, Reduction red,
+              double* __restrict__ g_par, ScalarAdam adam, const float2* __restrict__ tw) {
   constexpr int T = Plan1D<N>::T;
   constexpr int E = N / T;
   constexpr int L = kRowThreads / T;
   __shared__ float2 lds[L * (N + 1)];
   int b, c;
-  if (!xcd_map(blockIdx.x, chunks, B, b, c)) return;
-  const int led = leds[b];
-  if ((unsigned)led >= (unsigned)n_led) return;
+  bool live = xcd_map(blockIdx.x, chunks, bt.B, b, c);
+  const int led = live ? bt.leds[b] : -1;
+  live = live && (unsigned)led < (unsigned)bt.n_led;
   const int line = threadIdx.x / T;
   const int t = threadIdx.x % T;
   const int rr = c * L + line;
-  const bool active = rr < nrows;
-  const int ky = ky0 + (active ? rr : 0);
-  const float2* xr = X + ((size_t)b * N + ky) * N;
-  float2 v[E];
+  const bool active = rr < dk.nrows;
+  const int ky = dk.ky_lo + (active ? rr : 0);
+  float zacc[kPar];
 #pragma unroll
-  for (int m = 0; m < E; ++m) v[m] = active ? xr[t + m * T] : make_float2(0.f, 0.f);
-  float2* my = lds + line * (N + 1);
-  Plan1D<N>::template run<-1>(v, t, my, [](int n) { return n; }, tw);
-  if (!active) return;
-  const int2 s = shifts[led];
-  const int base = M / 2 - N / 2;
-  const int2 ext = rowext[ky];
-  const size_t orow = (size_t)(base + s.x + ky) * M + (base + s.y);
-  const float2* prow = P + (size_t)ky * N;
+  for (int j = 0; j < kPar; ++j) zacc[j] = 0.f;
+  if (live) {
+    const float2* xr = X + ((size_t)b * N + ky) * N;
+    float2 v[E];
 #pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int kx = half_shift<N>(t + m * T);
-    if (kx >= ext.x && kx <= ext.y) {
-      const float2 g = v[m];
-      atomic_add_c(gO + orow + kx, cmulc(prow[kx], g));
-      if (gP) atomic_add_c(gP + (size_t)ky * N + kx, cmulc(O[orow + kx], g));
+    for (int m = 0; m < E; ++m) v[m] = active ? xr[t + m * T] : make_float2(0.f, 0.f);
+    Plan1D<N>::template run<-1>(v, t, lds + line * (N + 1), [](int n) { return n; }, tw);
+    if (active) {
+      const int2 s = bt.shifts[led];
+      const int base = bt.M / 2 - N / 2;
+      const int2 ext = dk.rowext[ky];
+      const size_t orow = (size_t)(base + s.x + ky) * bt.M + (base + s.y);
+      const float2* prow = P + (size_t)ky * N;
+      const float uy = (float)(ky - N / 2);
+#pragma unroll
+      for (int m = 0; m < E; ++m) {
+        const int kx = half_shift<N>(t + m * T);
+        if (kx >= ext.x && kx <= ext.y) {
+          const float2 g = v[m];
+          const float2 p = prow[kx];
+          atomic_add_c(gO + orow + kx, cmulc(p, g));
+          if constexpr (MODE == kGradOP) {
+            atomic_add_c(gP + (size_t)ky * N + kx, cmulc(O[orow + kx], g));
+          } else if constexpr (MODE == kGradOZern) {
+            const float2 gp = cmulc(O[orow + kx], g);           // conj(C) g_Phi
+            const float gth = gp.y * p.x - gp.x * p.y;          // Im(g_P conj(P))
+            const float ux = (float)(kx - N / 2);
+            const float ir = (float)pg.inv_r;
+            float z[kZern];
+            zernike15(ux * ir, uy * ir, z);
+#pragma unroll
+            for (int j = 0; j < kZern; ++j) zacc[j] += gth * z[j];
+            zacc[kZern] += gth * defocus_kappa((ux * ux + uy * uy) * (float)pg.dk2,
+                                               (float)pg.inv_l);
+          }
+        }
+      }
     }
+  }
+  if constexpr (MODE == kGradOZern) {
+    grid_reduce<kPar>(zacc, red, [&](const double* tot, int lane) {
+      if (lane < kPar) {
+        double gj = 0.0;
+#pragma unroll
+        for (int j = 0; j < kPar; ++j)
+          if (j == lane) gj = tot[j];
+        if (g_par) g_par[lane] += gj;
+        scalar_adam(adam, lane, gj);
+      }
+    });
   }
 }
 

@@ -1,0 +1,79 @@
+// fpm_optics.hpp - pupil-plane functions shared by the kernels: OSA/ANSI
+// Zernike terms (Eq. 3's aberrated pupil) and the defocus phase of H(k, z).
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace fpm {
+
+constexpr int kZern = 15;
+constexpr int kPar = 16;   // 15 Zernike coefficients + defocus
+
+// OSA/ANSI Zernike terms j = 0..14, unit RMS on the unit disk, as Cartesian
+// polynomials of the normalised pupil coordinates (x along k_x, y along k_y).
+template <class R>
+__device__ __forceinline__ void zernike15(R x, R y, R* z) {
+  const R s3 = R(1.7320508075688772), s5 = R(2.2360679774997897), s6 = R(2.4494897427831781);
+  const R s8 = R(2.8284271247461901), s10 = R(3.1622776601683795);
+  const R x2 = x * x, y2 = y * y, r2 = x2 + y2, xy = x * y;
+  z[0] = R(1);
+  z[1] = R(2) * y;
+  z[2] = R(2) * x;
+  z[3] = s6 * R(2) * xy;
+  z[4] = s3 * (R(2) * r2 - R(1));
+  z[5] = s6 * (x2 - y2);
+  z[6] = s8 * (R(3) * x2 - y2) * y;
+  z[7] = s8 * (R(3) * r2 - R(2)) * y;
+  z[8] = s8 * (R(3) * r2 - R(2)) * x;
+  z[9] = s8 * (x2 - R(3) * y2) * x;
+  z[10] = s10 * R(4) * xy * (x2 - y2);
+  z[11] = s10 * (R(4) * r2 - R(3)) * R(2) * xy;
+  z[12] = s5 * (R(6) * r2 * r2 - R(6) * r2 + R(1));
+  z[13] = s10 * (R(4) * r2 - R(3)) * (x2 - y2);
+  z[14] = s10 * (x2 * x2 - R(6) * x2 * y2 + y2 * y2);
+}
+
+// Defocus phase per um, kappa = 2 pi (sqrt(1/l^2 - k^2) - 1/l), written in the
+// cancellation-free form -2 pi k^2 / (sqrt(1/l^2 - k^2) + 1/l); 0 if evanescent.
+template <class R>
+__device__ __forceinline__ R defocus_kappa(R k2, R inv_l) {
+  const R a = inv_l * inv_l - k2;
+  if (a < R(0)) return R(0);
+  return R(-6.283185307179586) * k2 / (sqrt(a) + inv_l);
+}
+
+// Pupil-plane constants (N, 1/radius in pixels, dk^2, 1/lambda).
+struct PupilGeom {
+  int n;
+  double inv_r;
+  double dk2;
+  double inv_l;
+};
+
+// Learned pupil parameters as device pointers (NULL: zero).
+struct PupilParams {
+  const float* coeffs;
+  int n_zern;
+  const float* z_um;
+};
+
+// P(u) = exp(i (sum_j c_j Z_j(u) + z kappa(u))) on the disk, in FP32.
+__device__ __forceinline__ float2 pupil_value(const PupilGeom& g, const PupilParams& pp, int kx,
+                                              int ky) {
+  const float ux = (float)(kx - g.n / 2), uy = (float)(ky - g.n / 2);
+  float th = 0.f;
+  if (pp.coeffs && pp.n_zern > 0) {
+    float z[kZern];
+    const float ir = (float)g.inv_r;
+    zernike15(ux * ir, uy * ir, z);
+#pragma unroll
+    for (int j = 0; j < kZern; ++j)
+      if (j < pp.n_zern) th += pp.coeffs[j] * z[j];
+  }
+  if (pp.z_um)
+    th += pp.z_um[0] * defocus_kappa((ux * ux + uy * uy) * (float)g.dk2, (float)g.inv_l);
+  float s, c;
+  sincosf(th, &s, &c);
+  return make_float2(c, s);
+}
+
+}  // namespace fpm

@@ -72,9 +72,14 @@ EXPORTS = {
     "fpm_pupil_grad": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "fpm_step": [C.c_void_p, C.POINTER(_State), C.POINTER(_HParams), C.c_void_p, C.c_int32,
                  C.c_void_p, C.c_void_p, C.c_void_p],
+    "fpm_run": [C.c_void_p, C.POINTER(_State), C.POINTER(_HParams), C.c_void_p, C.c_void_p,
+                C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
     "fpm_hr_transform": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
     "fpm_init_spectrum": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "fpm_refocus": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
+    "fpm_timing_enable": [C.c_void_p, C.c_int32],
+    "fpm_timing_collect": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                           C.POINTER(C.c_int32)],
 }
 
 _lib = None
@@ -105,6 +110,25 @@ def _check(rc: int):
 
 def _ptr(t):
     return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _need(t, name, dtype, shape=None, min_numel=None, optional=False):
+    """Check a device tensor before its pointer crosses the ABI (sizes are not re-checked there)."""
+    import torch
+    if t is None:
+        if optional:
+            return
+        raise FpmError(f"{name} is required")
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise FpmError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise FpmError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise FpmError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise FpmError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if min_numel is not None and t.numel() < min_numel:
+        raise FpmError(f"{name} needs at least {min_numel} elements")
 
 
 def _stream(device=None):
@@ -224,18 +248,48 @@ class Plan:
 
     # -- entry points -------------------------------------------------------
 
+    # -- argument checks ------------------------------------------------------
+
+    def _spectrum(self, O, name="O"):
+        import torch
+        _need(O, name, torch.complex64, (self.M, self.M))
+
+    def _pupil(self, P, name="P"):
+        import torch
+        _need(P, name, torch.complex64, (self.N, self.N))
+
+    def _leds(self, leds):
+        import torch
+        _need(leds, "leds", torch.int32)
+        if leds.dim() != 1:
+            raise FpmError("leds must be one-dimensional")
+        return int(leds.numel())
+
+    def _images(self, A, gamma):
+        import torch
+        _need(A, "meas_amp", torch.float32, (self.n_led, self.N, self.N))
+        _need(gamma, "gamma", torch.float32, (self.n_led,), optional=True)
+
     def pupil(self, coeffs=None, z_um=None, out=None):
         import torch
         dev = torch.device("cuda", torch.cuda.current_device())
         if out is None:
             out = torch.empty((self.N, self.N), dtype=torch.complex64, device=dev)
+        self._pupil(out, "out")
+        _need(coeffs, "coeffs", torch.float32, optional=True)
+        _need(z_um, "z_um", torch.float32, min_numel=1, optional=True)
+        if coeffs is not None and coeffs.numel() > N_ZERN:
+            raise FpmError("at most 15 Zernike coefficients")
         n = 0 if coeffs is None else int(coeffs.numel())
         _check(self._lib.fpm_pupil(self._h, _ptr(coeffs), n, _ptr(z_um), _ptr(out), _stream()))
         return out
 
     def forward(self, O, P, leds, gamma=None, with_field=False):
         import torch
-        B = int(leds.numel())
+        self._spectrum(O)
+        self._pupil(P)
+        B = self._leds(leds)
+        _need(gamma, "gamma", torch.float32, (self.n_led,), optional=True)
         amp = torch.empty((B, self.N, self.N), dtype=torch.float32, device=O.device)
         field = (torch.empty((B, self.N, self.N), dtype=torch.complex64, device=O.device)
                  if with_field else None)
@@ -244,39 +298,91 @@ class Plan:
         return (amp, field) if with_field else amp
 
     def backward(self, O, P, leds, meas_amp, gO, gP=None, loss=None, gamma=None):
-        B = int(leds.numel())
+        import torch
+        self._spectrum(O)
+        self._pupil(P)
+        B = self._leds(leds)
+        self._images(meas_amp, gamma)
+        self._spectrum(gO, "gO")
+        _need(gP, "gP", torch.complex64, (self.N, self.N), optional=True)
+        _need(loss, "loss", torch.float64, min_numel=1, optional=True)
         _check(self._lib.fpm_backward(self._h, _ptr(O), _ptr(P), _ptr(leds), B, _ptr(gamma),
                                       _ptr(meas_amp), _ptr(gO), _ptr(gP), _ptr(loss), _stream()))
 
     def pupil_grad(self, gP, P, g_par):
+        import torch
+        self._pupil(gP, "gP")
+        self._pupil(P)
+        _need(g_par, "g_par", torch.float64, min_numel=N_PAR)
         _check(self._lib.fpm_pupil_grad(self._h, _ptr(gP), _ptr(P), _ptr(g_par), _stream()))
 
     def step(self, state: State, hp: HParams, leds, meas_amp, gamma=None):
+        B = self._leds(leds)
+        self._images(meas_amp, gamma)
+        self._spectrum(state.O)
+        self._pupil(state.P)
         cs = state.c()
         hc = hp.c()
-        B = int(leds.numel())
         _check(self._lib.fpm_step(self._h, C.byref(cs), C.byref(hc), _ptr(leds), B, _ptr(gamma),
                                   _ptr(meas_amp), _stream()))
         state.t = cs.t
 
+    def run(self, state: State, hp: HParams, leds_flat, batch_sizes, meas_amp, gamma=None):
+        """Consecutive updates: batch i is the next batch_sizes[i] ids of leds_flat."""
+        sizes = np.ascontiguousarray(np.asarray(batch_sizes, np.int32))
+        n = self._leds(leds_flat)
+        if int(sizes.sum()) > n:
+            raise FpmError("batch sizes exceed the number of LED ids")
+        self._images(meas_amp, gamma)
+        self._spectrum(state.O)
+        self._pupil(state.P)
+        cs = state.c()
+        hc = hp.c()
+        _check(self._lib.fpm_run(self._h, C.byref(cs), C.byref(hc), _ptr(leds_flat),
+                                 sizes.ctypes.data, int(sizes.size), _ptr(gamma), _ptr(meas_amp),
+                                 _stream()))
+        state.t = cs.t
+
     def hr_transform(self, x, direction: int, out=None):
         import torch
+        self._spectrum(x, "in")
         if out is None:
             out = torch.empty_like(x)
+        self._spectrum(out, "out")
         _check(self._lib.fpm_hr_transform(self._h, _ptr(x), _ptr(out), int(direction), _stream()))
         return out
 
     def init_spectrum(self, centre_amp, out=None):
         import torch
+        _need(centre_amp, "centre_amp", torch.float32, (self.N, self.N))
         if out is None:
             out = torch.empty((self.M, self.M), dtype=torch.complex64, device=centre_amp.device)
+        self._spectrum(out, "out")
         _check(self._lib.fpm_init_spectrum(self._h, _ptr(centre_amp), _ptr(out), _stream()))
         return out
 
+    def timing(self, enable: bool):
+        _check(self._lib.fpm_timing_enable(self._h, int(bool(enable))))
+
+    def timing_collect(self) -> dict:
+        """{kernel name: (total ms, launches)} since the last collection."""
+        kmax = 32
+        names = (C.c_char_p * kmax)()
+        total = np.zeros(kmax, np.float64)
+        counts = np.zeros(kmax, np.int32)
+        nk = C.c_int32(0)
+        _check(self._lib.fpm_timing_collect(self._h, kmax, C.cast(names, C.c_void_p),
+                                            total.ctypes.data, counts.ctypes.data, C.byref(nk)))
+        return {names[i].decode(): (float(total[i]), int(counts[i])) for i in range(nk.value)
+                if counts[i] > 0}
+
     def refocus(self, O, z_um, out=None):
         import torch
+        self._spectrum(O)
+        _need(z_um, "z_um", torch.float32)
         nz = int(z_um.numel())
         if out is None:
             out = torch.empty((nz, self.M, self.M), dtype=torch.complex64, device=O.device)
+        _need(out, "out", torch.complex64, (nz, self.M, self.M))
         _check(self._lib.fpm_refocus(self._h, _ptr(O), _ptr(z_um), nz, _ptr(out), _stream()))
         return out

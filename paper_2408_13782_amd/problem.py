@@ -92,20 +92,33 @@ def hparams(w: inputs.Workload) -> fpm.HParams:
                        learn_zernike=w.learn_zernike, learn_z=w.learn_z)
 
 
-def upload_schedule(batches, device="cuda"):
-    """All batches as one device array plus per-step views (no host work per step)."""
+@dataclass
+class DeviceSchedule:
+    flat: object            # torch int32 [sum of batch sizes], all batches back to back
+    sizes: np.ndarray       # int32 [n_steps]
+    offsets: np.ndarray     # int64 [n_steps] start of each batch in flat
+
+    def view(self, i: int):
+        return self.flat[int(self.offsets[i]):int(self.offsets[i]) + int(self.sizes[i])]
+
+    def span(self, start: int, stop: int):
+        """(flat ids, sizes) of steps start..stop-1, for Plan.run."""
+        a = int(self.offsets[start]) if start < len(self.sizes) else int(self.flat.numel())
+        b = int(self.offsets[stop]) if stop < len(self.sizes) else int(self.flat.numel())
+        return self.flat[a:b], self.sizes[start:stop]
+
+
+def upload_schedule(batches, device="cuda") -> DeviceSchedule:
+    """All batches as one device array (no host-to-device copy per step)."""
     import torch
-    flat = np.concatenate(batches).astype(np.int32)
-    dev = torch.as_tensor(flat, device=device)
-    views, off = [], 0
-    for b in batches:
-        views.append(dev[off:off + len(b)])
-        off += len(b)
-    return views
+    sizes = np.array([len(b) for b in batches], np.int32)
+    offsets = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
+    flat = torch.as_tensor(np.concatenate(batches).astype(np.int32), device=device)
+    return DeviceSchedule(flat, sizes, offsets)
 
 
-def solve(prob: Problem, state: fpm.State, hp: fpm.HParams, batch_views, gamma=None):
-    """Run the random-batch updates; state.loss accumulates the summed loss."""
-    for leds in batch_views:
-        prob.plan.step(state, hp, leds, prob.meas_amp, gamma)
+def solve(prob: Problem, state: fpm.State, hp: fpm.HParams, sched: DeviceSchedule, gamma=None):
+    """Run every random-batch update of the schedule in one library call."""
+    flat, sizes = sched.span(0, len(sched.sizes))
+    prob.plan.run(state, hp, flat, sizes, prob.meas_amp, gamma)
     return state

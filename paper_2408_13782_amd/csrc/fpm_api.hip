@@ -62,8 +62,7 @@ enum Kind {
   kHrRows, kHrCols, kKinds
 };
 const char* const kKindNames[kKinds] = {"pupil_build", "rows_forward", "cols", "rows_backward",
-                                        "pupil_grad", "adam_object", "adam_scalars", "hr_rows",
-                                        "hr_cols"};
+                                        "pupil_grad", "update", "commit", "hr_rows", "hr_cols"};
 constexpr size_t kMaxTimed = 65536;
 
 struct TimedLaunch {
@@ -88,8 +87,12 @@ struct fpm_plan {
   float2* X = nullptr;        // [max_batch][N][N] row/column scratch
   float2* gP = nullptr;       // [N][N] pupil-gradient accumulator for fpm_step
   int2* tiles = nullptr;      // [n_tiles] 32 x 32 HR tiles covered by some window
-  double* part = nullptr;     // per-workgroup partial sums of the grid reductions
-  unsigned* counters = nullptr;  // completion counters, one per reducing kernel
+  double* part = nullptr;     // per-workgroup partial sums (loss | Zernike | pupil_grad)
+  double* part_loss = nullptr;
+  double* part_z = nullptr;
+  double* part_pg = nullptr;
+  float* staging = nullptr;   // next pupil-parameter state, written by the update kernel
+  unsigned* counters = nullptr;  // completion counter of pupil_grad's reduction
   bool timing = false;
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> event_pool;
@@ -146,6 +149,7 @@ void plan_free(fpm_plan* p) {
   (void)hipFree(p->gP);
   (void)hipFree(p->tiles);
   (void)hipFree(p->part);
+  (void)hipFree(p->staging);
   (void)hipFree(p->counters);
   delete p;
 }
@@ -173,7 +177,7 @@ int check_batch(const fpm_plan* p, const int32_t* leds, int32_t B) {
   return FPM_OK;
 }
 
-enum { kCounterCols = 0, kCounterRows = 1, kCounterPupil = 2, kCounters = 3 };
+enum { kCounterPupil = 0, kCounters = 1 };
 
 Batch batch_of(const fpm_plan* p, const int32_t* leds, int B) {
   Batch b;
@@ -194,66 +198,65 @@ Disk disk_of(const fpm_plan* p) {
   return d;
 }
 
-Reduction reduction_of(const fpm_plan* p, int which) {
-  Reduction r;
-  r.part = p->part;
-  r.counter = p->counters + which;
-  return r;
+template <int N> constexpr int row_lines() { return kRowThreads / Plan1D<N>::T; }
+
+struct Grids {
+  int slots, row_chunks, col_groups;
+  int rows() const { return slots * row_chunks; }
+  int cols() const { return slots * col_groups; }
+};
+
+template <int N>
+Grids grids_of(const fpm_plan* p, int B) {
+  Grids g;
+  g.slots = (B + kXcds - 1) / kXcds * kXcds;
+  g.row_chunks = (p->nrows + row_lines<N>() - 1) / row_lines<N>();
+  g.col_groups = N / ColLines<N>::value;
+  return g;
 }
 
 // What a loss-and-gradient pass produces besides g_O.
 struct BackwardOut {
-  bool live_pupil = false;    // rebuild P from pp into P (slot 0 writes it)
-  PupilParams pp{};
   int mode = kGradO;          // rows_backward mode
   float2* gP = nullptr;       // kGradOP
-  double* g_par = nullptr;    // kGradOZern: += parameter gradients (nullable)
-  ScalarAdam adam{};          // kGradOZern: Adam on the pupil parameters
-  double* loss = nullptr;
+  bool loss = false;          // column pass stores loss partials in part_loss
+  int commit = 0;             // rows_forward commits the staged pupil-parameter state
+  ScalarState scal{};
 };
 
 template <int N>
-int launch_backward(fpm_plan* p, const float2* O, float2* P, const int32_t* leds, int B,
+int launch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t* leds, int B,
                     const float* gamma, const float* A, float2* gO, const BackwardOut& o,
                     hipStream_t st) {
-  constexpr int Lr = kRowThreads / Plan1D<N>::T;
-  constexpr int Lc = ColLines<N>::value;
-  const int slots = (B + kXcds - 1) / kXcds * kXcds;
-  const int row_chunks = (p->nrows + Lr - 1) / Lr;
-  const int col_groups = N / Lc;
+  const Grids gr = grids_of<N>(p, B);
   const Batch bt = batch_of(p, leds, B);
   const Disk dk = disk_of(p);
-  const PupilGeom pg = pupil_geom(p);
   {
     Timed tm(p, kRowsForward, st);
-    if (o.live_pupil)
-      rows_forward<N, true><<<slots * row_chunks, kRowThreads, 0, st>>>(
-          O, P, bt, dk, pg, o.pp, P, row_chunks, p->X, p->twN);
-    else
-      rows_forward<N, false><<<slots * row_chunks, kRowThreads, 0, st>>>(
-          O, P, bt, dk, pg, o.pp, nullptr, row_chunks, p->X, p->twN);
+    rows_forward<N><<<gr.rows(), kRowThreads, 0, st>>>(O, P, bt, dk, gr.row_chunks, p->X,
+                                                         p->twN, o.commit, p->staging, o.scal);
   }
   {
     Timed tm(p, kCols, st);
-    cols<N, false><<<slots * col_groups, Lc * Plan1D<N>::T, 0, st>>>(
-        p->X, A, gamma, bt, dk, col_groups, reduction_of(p, kCounterCols), o.loss, nullptr,
-        nullptr, p->twN, 1.0f / p->M);
+    cols<N, false><<<gr.cols(), ColLines<N>::value * Plan1D<N>::T, 0, st>>>(
+        p->X, A, gamma, bt, dk, gr.col_groups, o.loss ? p->part_loss : nullptr, nullptr, nullptr,
+        p->twN, 1.0f / p->M);
   }
   {
     Timed tm(p, kRowsBackward, st);
-    const Reduction red = reduction_of(p, kCounterRows);
+    const PupilGeom pg = pupil_geom(p);
     switch (o.mode) {
       case kGradO:
-        rows_backward<N, kGradO><<<slots * row_chunks, kRowThreads, 0, st>>>(
-            p->X, O, P, bt, dk, pg, row_chunks, gO, nullptr, red, nullptr, o.adam, p->twN);
+        rows_backward<N, kGradO><<<gr.rows(), kRowThreads, 0, st>>>(
+            p->X, O, P, bt, dk, pg, gr.row_chunks, gO, nullptr, nullptr, p->twN);
         break;
       case kGradOP:
-        rows_backward<N, kGradOP><<<slots * row_chunks, kRowThreads, 0, st>>>(
-            p->X, O, P, bt, dk, pg, row_chunks, gO, o.gP, red, nullptr, o.adam, p->twN);
+        rows_backward<N, kGradOP><<<gr.rows(), kRowThreads, 0, st>>>(
+            p->X, O, P, bt, dk, pg, gr.row_chunks, gO, o.gP, nullptr, p->twN);
         break;
       default:
-        rows_backward<N, kGradOZern><<<slots * row_chunks, kRowThreads, 0, st>>>(
-            p->X, O, P, bt, dk, pg, row_chunks, gO, nullptr, red, o.g_par, o.adam, p->twN);
+        rows_backward<N, kGradOZern><<<gr.rows(), kRowThreads, 0, st>>>(
+            p->X, O, P, bt, dk, pg, gr.row_chunks, gO, nullptr, p->part_z, p->twN);
         break;
     }
   }
@@ -264,29 +267,24 @@ int launch_backward(fpm_plan* p, const float2* O, float2* P, const int32_t* leds
 template <int N>
 int launch_forward(fpm_plan* p, const float2* O, const float2* P, const int32_t* leds, int B,
                    const float* gamma, float* amp, float2* field, hipStream_t st) {
-  constexpr int Lr = kRowThreads / Plan1D<N>::T;
-  constexpr int Lc = ColLines<N>::value;
-  const int slots = (B + kXcds - 1) / kXcds * kXcds;
-  const int row_chunks = (p->nrows + Lr - 1) / Lr;
-  const int col_groups = N / Lc;
+  const Grids gr = grids_of<N>(p, B);
   const Batch bt = batch_of(p, leds, B);
   const Disk dk = disk_of(p);
   {
     Timed tm(p, kRowsForward, st);
-    rows_forward<N, false><<<slots * row_chunks, kRowThreads, 0, st>>>(
-        O, P, bt, dk, pupil_geom(p), PupilParams{}, nullptr, row_chunks, p->X, p->twN);
+    rows_forward<N><<<gr.rows(), kRowThreads, 0, st>>>(O, P, bt, dk, gr.row_chunks, p->X,
+                                                         p->twN, 0, nullptr, ScalarState{});
   }
   {
     Timed tm(p, kCols, st);
-    cols<N, true><<<slots * col_groups, Lc * Plan1D<N>::T, 0, st>>>(
-        p->X, nullptr, gamma, bt, dk, col_groups, reduction_of(p, kCounterCols), nullptr, amp,
-        field, p->twN, 1.0f / p->M);
+    cols<N, true><<<gr.cols(), ColLines<N>::value * Plan1D<N>::T, 0, st>>>(
+        p->X, nullptr, gamma, bt, dk, gr.col_groups, nullptr, amp, field, p->twN, 1.0f / p->M);
   }
   FPM_HIP(hipGetLastError());
   return FPM_OK;
 }
 
-int dispatch_backward(fpm_plan* p, const float2* O, float2* P, const int32_t* leds, int B,
+int dispatch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t* leds, int B,
                       const float* gamma, const float* A, float2* gO, const BackwardOut& o,
                       hipStream_t st) {
   switch (p->N) {
@@ -298,21 +296,35 @@ int dispatch_backward(fpm_plan* p, const float2* O, float2* P, const int32_t* le
   return fail(FPM_EUNSUPPORTED, "unsupported N");
 }
 
-// Largest grid of any reducing kernel (sizes the partial-sum buffer).
-int max_reduce_grid(const fpm_plan* p) {
-  const int slots = (p->max_batch + kXcds - 1) / kXcds * kXcds;
-  int rows_l = 0, cols_l = 0;
+// Grid sizes of the reducing kernels at B = max_batch (sizes the partial buffers).
+void reduce_grids(const fpm_plan* p, int& rows_grid, int& cols_grid) {
   switch (p->N) {
-    case 64: rows_l = kRowThreads / Plan1D<64>::T; cols_l = ColLines<64>::value; break;
-    case 128: rows_l = kRowThreads / Plan1D<128>::T; cols_l = ColLines<128>::value; break;
-    case 256: rows_l = kRowThreads / Plan1D<256>::T; cols_l = ColLines<256>::value; break;
-    case 512: rows_l = kRowThreads / Plan1D<512>::T; cols_l = ColLines<512>::value; break;
+    case 64: { auto g = grids_of<64>(p, p->max_batch); rows_grid = g.rows(); cols_grid = g.cols(); break; }
+    case 128: { auto g = grids_of<128>(p, p->max_batch); rows_grid = g.rows(); cols_grid = g.cols(); break; }
+    case 256: { auto g = grids_of<256>(p, p->max_batch); rows_grid = g.rows(); cols_grid = g.cols(); break; }
+    default: { auto g = grids_of<512>(p, p->max_batch); rows_grid = g.rows(); cols_grid = g.cols(); break; }
   }
-  const int rows_grid = slots * ((p->nrows + rows_l - 1) / rows_l);
-  const int cols_grid = slots * (p->N / cols_l);
-  const int pupil_grid = (p->N * p->N + 255) / 256;
-  return std::max(rows_grid, std::max(cols_grid, pupil_grid));
 }
+
+int rows_grid_of(const fpm_plan* p, int B) {
+  switch (p->N) {
+    case 64: return grids_of<64>(p, B).rows();
+    case 128: return grids_of<128>(p, B).rows();
+    case 256: return grids_of<256>(p, B).rows();
+    default: return grids_of<512>(p, B).rows();
+  }
+}
+
+int cols_grid_of(const fpm_plan* p, int B) {
+  switch (p->N) {
+    case 64: return grids_of<64>(p, B).cols();
+    case 128: return grids_of<128>(p, B).cols();
+    case 256: return grids_of<256>(p, B).cols();
+    default: return grids_of<512>(p, B).cols();
+  }
+}
+
+int pupil_wgs(const fpm_plan* p) { return (p->N * p->N + kPupilPerWg - 1) / kPupilPerWg; }
 
 template <int M>
 int launch_hr(fpm_plan* p, HrArgs a, int row_mode, int dir, hipStream_t st) {
@@ -454,12 +466,19 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
     plan_free(p);
     return rc;
   }
-  const size_t n_part = (size_t)max_reduce_grid(p) * kPar;
+  int rows_grid = 0, cols_grid = 0;
+  reduce_grids(p, rows_grid, cols_grid);
+  const int pg_grid = (p->N * p->N + 255) / 256;
+  const size_t n_part = (size_t)cols_grid + (size_t)rows_grid * kPar + (size_t)pg_grid * kPar;
   if ((rc = upload<double>(&p->part, nullptr, n_part)) ||
+      (rc = upload<float>(&p->staging, nullptr, kScal)) ||
       (rc = upload<unsigned>(&p->counters, nullptr, kCounters))) {
     plan_free(p);
     return rc;
   }
+  p->part_loss = p->part;
+  p->part_z = p->part + cols_grid;
+  p->part_pg = p->part_z + (size_t)rows_grid * kPar;
   if (hipMemset(p->counters, 0, kCounters * sizeof(unsigned)) != hipSuccess) {
     plan_free(p);
     return fail(FPM_EHIP, "hipMemset failed");
@@ -569,11 +588,22 @@ int fpm_backward(fpm_plan* p, const fpm_c32* O, const fpm_c32* P, const int32_t*
   BackwardOut o;
   o.mode = gP ? kGradOP : kGradO;
   o.gP = reinterpret_cast<float2*>(gP);
-  o.loss = loss;
-  return dispatch_backward(p, reinterpret_cast<const float2*>(O),
-                           const_cast<float2*>(reinterpret_cast<const float2*>(P)), leds, B,
-                           gamma, meas_amp, reinterpret_cast<float2*>(gO), o,
-                           (hipStream_t)stream);
+  o.loss = loss != nullptr;
+  hipStream_t st = (hipStream_t)stream;
+  if (int rc = dispatch_backward(p, reinterpret_cast<const float2*>(O),
+                                 reinterpret_cast<const float2*>(P), leds, B, gamma, meas_amp,
+                                 reinterpret_cast<float2*>(gO), o, st))
+    return rc;
+  if (loss) {   // add the column pass's partials (fixed order)
+    UpdateArgs a{};
+    a.loss_part = p->part_loss;
+    a.n_loss = cols_grid_of(p, B);
+    a.loss = loss;
+    Timed tm(p, kAdamObject, st);
+    update<<<1, 256, 0, st>>>(a);
+    FPM_HIP(hipGetLastError());
+  }
+  return FPM_OK;
 }
 
 int fpm_pupil_grad(fpm_plan* p, const fpm_c32* gP, const fpm_c32* P, double* g_par,
@@ -584,7 +614,8 @@ int fpm_pupil_grad(fpm_plan* p, const fpm_c32* gP, const fpm_c32* P, double* g_p
   Timed tm(p, kPupilGrad, (hipStream_t)stream);
   pupil_grad<<<(nn + 255) / 256, 256, 0, (hipStream_t)stream>>>(
       pupil_geom(p), p->rowext, reinterpret_cast<const float2*>(gP),
-      reinterpret_cast<const float2*>(P), reduction_of(p, kCounterPupil), g_par);
+      reinterpret_cast<const float2*>(P), Reduction{p->part_pg, p->counters + kCounterPupil},
+      g_par);
   FPM_HIP(hipGetLastError());
   return FPM_OK;
 }
@@ -603,48 +634,81 @@ int check_state(fpm_plan* p, const fpm_state* s, const fpm_hparams* hp, const fl
   return check_device(p);
 }
 
-// One update: loss and gradients (pupil rebuilt and its parameters updated
-// inside the row passes when learned), then Adam on the spectrum.
+ScalarState scalar_state_of(const fpm_state* s) {
+  ScalarState d;
+  d.coeffs = s->coeffs; d.m_c = s->m_c; d.v_c = s->v_c;
+  d.z = s->z_um; d.m_z = s->m_z; d.v_z = s->v_z;
+  return d;
+}
+
+// One update: loss and gradients of the batch (projected onto the pupil
+// parameters when they are learned), then the update kernel (Adam on the
+// spectrum; Adam on the pupil parameters and the pupil rebuilt from them).
+// `commit`: the previous step of this call staged a pupil-parameter state.
 int step_launches(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_t* leds, int B,
-                  const float* gamma, const float* meas_amp, hipStream_t st) {
+                  const float* gamma, const float* meas_amp, int commit, hipStream_t st) {
   const bool learn_c = hp->learn_zernike != 0, learn_z = hp->learn_z != 0;
+  const bool learn_p = learn_c || learn_z;
   const int t = s->t + 1;
   const double b1 = hp->beta1, b2 = hp->beta2;
   const double bc1 = 1.0 - std::pow(b1, t), bc2 = 1.0 - std::pow(b2, t);
   float2* P = reinterpret_cast<float2*>(s->P);
   BackwardOut o;
-  o.loss = s->loss;
-  if (learn_c || learn_z) {
-    o.live_pupil = true;
-    o.pp.coeffs = s->coeffs;
-    o.pp.n_zern = s->coeffs ? kZern : 0;
-    o.pp.z_um = s->z_um;
-    o.mode = kGradOZern;
-    o.g_par = s->g_par;
-    ScalarAdam& a = o.adam;
-    a.coeffs = s->coeffs; a.m_c = s->m_c; a.v_c = s->v_c; a.learn_c = learn_c;
-    a.z = s->z_um; a.m_z = s->m_z; a.v_z = s->v_z; a.learn_z = learn_z;
-    a.lr_c = hp->lr_zernike; a.lr_z = hp->lr_z;
-    a.b1 = b1; a.b2 = b2; a.eps = hp->eps; a.bc1 = bc1; a.sqrt_bc2 = std::sqrt(bc2);
-  }
+  o.mode = learn_p ? kGradOZern : kGradO;
+  o.loss = s->loss != nullptr;
+  o.commit = commit;
+  o.scal = scalar_state_of(s);
   if (int rc = dispatch_backward(p, reinterpret_cast<const float2*>(s->O), P, leds, B, gamma,
                                  meas_amp, reinterpret_cast<float2*>(s->g_O), o, st))
     return rc;
-  AdamCoef c;
-  c.b1 = hp->beta1;
-  c.b2 = hp->beta2;
-  c.eps = hp->eps;
-  c.step_size = (float)(hp->lr_object / bc1);
-  c.sqrt_bc2 = (float)std::sqrt(bc2);
+  UpdateArgs a{};
+  a.tiles = p->tiles;
+  a.n_tiles = p->n_tiles;
+  a.M = p->M;
+  a.O = reinterpret_cast<float*>(s->O);
+  a.mO = reinterpret_cast<float*>(s->m_O);
+  a.vO = reinterpret_cast<float*>(s->v_O);
+  a.gO = reinterpret_cast<float*>(s->g_O);
+  a.c.b1 = hp->beta1;
+  a.c.b2 = hp->beta2;
+  a.c.eps = hp->eps;
+  a.c.step_size = (float)(hp->lr_object / bc1);
+  a.c.sqrt_bc2 = (float)std::sqrt(bc2);
+  a.loss_part = p->part_loss;
+  a.n_loss = cols_grid_of(p, B);
+  a.loss = s->loss;
+  a.pupil = learn_p;
+  a.zpart = p->part_z;
+  a.n_zpart = rows_grid_of(p, B);
+  a.cur = o.scal;
+  a.sa.learn_c = learn_c;
+  a.sa.learn_z = learn_z;
+  a.sa.lr_c = hp->lr_zernike;
+  a.sa.lr_z = hp->lr_z;
+  a.sa.b1 = b1;
+  a.sa.b2 = b2;
+  a.sa.eps = hp->eps;
+  a.sa.bc1 = bc1;
+  a.sa.sqrt_bc2 = std::sqrt(bc2);
+  a.g_par = s->g_par;
+  a.staging = p->staging;
+  a.pg = pupil_geom(p);
+  a.rowext = p->rowext;
+  a.P = P;
+  const int extra = learn_p ? pupil_wgs(p) : 1;
   {
     Timed tm(p, kAdamObject, st);
-    adam_object<<<p->n_tiles, 256, 0, st>>>(p->tiles, p->M, reinterpret_cast<float*>(s->O),
-                                            reinterpret_cast<float*>(s->m_O),
-                                            reinterpret_cast<float*>(s->v_O),
-                                            reinterpret_cast<float*>(s->g_O), c);
+    update<<<p->n_tiles + extra, 256, 0, st>>>(a);
   }
   FPM_HIP(hipGetLastError());
   s->t = t;
+  return FPM_OK;
+}
+
+int commit_launch(fpm_plan* p, const fpm_state* s, hipStream_t st) {
+  Timed tm(p, kAdamScalars, st);
+  commit_scalar_state<<<1, 64, 0, st>>>(p->staging, scalar_state_of(s));
+  FPM_HIP(hipGetLastError());
   return FPM_OK;
 }
 
@@ -657,7 +721,10 @@ int fpm_step(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_t* le
   if (int rc = check_state(p, s, hp, meas_amp)) return rc;
   FPM_REQUIRE(B >= 1, "fpm_step needs a non-empty batch");
   if (int rc = check_batch(p, leds, B)) return rc;
-  return step_launches(p, s, hp, leds, B, gamma, meas_amp, (hipStream_t)stream);
+  hipStream_t st = (hipStream_t)stream;
+  if (int rc = step_launches(p, s, hp, leds, B, gamma, meas_amp, 0, st)) return rc;
+  if (hp->learn_zernike || hp->learn_z) return commit_launch(p, s, st);
+  return FPM_OK;
 }
 
 int fpm_run(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_t* leds,
@@ -670,13 +737,16 @@ int fpm_run(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_t* led
     FPM_REQUIRE(batch_sizes[i] >= 1 && batch_sizes[i] <= p->max_batch,
                 "every batch size must be in [1, max_batch]");
   }
+  hipStream_t st = (hipStream_t)stream;
+  const bool learn_p = hp->learn_zernike || hp->learn_z;
   size_t off = 0;
   for (int i = 0; i < n_steps; ++i) {
     if (int rc = step_launches(p, s, hp, leds + off, batch_sizes[i], gamma, meas_amp,
-                               (hipStream_t)stream))
+                               learn_p && i > 0, st))
       return rc;
     off += batch_sizes[i];
   }
+  if (learn_p && n_steps > 0) return commit_launch(p, s, st);
   return FPM_OK;
 }
 

@@ -70,8 +70,7 @@ pupil_grad(PupilGeom g, const int2* __restrict__ rowext, const float2* __restric
   });
 }
 
-// Adam over 32 x 32 tiles of the HR spectrum (each thread: 8 consecutive floats);
-// the gradient is read and cleared.
+// Adam (torch.optim.Adam arithmetic) on one float of the spectrum.
 struct AdamCoef {
   float b1, b2, eps, step_size, sqrt_bc2;
 };
@@ -83,28 +82,121 @@ __device__ __forceinline__ void adam1(float& p, float& m, float& v, float g, con
   p -= c.step_size * (m / den);
 }
 
-__global__ void __launch_bounds__(256)
-adam_object(const int2* __restrict__ tiles, int M, float* __restrict__ O, float* __restrict__ mO,
-            float* __restrict__ vO, float* __restrict__ gO, AdamCoef c) {
-  const int2 tl = tiles[blockIdx.x];
-  const int r = tl.x * 32 + (threadIdx.x >> 3);
-  const int col = tl.y * 32 + (threadIdx.x & 7) * 4;         // complex column
-  const size_t f = ((size_t)r * M + col) * 2;                  // float offset
+// Adam on the pupil parameters (Zernike 1..14, defocus), FP64 arithmetic.
+struct ScalarAdam {
+  int learn_c, learn_z;
+  double lr_c, lr_z, b1, b2, eps, bc1, sqrt_bc2;
+};
+
+// The last launch of a step:
+//  workgroups [0, n_tiles): Adam over 32 x 32 tiles of the spectrum (each
+//    thread 8 consecutive floats); the gradient is read and cleared;
+//  the remaining workgroups: with `pupil`, each one sums the per-workgroup
+//    Zernike/defocus partials of the row pass in a fixed order, applies Adam
+//    to the 16 pupil parameters (all of them compute the same numbers), and
+//    rebuilds its share of the pupil from the new parameters; workgroup 0 of
+//    them stages the new parameter state, adds the gradients to g_par, and
+//    adds the batch loss (summed from the column pass's partials) to *loss.
+struct UpdateArgs {
+  const int2* tiles; int n_tiles; int M;
+  float* O; float* mO; float* vO; float* gO;
+  AdamCoef c;
+  const double* loss_part; int n_loss; double* loss;
+  int pupil;
+  const double* zpart; int n_zpart;
+  ScalarState cur; ScalarAdam sa; double* g_par; float* staging;
+  PupilGeom pg; const int2* rowext; float2* P;
+};
+
+constexpr int kPupilPerWg = 1024;   // pupil points rebuilt per workgroup
+
+__global__ void __launch_bounds__(256) update(UpdateArgs a) {
+  if ((int)blockIdx.x < a.n_tiles) {
+    const int2 tl = a.tiles[blockIdx.x];
+    const int r = tl.x * 32 + (threadIdx.x >> 3);
+    const int col = tl.y * 32 + (threadIdx.x & 7) * 4;         // complex column
+    const size_t f = ((size_t)r * a.M + col) * 2;                // float offset
 #pragma unroll
-  for (int h = 0; h < 2; ++h) {
-    float4* po = reinterpret_cast<float4*>(O + f) + h;
-    float4* pm = reinterpret_cast<float4*>(mO + f) + h;
-    float4* pv = reinterpret_cast<float4*>(vO + f) + h;
-    float4* pg = reinterpret_cast<float4*>(gO + f) + h;
-    float4 o = *po, m = *pm, v = *pv, g = *pg;
-    adam1(o.x, m.x, v.x, g.x, c);
-    adam1(o.y, m.y, v.y, g.y, c);
-    adam1(o.z, m.z, v.z, g.z, c);
-    adam1(o.w, m.w, v.w, g.w, c);
-    *po = o;
-    *pm = m;
-    *pv = v;
-    *pg = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int h = 0; h < 2; ++h) {
+      float4* po = reinterpret_cast<float4*>(a.O + f) + h;
+      float4* pm = reinterpret_cast<float4*>(a.mO + f) + h;
+      float4* pv = reinterpret_cast<float4*>(a.vO + f) + h;
+      float4* pg = reinterpret_cast<float4*>(a.gO + f) + h;
+      float4 o = *po, m = *pm, v = *pv, g = *pg;
+      adam1(o.x, m.x, v.x, g.x, a.c);
+      adam1(o.y, m.y, v.y, g.y, a.c);
+      adam1(o.z, m.z, v.z, g.z, a.c);
+      adam1(o.w, m.w, v.w, g.w, a.c);
+      *po = o;
+      *pm = m;
+      *pv = v;
+      *pg = make_float4(0.f, 0.f, 0.f, 0.f);
+    }
+    return;
+  }
+  const int pw = blockIdx.x - a.n_tiles;
+  __shared__ double red[256];
+  __shared__ double gsum[kPar];
+  __shared__ float next[kScal];
+  if (a.pupil) {
+    const int j = threadIdx.x & (kPar - 1);
+    double sj = 0.0;
+    for (int i = threadIdx.x / kPar; i < a.n_zpart; i += 256 / kPar) sj += a.zpart[(size_t)i * kPar + j];
+    red[threadIdx.x] = sj;
+    __syncthreads();
+    if (threadIdx.x < kPar) {
+      double g = 0.0;
+      for (int k = 0; k < 256 / kPar; ++k) g += red[k * kPar + threadIdx.x];
+      gsum[threadIdx.x] = g;
+      // current value, moments; unchanged unless learned
+      const bool is_z = threadIdx.x == kZern;
+      const float* pc = is_z ? a.cur.z : a.cur.coeffs + threadIdx.x;
+      const float* pm = is_z ? a.cur.m_z : a.cur.m_c + threadIdx.x;
+      const float* pv = is_z ? a.cur.v_z : a.cur.v_c + threadIdx.x;
+      float p = pc ? *pc : 0.f, m = pm ? *pm : 0.f, v = pv ? *pv : 0.f;
+      // piston (j = 0): a global phase with an identically zero gradient, held fixed
+      const bool learn = is_z ? a.sa.learn_z : (a.sa.learn_c && threadIdx.x != 0);
+      if (learn) {
+        const double lr = is_z ? a.sa.lr_z : a.sa.lr_c;
+        const double mm = a.sa.b1 * (double)m + (1.0 - a.sa.b1) * g;
+        const double vv = a.sa.b2 * (double)v + (1.0 - a.sa.b2) * g * g;
+        const double den = sqrt(vv) / a.sa.sqrt_bc2 + a.sa.eps;
+        p = (float)((double)p - lr / a.sa.bc1 * mm / den);
+        m = (float)mm;
+        v = (float)vv;
+      }
+      next[threadIdx.x] = p;
+      next[kPar + threadIdx.x] = m;
+      next[2 * kPar + threadIdx.x] = v;
+    }
+    __syncthreads();
+    if (pw == 0 && threadIdx.x < kScal) a.staging[threadIdx.x] = next[threadIdx.x];
+    if (pw == 0 && threadIdx.x < kPar && a.g_par) a.g_par[threadIdx.x] += gsum[threadIdx.x];
+    // rebuild this workgroup's share of the pupil from the new parameters (FP64)
+    const int n = a.pg.n;
+    const int end = min((pw + 1) * kPupilPerWg, n * n);
+    for (int idx = pw * kPupilPerWg + threadIdx.x; idx < end; idx += 256) {
+      const int ky = idx / n, kx = idx - ky * n;
+      const int2 e = a.rowext[ky];
+      if (kx < e.x || kx > e.y) continue;   // off the disk P stays zero
+      const double ux = kx - n / 2, uy = ky - n / 2;
+      double z[kZern];
+      zernike15(ux * a.pg.inv_r, uy * a.pg.inv_r, z);
+      double th = 0.0;
+#pragma unroll
+      for (int q = 0; q < kZern; ++q) th += (double)next[q] * z[q];
+      if (a.cur.z) th += (double)next[kZern] * defocus_kappa((ux * ux + uy * uy) * a.pg.dk2, a.pg.inv_l);
+      double sn, cs;
+      sincos(th, &sn, &cs);
+      a.P[idx] = make_float2((float)cs, (float)sn);
+    }
+  }
+  if (pw == 0 && a.loss && threadIdx.x < 64) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < a.n_loss; i += 64) s += a.loss_part[i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (threadIdx.x == 0) *a.loss += s;
   }
 }
 

@@ -18,9 +18,9 @@
 //                  Zernike/defocus parameters
 //
 // Scalar results (loss, parameter gradients) are reduced without contended
-// atomics: each workgroup writes a partial, and the last workgroup to finish
-// (found with one counter atomic) sums the partials in a fixed order, so the
-// sums are deterministic.
+// atomics or device-scope fences (a fence writes back the XCD's L2): each
+// workgroup stores a partial sum, and a later kernel of the same stream adds
+// the partials in a fixed order, so the sums are deterministic.
 //
 // Workgroups of one LED are placed on one XCD (workgroup id mod 8 selects
 // the XCD) so that the scratch written by one pass is read from the same
@@ -87,6 +87,28 @@ struct Reduction {
   unsigned* counter;
 };
 
+// Sum K per-thread values over the workgroup; thread k < K stores total k into
+// part[blockIdx.x * K + k]. No ordering with other workgroups is implied.
+template <int K, class V>
+__device__ __forceinline__ void block_partials(const V* vals, double* part) {
+  __shared__ double wsum[16][K];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwaves = (blockDim.x + 63) >> 6;
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double v = vals[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (lane == 0) wsum[wave][k] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double s = 0.0;
+    for (int w = 0; w < nwaves; ++w) s += wsum[w][threadIdx.x];
+    part[(size_t)blockIdx.x * K + threadIdx.x] = s;
+  }
+}
+
 // Sum K per-thread values over the workgroup into part[blockIdx.x * K + k], then
 // let the last workgroup to arrive call done(sums) with the grid-wide totals
 // (summed in workgroup order). Every workgroup of the grid must call this.
@@ -137,48 +159,67 @@ __device__ __forceinline__ void grid_reduce(const V* vals, Reduction red, Done d
 }
 
 // ---------------------------------------------------------------------------
-// Row pass 1: crop, pupil, inverse DFT along k_x.
-// kLivePupil: P is rebuilt from its parameters (and written by slot 0).
-template <int N, bool kLivePupil>
+// Pupil-parameter state in one block: [0,15) coeffs, 15 z, [16,31) m_c, 31 m_z,
+// [32,47) v_c, 47 v_z. The update kernel writes the next state to a staging
+// block, which the following step's first kernel (or a commit launch) copies
+// into the caller's buffers; so no kernel reads state that it also writes.
+constexpr int kScal = 3 * kPar;
+
+struct ScalarState {
+  float* coeffs; float* m_c; float* v_c;
+  float* z; float* m_z; float* v_z;
+};
+
+__device__ __forceinline__ void commit_scalars(const float* __restrict__ staging, ScalarState d,
+                                               int i) {
+  if (i >= kScal) return;
+  const int part = i / kPar, j = i - part * kPar;
+  float* dst;
+  if (j < kZern) {
+    dst = part == 0 ? d.coeffs : part == 1 ? d.m_c : d.v_c;
+    if (dst) dst[j] = staging[i];
+  } else {
+    dst = part == 0 ? d.z : part == 1 ? d.m_z : d.v_z;
+    if (dst) dst[0] = staging[i];
+  }
+}
+
+__global__ void commit_scalar_state(const float* __restrict__ staging, ScalarState d) {
+  commit_scalars(staging, d, threadIdx.x);
+}
+
+// Row pass 1: crop, pupil, inverse DFT along k_x. With `commit`, workgroup 0
+// also copies the staged pupil-parameter state of the previous step.
+template <int N>
 __global__ void __launch_bounds__(kRowThreads)
-rows_forward(const float2* __restrict__ O, const float2* __restrict__ P_in, Batch bt, Disk dk,
-             PupilGeom pg, PupilParams pp, float2* __restrict__ P_out, int chunks,
-             float2* __restrict__ X, const float2* __restrict__ tw) {
+rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch bt, Disk dk,
+             int chunks, float2* __restrict__ X, const float2* __restrict__ tw, int commit,
+             const float* __restrict__ staging, ScalarState scal) {
   constexpr int T = Plan1D<N>::T;
   constexpr int E = N / T;
   constexpr int L = kRowThreads / T;
   __shared__ float2 lds[L * (N + 1)];
+  if (commit && blockIdx.x == 0) commit_scalars(staging, scal, threadIdx.x);
   int b, c;
   if (!xcd_map(blockIdx.x, chunks, bt.B, b, c)) return;
+  const int led = bt.leds[b];
+  if ((unsigned)led >= (unsigned)bt.n_led) return;   // invalid id: the image contributes nothing
   const int line = threadIdx.x / T;
   const int t = threadIdx.x % T;
   const int rr = c * L + line;
   const bool active = rr < dk.nrows;
   const int ky = dk.ky_lo + (active ? rr : 0);
   const int2 ext = dk.rowext[ky];
-  float2 p[E];
-#pragma unroll
-  for (int m = 0; m < E; ++m) {
-    const int kx = half_shift<N>(t + m * T);
-    const bool in = active && kx >= ext.x && kx <= ext.y;
-    if constexpr (kLivePupil) {
-      p[m] = in ? pupil_value(pg, pp, kx, ky) : make_float2(0.f, 0.f);
-      if (in && b == 0) P_out[(size_t)ky * N + kx] = p[m];
-    } else {
-      p[m] = in ? P_in[(size_t)ky * N + kx] : make_float2(0.f, 0.f);
-    }
-  }
-  const int led = bt.leds[b];
-  if ((unsigned)led >= (unsigned)bt.n_led) return;   // invalid id: the image contributes nothing
   const int2 s = bt.shifts[led];
   const int base = bt.M / 2 - N / 2;
   const float2* orow = O + (size_t)(base + s.x + ky) * bt.M + (base + s.y);
+  const float2* prow = P + (size_t)ky * N;
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int kx = half_shift<N>(t + m * T);
     const bool in = active && kx >= ext.x && kx <= ext.y;
-    v[m] = in ? cmul(orow[kx], p[m]) : make_float2(0.f, 0.f);
+    v[m] = in ? cmul(orow[kx], prow[kx]) : make_float2(0.f, 0.f);
   }
   Plan1D<N>::template run<+1>(v, t, lds + line * (N + 1), [](int n) { return n; }, tw);
   if (active) {
@@ -193,7 +234,7 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P_in, Batc
 template <int N, bool kForward>
 __global__ void __launch_bounds__(ColLines<N>::value * Plan1D<N>::T)
 cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restrict__ gamma,
-     Batch bt, Disk dk, int groups, Reduction red, double* __restrict__ loss,
+     Batch bt, Disk dk, int groups, double* __restrict__ loss_part,
      float* __restrict__ amp_out, float2* __restrict__ field_out, const float2* __restrict__ tw,
      float inv_m) {
   constexpr int T = Plan1D<N>::T;
@@ -249,52 +290,21 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
     }
   }
   if constexpr (!kForward) {
-    if (loss) {
-      grid_reduce<1>(&acc, red, [&](const double* tot, int lane) {
-        if (lane == 0) *loss += tot[0];
-      });
-    }
+    if (loss_part) block_partials<1>(&acc, loss_part);
   }
-}
-
-// Adam on the pupil parameters (Zernike 1..14, defocus); FP64 arithmetic.
-struct ScalarAdam {
-  float* coeffs; float* m_c; float* v_c; int learn_c;
-  float* z; float* m_z; float* v_z; int learn_z;
-  double lr_c, lr_z, b1, b2, eps, bc1, sqrt_bc2;
-};
-
-__device__ __forceinline__ void scalar_adam(const ScalarAdam& a, int j, double g) {
-  float *p, *m, *v;
-  double lr;
-  if (j < kZern) {
-    // piston (j = 0): a global phase with an identically zero gradient, held fixed
-    if (!a.learn_c || j == 0) return;
-    p = a.coeffs + j; m = a.m_c + j; v = a.v_c + j; lr = a.lr_c;
-  } else {
-    if (!a.learn_z) return;
-    p = a.z; m = a.m_z; v = a.v_z; lr = a.lr_z;
-  }
-  const double mm = a.b1 * (double)*m + (1.0 - a.b1) * g;
-  const double vv = a.b2 * (double)*v + (1.0 - a.b2) * g * g;
-  const double den = sqrt(vv) / a.sqrt_bc2 + a.eps;
-  *p = (float)((double)*p - lr / a.bc1 * mm / den);
-  *m = (float)mm;
-  *v = (float)vv;
 }
 
 enum RowsBackwardMode { kGradO = 0, kGradOP = 1, kGradOZern = 2 };
 
 // Row pass 2: forward DFT along x, conj-pupil, scatter-add into g_O; the pupil
 // gradient is scatter-added into g_P (kGradOP) or projected onto the Zernike
-// and defocus parameters (kGradOZern; the last workgroup then adds the
-// totals to g_par and, when `adam.learn_c | adam.learn_z`, updates them).
+// and defocus parameters (kGradOZern: per-workgroup partials in zpart).
 template <int N, int MODE>
 __global__ void __launch_bounds__(kRowThreads)
 rows_backward(const float2* __restrict__ X, const float2* __restrict__ O,
               const float2* __restrict__ P, Batch bt, Disk dk, PupilGeom pg, int chunks,
-              float2* __restrict__ gO, float2* __restrict__ gP, Reduction red,
-              double* __restrict__ g_par, ScalarAdam adam, const float2* __restrict__ tw) {
+              float2* __restrict__ gO, float2* __restrict__ gP, double* __restrict__ zpart,
+              const float2* __restrict__ tw) {
   constexpr int T = Plan1D<N>::T;
   constexpr int E = N / T;
   constexpr int L = kRowThreads / T;
@@ -349,18 +359,7 @@ rows_backward(const float2* __restrict__ X, const float2* __restrict__ O,
       }
     }
   }
-  if constexpr (MODE == kGradOZern) {
-    grid_reduce<kPar>(zacc, red, [&](const double* tot, int lane) {
-      if (lane < kPar) {
-        double gj = 0.0;
-#pragma unroll
-        for (int j = 0; j < kPar; ++j)
-          if (j == lane) gj = tot[j];
-        if (g_par) g_par[lane] += gj;
-        scalar_adam(adam, lane, gj);
-      }
-    });
-  }
+  if constexpr (MODE == kGradOZern) block_partials<kPar>(zacc, zpart);
 }
 
 }  // namespace fpm

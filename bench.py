@@ -119,6 +119,9 @@ def main():
     ap.add_argument("--workload", default="paper", choices=["small", "paper", "large"])
     ap.add_argument("--profile-steps", type=int, default=60,
                     help="steps timed per kernel with events (after the main timing)")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="after timing, one device-to-device copy of this size (a kernel of "
+                         "known traffic for calibrating HBM counters)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -171,6 +174,19 @@ def main():
     n_img = sum(len(b) for b in batches[args.warmup:args.warmup + args.steps])
     value = n_img / (ms / 1e3)
     log(f"{args.steps} timed steps: {ms:.2f} ms, {value:.4g} LED-images/s")
+
+    if args.copy_probe_mb > 0:
+        n = args.copy_probe_mb * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy probe: {2 * n * 4 / 1e6:.1f} MB moved (read + write)")
+        del src, dst
+    if args.profile_steps <= 0:
+        print(json.dumps({"metric": "profiling run", "value": value, "unit": "LED-images/s"}))
+        return
 
     # per-kernel durations with events around every launch (separate pass)
     plan.timing(True)

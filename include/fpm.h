@@ -177,8 +177,9 @@ typedef struct {
 
 /*
  * Device-resident optimiser state of one reconstruction (all caller-owned):
- * O, m_O, v_O, g_O: complex [M][M] (m, v per real component; g_O must be zero
- * before the first step and is left zero by every step);
+ * O, m_O, v_O: complex [M][M] (m, v per real component); g_O is not used by
+ * fpm_step / fpm_run (the object gradient is gathered from per-LED patches in
+ * the plan's scratch, in batch order) and may be NULL;
  * P: complex [N][N] pupil (input if the pupil is fixed, rebuilt otherwise);
  * coeffs/m_c/v_c: float [15]; z_um/m_z/v_z: float [1] (may be NULL when not
  * learned); g_par: double [16] or NULL: when the pupil is learned, += the
@@ -202,8 +203,10 @@ typedef struct {
  * pupil-parameter projection, Adam on the learned pupil parameters, then
  * Adam on the object (over the union of LED windows; elsewhere the gradient
  * is identically zero and Adam leaves O unchanged). The loss and the
- * pupil-parameter gradients are reduced in a fixed order (deterministic);
- * the object gradient is accumulated with atomics.
+ * pupil-parameter gradients and the object gradient are all summed in a
+ * fixed order: a step is deterministic.
+ * The pupil state->P must hold P(coeffs, z) on entry (fpm_pupil builds it);
+ * each step leaves it rebuilt from the updated parameters.
  */
 int fpm_step(fpm_plan* plan, fpm_state* state, const fpm_hparams* hp, const int32_t* leds,
              int32_t B, const float* gamma, const float* meas_amp, void* stream);

@@ -86,6 +86,7 @@ struct fpm_plan {
   float2* twM = nullptr;      // [M] when the HR transforms are available
   float2* X = nullptr;        // [max_batch][N][N] row/column scratch
   float2* gP = nullptr;       // [N][N] pupil-gradient accumulator for fpm_step
+  float* kappa_tab = nullptr;  // defocus phase per um at integer |u|^2 <= R^2
   int2* tiles = nullptr;      // [n_tiles] 32 x 32 HR tiles covered by some window
   double* part = nullptr;     // per-workgroup partial sums (loss | Zernike | pupil_grad)
   double* part_loss = nullptr;
@@ -147,6 +148,7 @@ void plan_free(fpm_plan* p) {
   (void)hipFree(p->twM);
   (void)hipFree(p->X);
   (void)hipFree(p->gP);
+  (void)hipFree(p->kappa_tab);
   (void)hipFree(p->tiles);
   (void)hipFree(p->part);
   (void)hipFree(p->staging);
@@ -248,15 +250,20 @@ int launch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t
     switch (o.mode) {
       case kGradO:
         rows_backward<N, kGradO><<<gr.rows(), kRowThreads, 0, st>>>(
-            p->X, O, P, bt, dk, pg, gr.row_chunks, gO, nullptr, nullptr, p->twN);
+            p->X, O, P, bt, dk, pg, gr.row_chunks, gO, nullptr, nullptr, nullptr, p->twN);
         break;
       case kGradOP:
         rows_backward<N, kGradOP><<<gr.rows(), kRowThreads, 0, st>>>(
-            p->X, O, P, bt, dk, pg, gr.row_chunks, gO, o.gP, nullptr, p->twN);
+            p->X, O, P, bt, dk, pg, gr.row_chunks, gO, o.gP, nullptr, nullptr, p->twN);
+        break;
+      case kPatch:
+        rows_backward<N, kPatch><<<gr.rows(), kRowThreads, 0, st>>>(
+            p->X, O, P, bt, dk, pg, gr.row_chunks, nullptr, nullptr, nullptr, nullptr, p->twN);
         break;
       default:
-        rows_backward<N, kGradOZern><<<gr.rows(), kRowThreads, 0, st>>>(
-            p->X, O, P, bt, dk, pg, gr.row_chunks, gO, nullptr, p->part_z, p->twN);
+        rows_backward<N, kPatchZern><<<gr.rows(), kRowThreads, 0, st>>>(
+            p->X, O, P, bt, dk, pg, gr.row_chunks, nullptr, nullptr, p->part_z, p->kappa_tab,
+            p->twN);
         break;
     }
   }
@@ -455,6 +462,12 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
   p->n_tiles = (int)tiles.size();
   p->hr_ok = hr_supported(p->M);
 
+  // kappa(|u|^2) = 2 pi (sqrt(1/l^2 - k^2) - 1/l), k^2 = |u|^2 dk^2, cancellation-free form
+  std::vector<float> kap((size_t)std::floor(r2) + 1);
+  for (size_t q = 0; q < kap.size(); ++q) {
+    const double k2 = (double)q * p->dk * p->dk, il = 1.0 / p->lambda;
+    kap[q] = (float)(-2.0 * M_PI * k2 / (std::sqrt(il * il - k2) + il));
+  }
   int rc = FPM_OK;
   const auto twn = twiddles(p->N);
   if ((rc = upload(&p->rowext, ext.data(), ext.size())) ||
@@ -462,6 +475,7 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
       (rc = upload(&p->twN, twn.data(), twn.size())) ||
       (rc = upload<float2>(&p->X, nullptr, (size_t)p->max_batch * p->N * p->N)) ||
       (rc = upload<float2>(&p->gP, nullptr, (size_t)p->N * p->N)) ||
+      (rc = upload(&p->kappa_tab, kap.data(), kap.size())) ||
       (rc = upload(&p->tiles, tiles.data(), std::max<size_t>(tiles.size(), 1)))) {
     plan_free(p);
     return rc;
@@ -596,6 +610,7 @@ int fpm_backward(fpm_plan* p, const fpm_c32* O, const fpm_c32* P, const int32_t*
     return rc;
   if (loss) {   // add the column pass's partials (fixed order)
     UpdateArgs a{};
+    a.n = p->N;
     a.loss_part = p->part_loss;
     a.n_loss = cols_grid_of(p, B);
     a.loss = loss;
@@ -626,8 +641,8 @@ namespace {
 
 int check_state(fpm_plan* p, const fpm_state* s, const fpm_hparams* hp, const float* meas_amp) {
   FPM_REQUIRE(p && s && hp, "plan, state and hparams must not be NULL");
-  FPM_REQUIRE(s->O && s->m_O && s->v_O && s->g_O && s->P && meas_amp,
-              "state O, m_O, v_O, g_O, P and meas_amp must not be NULL");
+  FPM_REQUIRE(s->O && s->m_O && s->v_O && s->P && meas_amp,
+              "state O, m_O, v_O, P and meas_amp must not be NULL");
   if (hp->learn_zernike) FPM_REQUIRE(s->coeffs && s->m_c && s->v_c, "Zernike state must not be NULL");
   if (hp->learn_z) FPM_REQUIRE(s->z_um && s->m_z && s->v_z, "defocus state must not be NULL");
   FPM_REQUIRE(s->t >= 0, "t must be >= 0");
@@ -654,21 +669,24 @@ int step_launches(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_
   const double bc1 = 1.0 - std::pow(b1, t), bc2 = 1.0 - std::pow(b2, t);
   float2* P = reinterpret_cast<float2*>(s->P);
   BackwardOut o;
-  o.mode = learn_p ? kGradOZern : kGradO;
+  o.mode = learn_p ? kPatchZern : kPatch;
   o.loss = s->loss != nullptr;
   o.commit = commit;
   o.scal = scalar_state_of(s);
   if (int rc = dispatch_backward(p, reinterpret_cast<const float2*>(s->O), P, leds, B, gamma,
-                                 meas_amp, reinterpret_cast<float2*>(s->g_O), o, st))
+                                 meas_amp, nullptr, o, st))
     return rc;
   UpdateArgs a{};
+  a.X = p->X;
+  a.bt = batch_of(p, leds, B);
+  a.dk = disk_of(p);
+  a.n = p->N;
   a.tiles = p->tiles;
   a.n_tiles = p->n_tiles;
   a.M = p->M;
   a.O = reinterpret_cast<float*>(s->O);
   a.mO = reinterpret_cast<float*>(s->m_O);
   a.vO = reinterpret_cast<float*>(s->v_O);
-  a.gO = reinterpret_cast<float*>(s->g_O);
   a.c.b1 = hp->beta1;
   a.c.b2 = hp->beta2;
   a.c.eps = hp->eps;
@@ -695,7 +713,7 @@ int step_launches(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_
   a.pg = pupil_geom(p);
   a.rowext = p->rowext;
   a.P = P;
-  const int extra = learn_p ? pupil_wgs(p) : 1;
+  const int extra = learn_p ? pupil_wgs(p) : 1;   // must match the kernel's n_pw
   {
     Timed tm(p, kAdamObject, st);
     update<<<p->n_tiles + extra, 256, 0, st>>>(a);

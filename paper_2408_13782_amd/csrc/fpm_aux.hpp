@@ -89,9 +89,10 @@ struct ScalarAdam {
 };
 
 // The last launch of a step:
-//  workgroups [0, n_tiles): Adam over 32 x 32 tiles of the spectrum (each
-//    thread 8 consecutive floats); the gradient is read and cleared;
-//  the remaining workgroups: with `pupil`, each one sums the per-workgroup
+//  the last n_tiles workgroups: Adam over 32 x 32 tiles of the spectrum (each
+//    thread 4 consecutive complex values), the gradient gathered from the
+//    batch's patches in batch order (deterministic, no atomics);
+//  the first workgroups: with `pupil`, each one sums the per-workgroup
 //    Zernike/defocus partials of the row pass in a fixed order, applies Adam
 //    to the 16 pupil parameters (all of them compute the same numbers), and
 //    rebuilds its share of the pupil from the new parameters; workgroup 0 of
@@ -99,8 +100,10 @@ struct ScalarAdam {
 //    adds the batch loss (summed from the column pass's partials) to *loss.
 struct UpdateArgs {
   const int2* tiles; int n_tiles; int M;
-  float* O; float* mO; float* vO; float* gO;
+  float* O; float* mO; float* vO;
   AdamCoef c;
+  // the batch's conj(P) g_Phi patches, stored in X by the row pass
+  const float2* X; Batch bt; Disk dk; int n;
   const double* loss_part; int n_loss; double* loss;
   int pupil;
   const double* zpart; int n_zpart;
@@ -110,44 +113,100 @@ struct UpdateArgs {
 
 constexpr int kPupilPerWg = 1024;   // pupil points rebuilt per workgroup
 
+// Gradient of the spectrum at 4 consecutive pixels (row r, columns c0..c0+3):
+// the sum, in batch order, of the patches of the LEDs whose disk covers them.
+__device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int c0, int tile_r0,
+                                                int tile_c0, float2 (&g)[4]) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) g[q] = make_float2(0.f, 0.f);
+  const int base = a.M / 2 - a.n / 2;
+  for (int b = 0; b < a.bt.B; ++b) {
+    const int led = a.bt.leds[b];
+    if ((unsigned)led >= (unsigned)a.bt.n_led) continue;
+    const int2 s = a.bt.shifts[led];
+    const int wr = base + s.x, wc = base + s.y;
+    // whole-tile test against the disk's bounding box (uniform over the workgroup)
+    if (tile_r0 + 31 < wr + a.dk.ky_lo || tile_r0 > wr + a.dk.ky_hi ||
+        tile_c0 + 31 < wc + a.dk.ky_lo || tile_c0 > wc + a.dk.ky_hi)
+      continue;
+    const int ky = r - wr;
+    if (ky < a.dk.ky_lo || ky > a.dk.ky_hi) continue;
+    const int2 e = a.dk.rowext[ky];
+    const float2* xr = a.X + ((size_t)b * a.n + ky) * a.n - wc;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int kx = c0 + q - wc;
+      if (kx >= e.x && kx <= e.y) {
+        const float2 v = xr[c0 + q];
+        g[q].x += v.x;
+        g[q].y += v.y;
+      }
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) update(UpdateArgs a) {
-  if ((int)blockIdx.x < a.n_tiles) {
-    const int2 tl = a.tiles[blockIdx.x];
+  const int n_pw = a.pupil ? (a.n * a.n + kPupilPerWg - 1) / kPupilPerWg : 1;
+  if ((int)blockIdx.x >= n_pw) {
+    const int2 tl = a.tiles[blockIdx.x - n_pw];
     const int r = tl.x * 32 + (threadIdx.x >> 3);
     const int col = tl.y * 32 + (threadIdx.x & 7) * 4;         // complex column
     const size_t f = ((size_t)r * a.M + col) * 2;                // float offset
+    float2 g[4];
+    gather_gradient(a, r, col, tl.x * 32, tl.y * 32, g);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       float4* po = reinterpret_cast<float4*>(a.O + f) + h;
       float4* pm = reinterpret_cast<float4*>(a.mO + f) + h;
       float4* pv = reinterpret_cast<float4*>(a.vO + f) + h;
-      float4* pg = reinterpret_cast<float4*>(a.gO + f) + h;
-      float4 o = *po, m = *pm, v = *pv, g = *pg;
-      adam1(o.x, m.x, v.x, g.x, a.c);
-      adam1(o.y, m.y, v.y, g.y, a.c);
-      adam1(o.z, m.z, v.z, g.z, a.c);
-      adam1(o.w, m.w, v.w, g.w, a.c);
+      float4 o = *po, m = *pm, v = *pv;
+      adam1(o.x, m.x, v.x, g[2 * h].x, a.c);
+      adam1(o.y, m.y, v.y, g[2 * h].y, a.c);
+      adam1(o.z, m.z, v.z, g[2 * h + 1].x, a.c);
+      adam1(o.w, m.w, v.w, g[2 * h + 1].y, a.c);
       *po = o;
       *pm = m;
       *pv = v;
-      *pg = make_float4(0.f, 0.f, 0.f, 0.f);
     }
     return;
   }
-  const int pw = blockIdx.x - a.n_tiles;
+  const int pw = blockIdx.x;
   __shared__ double red[256];
   __shared__ double gsum[kPar];
   __shared__ float next[kScal];
   if (a.pupil) {
+    // moments of the row pass: thread t sums entry t % 16 of partials t/16, t/16 + 16, ...
+    // (independent loads in flight, then a fixed summation order)
     const int j = threadIdx.x & (kPar - 1);
     double sj = 0.0;
-    for (int i = threadIdx.x / kPar; i < a.n_zpart; i += 256 / kPar) sj += a.zpart[(size_t)i * kPar + j];
+    constexpr int kStride = 256 / kPar, kUnroll = 8;
+    for (int i0 = threadIdx.x / kPar; i0 < a.n_zpart; i0 += kStride * kUnroll) {
+      double vals[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int i = i0 + u * kStride;
+        vals[u] = i < a.n_zpart ? a.zpart[(size_t)i * kPar + j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) sj += vals[u];
+    }
     red[threadIdx.x] = sj;
     __syncthreads();
     if (threadIdx.x < kPar) {
-      double g = 0.0;
-      for (int k = 0; k < 256 / kPar; ++k) g += red[k * kPar + threadIdx.x];
-      gsum[threadIdx.x] = g;
+      double mom = 0.0;
+      for (int k = 0; k < kStride; ++k) mom += red[k * kPar + threadIdx.x];
+      gsum[threadIdx.x] = mom;
+    }
+    __syncthreads();
+    if (threadIdx.x < kPar) {
+      // Zernike gradients from the monomial moments; defocus gradient directly
+      double g = gsum[kZern];
+      if (threadIdx.x < kZern) {
+        g = 0.0;
+#pragma unroll
+        for (int k = 0; k < kMono; ++k) g += kZernMono[threadIdx.x][k] * gsum[k];
+      }
+      red[threadIdx.x] = g;
       // current value, moments; unchanged unless learned
       const bool is_z = threadIdx.x == kZern;
       const float* pc = is_z ? a.cur.z : a.cur.coeffs + threadIdx.x;
@@ -171,7 +230,7 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     }
     __syncthreads();
     if (pw == 0 && threadIdx.x < kScal) a.staging[threadIdx.x] = next[threadIdx.x];
-    if (pw == 0 && threadIdx.x < kPar && a.g_par) a.g_par[threadIdx.x] += gsum[threadIdx.x];
+    if (pw == 0 && threadIdx.x < kPar && a.g_par) a.g_par[threadIdx.x] += red[threadIdx.x];
     // rebuild this workgroup's share of the pupil from the new parameters (FP64)
     const int n = a.pg.n;
     const int end = min((pw + 1) * kPupilPerWg, n * n);

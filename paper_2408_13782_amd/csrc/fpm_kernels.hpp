@@ -294,17 +294,22 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
   }
 }
 
-enum RowsBackwardMode { kGradO = 0, kGradOP = 1, kGradOZern = 2 };
+// kGradO: g_O scatter-added with atomics; kGradOP: and g_P; kPatch: conj(P) g_Phi
+// is stored in place in X (disk positions of each row) for the update kernel to
+// gather; kPatchZern: kPatch plus the pupil-parameter moments.
+enum RowsBackwardMode { kGradO = 0, kGradOP = 1, kPatch = 2, kPatchZern = 3 };
 
 // Row pass 2: forward DFT along x, conj-pupil, scatter-add into g_O; the pupil
-// gradient is scatter-added into g_P (kGradOP) or projected onto the Zernike
-// and defocus parameters (kGradOZern: per-workgroup partials in zpart).
+// gradient is scatter-added into g_P (kGradOP) or reduced to the moments
+// sum_u g_theta x^a y^b (a + b <= 4) and sum_u g_theta kappa (kGradOZern:
+// per-workgroup partials in zpart; kappa_tab[|u|^2] = kappa), from which the
+// Zernike gradients follow by the fixed map kZernMono.
 template <int N, int MODE>
 __global__ void __launch_bounds__(kRowThreads)
-rows_backward(const float2* __restrict__ X, const float2* __restrict__ O,
+rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
               const float2* __restrict__ P, Batch bt, Disk dk, PupilGeom pg, int chunks,
               float2* __restrict__ gO, float2* __restrict__ gP, double* __restrict__ zpart,
-              const float2* __restrict__ tw) {
+              const float* __restrict__ kappa_tab, const float2* __restrict__ tw) {
   constexpr int T = Plan1D<N>::T;
   constexpr int E = N / T;
   constexpr int L = kRowThreads / T;
@@ -322,7 +327,7 @@ rows_backward(const float2* __restrict__ X, const float2* __restrict__ O,
 #pragma unroll
   for (int j = 0; j < kPar; ++j) zacc[j] = 0.f;
   if (live) {
-    const float2* xr = X + ((size_t)b * N + ky) * N;
+    float2* xr = X + ((size_t)b * N + ky) * N;
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = active ? xr[t + m * T] : make_float2(0.f, 0.f);
@@ -333,33 +338,50 @@ rows_backward(const float2* __restrict__ X, const float2* __restrict__ O,
       const int2 ext = dk.rowext[ky];
       const size_t orow = (size_t)(base + s.x + ky) * bt.M + (base + s.y);
       const float2* prow = P + (size_t)ky * N;
-      const float uy = (float)(ky - N / 2);
+      const int uy = ky - N / 2;
+      const float ir = (float)pg.inv_r;
+      // row moments S_a = sum g_theta x^a (a <= 4) and sum g_theta kappa
+      float S0 = 0.f, S1 = 0.f, S2 = 0.f, S3 = 0.f, S4 = 0.f, SK = 0.f;
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int kx = half_shift<N>(t + m * T);
         if (kx >= ext.x && kx <= ext.y) {
           const float2 g = v[m];
           const float2 p = prow[kx];
-          atomic_add_c(gO + orow + kx, cmulc(p, g));
+          if constexpr (MODE == kGradO || MODE == kGradOP) {
+            atomic_add_c(gO + orow + kx, cmulc(p, g));
+          } else {
+            xr[kx] = cmulc(p, g);   // this row was read whole into registers above
+          }
           if constexpr (MODE == kGradOP) {
             atomic_add_c(gP + (size_t)ky * N + kx, cmulc(O[orow + kx], g));
-          } else if constexpr (MODE == kGradOZern) {
+          } else if constexpr (MODE == kPatchZern) {
             const float2 gp = cmulc(O[orow + kx], g);           // conj(C) g_Phi
             const float gth = gp.y * p.x - gp.x * p.y;          // Im(g_P conj(P))
-            const float ux = (float)(kx - N / 2);
-            const float ir = (float)pg.inv_r;
-            float z[kZern];
-            zernike15(ux * ir, uy * ir, z);
-#pragma unroll
-            for (int j = 0; j < kZern; ++j) zacc[j] += gth * z[j];
-            zacc[kZern] += gth * defocus_kappa((ux * ux + uy * uy) * (float)pg.dk2,
-                                               (float)pg.inv_l);
+            const int ux = kx - N / 2;
+            const float x = (float)ux * ir;
+            const float gx = gth * x, gx2 = gx * x, gx3 = gx2 * x;
+            S0 += gth;
+            S1 += gx;
+            S2 += gx2;
+            S3 += gx3;
+            S4 += gx3 * x;
+            SK += gth * kappa_tab[ux * ux + uy * uy];
           }
         }
       }
+      if constexpr (MODE == kPatchZern) {
+        // moments sum g x^a y^b of this row, in the monomial order of kZernMono
+        const float y = (float)uy * ir, y2 = y * y, y3 = y2 * y, y4 = y3 * y;
+        zacc[0] = S0;  zacc[1] = S1;  zacc[2] = S0 * y;
+        zacc[3] = S2;  zacc[4] = S1 * y;  zacc[5] = S0 * y2;
+        zacc[6] = S3;  zacc[7] = S2 * y;  zacc[8] = S1 * y2;  zacc[9] = S0 * y3;
+        zacc[10] = S4; zacc[11] = S3 * y; zacc[12] = S2 * y2; zacc[13] = S1 * y3; zacc[14] = S0 * y4;
+        zacc[15] = SK;
+      }
     }
   }
-  if constexpr (MODE == kGradOZern) block_partials<kPar>(zacc, zpart);
+  if constexpr (MODE == kPatchZern) block_partials<kPar>(zacc, zpart);
 }
 
 }  // namespace fpm

@@ -32,6 +32,30 @@ __device__ __forceinline__ void zernike15(R x, R y, R* z) {
   z[14] = s10 * (x2 * x2 - R(6) * x2 * y2 + y2 * y2);
 }
 
+// The same terms as linear combinations of the 15 monomials x^a y^b, a + b <= 4,
+// in the order (0,0) (1,0) (0,1) (2,0) (1,1) (0,2) (3,0) (2,1) (1,2) (0,3)
+// (4,0) (3,1) (2,2) (1,3) (0,4): Z_j = sum_k kZernMono[j][k] m_k. A sum of
+// g(u) Z_j(u) over the pupil is then kZernMono applied to the 15 moments
+// sum_u g(u) x^a y^b.
+constexpr int kMono = 15;
+constexpr double kZernMono[kZern][kMono] = {
+    {1, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 0, 2, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 2, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 4.8989794855663558, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {-1.7320508075688772, 0, 0, 3.4641016151377544, 0, 3.4641016151377544, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 2.4494897427831779, 0, -2.4494897427831779, 0, 0, 0, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 0, 8.4852813742385713, 0, -2.8284271247461903, 0, 0, 0, 0, 0},
+    {0, 0, -5.6568542494923806, 0, 0, 0, 0, 8.4852813742385713, 0, 8.4852813742385713, 0, 0, 0, 0, 0},
+    {0, -5.6568542494923806, 0, 0, 0, 0, 8.4852813742385713, 0, 8.4852813742385713, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 2.8284271247461903, 0, -8.4852813742385713, 0, 0, 0, 0, 0, 0},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 12.649110640673518, 0, -12.649110640673518, 0},
+    {0, 0, 0, 0, -18.973665961010276, 0, 0, 0, 0, 0, 0, 25.298221281347036, 0, 25.298221281347036, 0},
+    {2.2360679774997898, 0, 0, -13.416407864998739, 0, -13.416407864998739, 0, 0, 0, 0, 13.416407864998739, 0, 26.832815729997478, 0, 13.416407864998739},
+    {0, 0, 0, -9.4868329805051381, 0, 9.4868329805051381, 0, 0, 0, 0, 12.649110640673518, 0, 0, 0, -12.649110640673518},
+    {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 3.1622776601683795, 0, -18.973665961010276, 0, 3.1622776601683795},
+};
+
 // Defocus phase per um, kappa = 2 pi (sqrt(1/l^2 - k^2) - 1/l), written in the
 // cancellation-free form -2 pi k^2 / (sqrt(1/l^2 - k^2) + 1/l); 0 if evanescent.
 template <class R>

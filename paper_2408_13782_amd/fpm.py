@@ -184,7 +184,6 @@ class State:
         self.O = O0.clone().contiguous()
         self.m_O = torch.zeros((M, M), dtype=torch.complex64, device=dev)
         self.v_O = torch.zeros((M, M), dtype=torch.complex64, device=dev)
-        self.g_O = torch.zeros((M, M), dtype=torch.complex64, device=dev)
         self.coeffs = torch.zeros(N_ZERN, dtype=torch.float32, device=dev)
         if coeffs0 is not None:
             self.coeffs.copy_(torch.as_tensor(np.asarray(coeffs0, np.float32)))
@@ -205,7 +204,7 @@ class State:
     def c(self) -> _State:
         s = self._c
         s.O, s.m_O, s.v_O, s.g_O = (self.O.data_ptr(), self.m_O.data_ptr(), self.v_O.data_ptr(),
-                                    self.g_O.data_ptr())
+                                    None)
         s.P = self.P.data_ptr()
         s.coeffs, s.m_c, s.v_c = self.coeffs.data_ptr(), self.m_c.data_ptr(), self.v_c.data_ptr()
         s.z_um, s.m_z, s.v_z = self.z_um.data_ptr(), self.m_z.data_ptr(), self.v_z.data_ptr()

@@ -237,7 +237,6 @@ def test_single_step_matches_oracle(dev):
     assert st.t == 1
     assert rel_l2(H(st.O), ost.O) <= 1e-6
     assert abs(float(H(st.loss)[0]) - loss) <= 1e-5 * loss
-    assert np.all(H(st.g_O) == 0)          # the step leaves the gradient buffer cleared
 
 
 def test_step_pupil_parameter_gradients_match_oracle(dev):
@@ -268,7 +267,7 @@ def test_step_pupil_parameter_gradients_match_oracle(dev):
     assert np.abs(H(st.P) - P1).max() <= 2e-6
 
 
-def test_loss_and_parameter_sums_are_deterministic(dev):
+def test_step_is_deterministic(dev):
     w = inputs.workload("small", learn_zernike=True, learn_z=True)
     say("deterministic reductions")
     pr = oracle_problem(w, seed=1)
@@ -280,7 +279,8 @@ def test_loss_and_parameter_sums_are_deterministic(dev):
         st = fpm.State(plan, T(pr.O0, dev), np.full(15, 0.1), 0.5)
         plan.step(st, problem.hparams(w), leds, A)
         torch.cuda.synchronize()
-        outs.append((H(st.loss).copy(), H(st.g_par).copy(), H(st.coeffs).copy()))
+        outs.append((H(st.loss).copy(), H(st.g_par).copy(), H(st.coeffs).copy(),
+                     H(st.O).copy(), H(st.P).copy()))
     for a, b in zip(outs[0], outs[1]):
         np.testing.assert_array_equal(a, b)
 

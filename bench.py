@@ -149,7 +149,7 @@ def main():
     total = args.warmup + args.steps + args.profile_steps
     epochs = -(-total // w.steps_per_epoch())
     batches = problem.schedule(inputs.led_permutations(w.n_led, epochs, seed=0), w.batch)
-    ds = problem.upload_schedule(batches[:total])
+    ds = problem.flatten_schedule(batches[:total])
     A = prob.meas_amp
     torch.cuda.synchronize()
     log("set-up done")

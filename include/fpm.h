@@ -21,7 +21,10 @@
  *   Eq. 2 with k_m the illumination propagation direction).
  *
  * Images.  Measured amplitudes A = sqrt(I), float [n_led][N][N] natural
- *   order, indexed by LED id. Batches are int32 device arrays of LED ids.
+ *   order, indexed by LED id. Batches are int32 HOST arrays of LED ids (the
+ *   random schedule is host data; each launch receives its batch's ids and
+ *   window offsets by value). Every id must lie in [0, n_led): a call with
+ *   an id outside fails with FPM_EINVAL and enqueues nothing.
  *
  * Loss (Eq. 5, amplitude form, summed over the batch as in Eq. 13):
  *   L = sum_b sum_r (sqrt(gamma_b) |psi_b(r)| - A_b(r))^2,
@@ -29,7 +32,8 @@
  * Gradients are real gradients written as complex numbers,
  *   g = dL/dRe + i dL/dIm, accumulated (+=) into caller buffers.
  *
- * Memory.  Every pointer argument except `desc`, `shifts_host` and the
+ * Memory.  Every pointer argument except `desc`, `shifts_host`, `leds`,
+ *   `batch_sizes`, the fpm_led_shifts outputs, the timing outputs and the
  *   output `plan` handle is DEVICE memory on the current HIP device, owned by
  *   the caller. The plan owns only its scratch (sized at creation from N, M
  *   and max_batch). No entry point allocates after plan creation.
@@ -71,7 +75,7 @@ typedef struct {
   int32_t n_lr;          /* N */
   int32_t upsample;      /* s, M = s N (M <= 4096) */
   int32_t n_led;         /* rows of the LED table */
-  int32_t max_batch;     /* largest B any call on this plan will pass */
+  int32_t max_batch;     /* largest B any call on this plan will pass (<= 64) */
   double wavelength_um;  /* lambda */
   double na;             /* objective numerical aperture */
   double mag;            /* objective magnification */
@@ -214,8 +218,9 @@ int fpm_step(fpm_plan* plan, fpm_state* state, const fpm_hparams* hp, const int3
 /*
  * n_steps consecutive updates (a whole solve or a slice of one) in one call:
  * step i uses the batch_sizes[i] LED ids that follow those of step i-1 in
- * `leds` (device, int32, concatenated); batch_sizes is HOST memory
- * [n_steps], each in [1, max_batch]. Same effect as n_steps fpm_step calls.
+ * `leds` (HOST, int32, concatenated); batch_sizes is HOST memory [n_steps],
+ * each in [1, max_batch]. Same effect as n_steps fpm_step calls; all ids
+ * are validated before anything is enqueued.
  */
 int fpm_run(fpm_plan* plan, fpm_state* state, const fpm_hparams* hp, const int32_t* leds,
             const int32_t* batch_sizes, int32_t n_steps, const float* gamma,

@@ -81,7 +81,6 @@ struct fpm_plan {
   bool hr_ok = false;
   std::vector<int2> shifts_h;
   int2* rowext = nullptr;     // [N] (first, last) disk column of each pupil row
-  int2* shifts = nullptr;     // [n_led]
   float2* twN = nullptr;      // [N]
   float2* twM = nullptr;      // [M] when the HR transforms are available
   float2* X = nullptr;        // [max_batch][N][N] row/column scratch
@@ -143,7 +142,6 @@ void plan_free(fpm_plan* p) {
   }
   for (auto e : p->event_pool) (void)hipEventDestroy(e);
   (void)hipFree(p->rowext);
-  (void)hipFree(p->shifts);
   (void)hipFree(p->twN);
   (void)hipFree(p->twM);
   (void)hipFree(p->X);
@@ -176,19 +174,31 @@ int check_batch(const fpm_plan* p, const int32_t* leds, int32_t B) {
   FPM_REQUIRE(B >= 0, "batch size must be >= 0");
   FPM_REQUIRE(B <= p->max_batch, "batch size exceeds the plan's max_batch");
   FPM_REQUIRE(B == 0 || leds != nullptr, "leds must not be NULL");
+  for (int b = 0; b < B; ++b) {
+    if (leds[b] < 0 || leds[b] >= p->n_led) {
+      char buf[96];
+      std::snprintf(buf, sizeof buf, "LED id %d at batch position %d is outside [0, %d)", leds[b],
+                    b, p->n_led);
+      return fail(FPM_EINVAL, buf);
+    }
+  }
   return FPM_OK;
 }
 
 enum { kCounterPupil = 0, kCounters = 1 };
 
+// LED ids (validated by check_batch) and window corners of one batch, by value.
 Batch batch_of(const fpm_plan* p, const int32_t* leds, int B) {
-  Batch b;
-  b.shifts = p->shifts;
-  b.leds = leds;
-  b.B = B;
-  b.n_led = p->n_led;
-  b.M = p->M;
-  return b;
+  Batch bt{};
+  bt.B = B;
+  bt.M = p->M;
+  const int base = p->M / 2 - p->N / 2;
+  for (int b = 0; b < B; ++b) {
+    const int2 s = p->shifts_h[leds[b]];
+    bt.led[b] = leds[b];
+    bt.win[b] = make_int2(base + s.x, base + s.y);
+  }
+  return bt;
 }
 
 Disk disk_of(const fpm_plan* p) {
@@ -197,6 +207,7 @@ Disk disk_of(const fpm_plan* p) {
   d.ky_lo = p->ky_lo;
   d.ky_hi = p->ky_hi;
   d.nrows = p->nrows;
+  d.r2i = (int)std::floor(p->radius * p->radius);
   return d;
 }
 
@@ -389,6 +400,7 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
   if (!lr_supported(d->n_lr)) return fail(FPM_EUNSUPPORTED, "n_lr must be 64, 128, 256 or 512");
   FPM_REQUIRE(d->upsample >= 1 && (int64_t)d->upsample * d->n_lr <= 4096, "upsample out of range");
   FPM_REQUIRE(d->n_led >= 1 && d->max_batch >= 1, "n_led and max_batch must be >= 1");
+  FPM_REQUIRE(d->max_batch <= kMaxSlots, "max_batch must be <= 64");
   FPM_REQUIRE(d->wavelength_um > 0 && d->na > 0 && d->mag > 0 && d->pixel_um > 0,
               "optics must be positive");
   fpm_plan* p = new fpm_plan();
@@ -471,7 +483,6 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
   int rc = FPM_OK;
   const auto twn = twiddles(p->N);
   if ((rc = upload(&p->rowext, ext.data(), ext.size())) ||
-      (rc = upload(&p->shifts, p->shifts_h.data(), p->shifts_h.size())) ||
       (rc = upload(&p->twN, twn.data(), twn.size())) ||
       (rc = upload<float2>(&p->X, nullptr, (size_t)p->max_batch * p->N * p->N)) ||
       (rc = upload<float2>(&p->gP, nullptr, (size_t)p->N * p->N)) ||
@@ -751,9 +762,12 @@ int fpm_run(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_t* led
   if (int rc = check_state(p, s, hp, meas_amp)) return rc;
   FPM_REQUIRE(n_steps >= 0, "n_steps must be >= 0");
   FPM_REQUIRE(n_steps == 0 || (leds && batch_sizes), "leds and batch_sizes must not be NULL");
+  size_t total = 0;
   for (int i = 0; i < n_steps; ++i) {
     FPM_REQUIRE(batch_sizes[i] >= 1 && batch_sizes[i] <= p->max_batch,
                 "every batch size must be in [1, max_batch]");
+    if (int rc = check_batch(p, leds + total, batch_sizes[i])) return rc;
+    total += batch_sizes[i];
   }
   hipStream_t st = (hipStream_t)stream;
   const bool learn_p = hp->learn_zernike || hp->learn_z;

@@ -119,12 +119,8 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
                                                 int tile_c0, float2 (&g)[4]) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) g[q] = make_float2(0.f, 0.f);
-  const int base = a.M / 2 - a.n / 2;
   for (int b = 0; b < a.bt.B; ++b) {
-    const int led = a.bt.leds[b];
-    if ((unsigned)led >= (unsigned)a.bt.n_led) continue;
-    const int2 s = a.bt.shifts[led];
-    const int wr = base + s.x, wc = base + s.y;
+    const int wr = a.bt.win[b].x, wc = a.bt.win[b].y;
     // whole-tile test against the disk's bounding box (uniform over the workgroup)
     if (tile_r0 + 31 < wr + a.dk.ky_lo || tile_r0 > wr + a.dk.ky_hi ||
         tile_c0 + 31 < wc + a.dk.ky_lo || tile_c0 > wc + a.dk.ky_hi)

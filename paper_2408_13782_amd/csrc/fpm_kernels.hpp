@@ -66,20 +66,36 @@ __device__ __forceinline__ void atomic_add_c(float2* p, float2 v) {
   unsafeAtomicAdd(f + 1, v.y);
 }
 
-// Batch description shared by the three passes.
+// The batch, passed by value: LED ids and the top-left corner (HR row, column)
+// of each LED's window, so no kernel has to look them up in memory.
+constexpr int kMaxSlots = 64;
+
 struct Batch {
-  const int2* shifts;   // [n_led] window offsets (row, col)
-  const int* leds;      // [B] LED ids
   int B;
-  int n_led;
   int M;
+  int led[kMaxSlots];
+  int2 win[kMaxSlots];
 };
 
-// Pupil disk: per-row column extents and the row range.
+// Pupil disk |u|^2 <= R^2: per-row column extents, the row range, and
+// floor(R^2) (the test on integer |u|^2 is exact against it).
 struct Disk {
   const int2* rowext;
   int ky_lo, ky_hi, nrows;
+  int r2i;
 };
+
+// First and last disk column of pupil row ky (exact integer square root).
+template <int N>
+__device__ __forceinline__ int2 disk_extent(const Disk& dk, int ky) {
+  const int uy = ky - N / 2;
+  const int q = dk.r2i - uy * uy;
+  if (q < 0) return make_int2(N, -1);
+  int h = (int)sqrtf((float)q);
+  while (h * h > q) --h;
+  while ((h + 1) * (h + 1) <= q) ++h;
+  return make_int2(N / 2 - h, N / 2 + h);
+}
 
 // Per-workgroup partials and the completion counter of a last-workgroup reduction.
 struct Reduction {
@@ -202,17 +218,14 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch b
   if (commit && blockIdx.x == 0) commit_scalars(staging, scal, threadIdx.x);
   int b, c;
   if (!xcd_map(blockIdx.x, chunks, bt.B, b, c)) return;
-  const int led = bt.leds[b];
-  if ((unsigned)led >= (unsigned)bt.n_led) return;   // invalid id: the image contributes nothing
   const int line = threadIdx.x / T;
   const int t = threadIdx.x % T;
   const int rr = c * L + line;
   const bool active = rr < dk.nrows;
   const int ky = dk.ky_lo + (active ? rr : 0);
-  const int2 ext = dk.rowext[ky];
-  const int2 s = bt.shifts[led];
-  const int base = bt.M / 2 - N / 2;
-  const float2* orow = O + (size_t)(base + s.x + ky) * bt.M + (base + s.y);
+  const int2 ext = disk_extent<N>(dk, ky);
+  const int2 w = bt.win[b];
+  const float2* orow = O + (size_t)(w.x + ky) * bt.M + w.y;
   const float2* prow = P + (size_t)ky * N;
   float2 v[E];
 #pragma unroll
@@ -242,14 +255,13 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
   constexpr int L = ColLines<N>::value;
   __shared__ float2 lds[N * (L + 1)];
   int b, g;
-  bool live = xcd_map(blockIdx.x, groups, bt.B, b, g);
-  const int led = live ? bt.leds[b] : -1;
-  live = live && (unsigned)led < (unsigned)bt.n_led;
+  const bool live = xcd_map(blockIdx.x, groups, bt.B, b, g);
   const int line = threadIdx.x % L;
   const int t = threadIdx.x / L;
   const int x = g * L + line;
   float acc = 0.f;
   if (live) {
+    const int led = bt.led[b];
     float2* xb = X + (size_t)b * N * N;
     float2 v[E];
 #pragma unroll
@@ -257,9 +269,15 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
       const int ky = half_shift<N>(t + m * T);
       v[m] = (ky >= dk.ky_lo && ky <= dk.ky_hi) ? xb[(size_t)ky * N + x] : make_float2(0.f, 0.f);
     }
+    float a_meas[kForward ? 1 : E];
+    if constexpr (!kForward) {
+      const float* ab = A + (size_t)led * N * N;
+#pragma unroll
+      for (int m = 0; m < E; ++m) a_meas[m] = ab[(size_t)(t + m * T) * N + x];   // prefetch
+    }
+    const float sg = gamma ? sqrtf(gamma[led]) : 1.0f;
     auto lay = [line](int n) { return n * (L + 1) + line; };
     Plan1D<N>::template run<+1>(v, t, lds, lay, tw);
-    const float sg = gamma ? sqrtf(gamma[led]) : 1.0f;
     if constexpr (kForward) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
@@ -270,13 +288,11 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
         if (field_out) field_out[o] = psi;
       }
     } else {
-      const float* ab = A + (size_t)led * N * N;
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const int y = t + m * T;
         const float2 psi = cscale(v[m], inv_m);
         const float a = sqrtf(psi.x * psi.x + psi.y * psi.y);
-        const float e = sg * a - ab[(size_t)y * N + x];
+        const float e = sg * a - a_meas[m];
         acc += e * e;
         const float f = a > 0.f ? 2.f * sg * e / a : 0.f;
         v[m] = cscale(psi, f);
@@ -313,11 +329,10 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
   constexpr int T = Plan1D<N>::T;
   constexpr int E = N / T;
   constexpr int L = kRowThreads / T;
+  constexpr bool kNeedC = MODE == kGradOP || MODE == kPatchZern;
   __shared__ float2 lds[L * (N + 1)];
   int b, c;
-  bool live = xcd_map(blockIdx.x, chunks, bt.B, b, c);
-  const int led = live ? bt.leds[b] : -1;
-  live = live && (unsigned)led < (unsigned)bt.n_led;
+  const bool live = xcd_map(blockIdx.x, chunks, bt.B, b, c);
   const int line = threadIdx.x / T;
   const int t = threadIdx.x % T;
   const int rr = c * L + line;
@@ -328,16 +343,23 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
   for (int j = 0; j < kPar; ++j) zacc[j] = 0.f;
   if (live) {
     float2* xr = X + ((size_t)b * N + ky) * N;
-    float2 v[E];
+    const int2 ext = disk_extent<N>(dk, ky);
+    const int2 w = bt.win[b];
+    const size_t orow = (size_t)(w.x + ky) * bt.M + w.y;
+    const float2* prow = P + (size_t)ky * N;
+    float2 v[E], pv[E], cv[kNeedC ? E : 1];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = active ? xr[t + m * T] : make_float2(0.f, 0.f);
+    // the pupil and the cropped spectrum at this thread's output columns, fetched early
+#pragma unroll
+    for (int m = 0; m < E; ++m) {
+      const int kx = half_shift<N>(t + m * T);
+      const bool in = active && kx >= ext.x && kx <= ext.y;
+      pv[m] = in ? prow[kx] : make_float2(0.f, 0.f);
+      if constexpr (kNeedC) cv[m] = in ? O[orow + kx] : make_float2(0.f, 0.f);
+    }
     Plan1D<N>::template run<-1>(v, t, lds + line * (N + 1), [](int n) { return n; }, tw);
     if (active) {
-      const int2 s = bt.shifts[led];
-      const int base = bt.M / 2 - N / 2;
-      const int2 ext = dk.rowext[ky];
-      const size_t orow = (size_t)(base + s.x + ky) * bt.M + (base + s.y);
-      const float2* prow = P + (size_t)ky * N;
       const int uy = ky - N / 2;
       const float ir = (float)pg.inv_r;
       // row moments S_a = sum g_theta x^a (a <= 4) and sum g_theta kappa
@@ -347,25 +369,25 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
         const int kx = half_shift<N>(t + m * T);
         if (kx >= ext.x && kx <= ext.y) {
           const float2 g = v[m];
-          const float2 p = prow[kx];
+          const float2 p = pv[m];
           if constexpr (MODE == kGradO || MODE == kGradOP) {
             atomic_add_c(gO + orow + kx, cmulc(p, g));
           } else {
             xr[kx] = cmulc(p, g);   // this row was read whole into registers above
           }
           if constexpr (MODE == kGradOP) {
-            atomic_add_c(gP + (size_t)ky * N + kx, cmulc(O[orow + kx], g));
+            atomic_add_c(gP + (size_t)ky * N + kx, cmulc(cv[m], g));
           } else if constexpr (MODE == kPatchZern) {
-            const float2 gp = cmulc(O[orow + kx], g);           // conj(C) g_Phi
+            const float2 gp = cmulc(cv[m], g);                  // conj(C) g_Phi
             const float gth = gp.y * p.x - gp.x * p.y;          // Im(g_P conj(P))
             const int ux = kx - N / 2;
-            const float x = (float)ux * ir;
-            const float gx = gth * x, gx2 = gx * x, gx3 = gx2 * x;
+            const float xx = (float)ux * ir;
+            const float gx = gth * xx, gx2 = gx * xx, gx3 = gx2 * xx;
             S0 += gth;
             S1 += gx;
             S2 += gx2;
             S3 += gx3;
-            S4 += gx3 * x;
+            S4 += gx3 * xx;
             SK += gth * kappa_tab[ux * ux + uy * uy];
           }
         }

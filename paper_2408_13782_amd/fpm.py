@@ -257,12 +257,11 @@ class Plan:
         import torch
         _need(P, name, torch.complex64, (self.N, self.N))
 
-    def _leds(self, leds):
-        import torch
-        _need(leds, "leds", torch.int32)
-        if leds.dim() != 1:
-            raise FpmError("leds must be one-dimensional")
-        return int(leds.numel())
+    @staticmethod
+    def _leds(leds):
+        """LED ids as a host int32 array (the library validates the values)."""
+        arr = np.ascontiguousarray(np.asarray(leds, dtype=np.int32).reshape(-1))
+        return arr, int(arr.size)
 
     def _images(self, A, gamma):
         import torch
@@ -287,12 +286,12 @@ class Plan:
         import torch
         self._spectrum(O)
         self._pupil(P)
-        B = self._leds(leds)
+        ids, B = self._leds(leds)
         _need(gamma, "gamma", torch.float32, (self.n_led,), optional=True)
         amp = torch.empty((B, self.N, self.N), dtype=torch.float32, device=O.device)
         field = (torch.empty((B, self.N, self.N), dtype=torch.complex64, device=O.device)
                  if with_field else None)
-        _check(self._lib.fpm_forward(self._h, _ptr(O), _ptr(P), _ptr(leds), B, _ptr(gamma),
+        _check(self._lib.fpm_forward(self._h, _ptr(O), _ptr(P), ids.ctypes.data, B, _ptr(gamma),
                                      _ptr(amp), _ptr(field), _stream()))
         return (amp, field) if with_field else amp
 
@@ -300,12 +299,12 @@ class Plan:
         import torch
         self._spectrum(O)
         self._pupil(P)
-        B = self._leds(leds)
+        ids, B = self._leds(leds)
         self._images(meas_amp, gamma)
         self._spectrum(gO, "gO")
         _need(gP, "gP", torch.complex64, (self.N, self.N), optional=True)
         _need(loss, "loss", torch.float64, min_numel=1, optional=True)
-        _check(self._lib.fpm_backward(self._h, _ptr(O), _ptr(P), _ptr(leds), B, _ptr(gamma),
+        _check(self._lib.fpm_backward(self._h, _ptr(O), _ptr(P), ids.ctypes.data, B, _ptr(gamma),
                                       _ptr(meas_amp), _ptr(gO), _ptr(gP), _ptr(loss), _stream()))
 
     def pupil_grad(self, gP, P, g_par):
@@ -316,20 +315,20 @@ class Plan:
         _check(self._lib.fpm_pupil_grad(self._h, _ptr(gP), _ptr(P), _ptr(g_par), _stream()))
 
     def step(self, state: State, hp: HParams, leds, meas_amp, gamma=None):
-        B = self._leds(leds)
+        ids, B = self._leds(leds)
         self._images(meas_amp, gamma)
         self._spectrum(state.O)
         self._pupil(state.P)
         cs = state.c()
         hc = hp.c()
-        _check(self._lib.fpm_step(self._h, C.byref(cs), C.byref(hc), _ptr(leds), B, _ptr(gamma),
+        _check(self._lib.fpm_step(self._h, C.byref(cs), C.byref(hc), ids.ctypes.data, B, _ptr(gamma),
                                   _ptr(meas_amp), _stream()))
         state.t = cs.t
 
     def run(self, state: State, hp: HParams, leds_flat, batch_sizes, meas_amp, gamma=None):
         """Consecutive updates: batch i is the next batch_sizes[i] ids of leds_flat."""
         sizes = np.ascontiguousarray(np.asarray(batch_sizes, np.int32))
-        n = self._leds(leds_flat)
+        ids, n = self._leds(leds_flat)
         if int(sizes.sum()) > n:
             raise FpmError("batch sizes exceed the number of LED ids")
         self._images(meas_amp, gamma)
@@ -337,7 +336,7 @@ class Plan:
         self._pupil(state.P)
         cs = state.c()
         hc = hp.c()
-        _check(self._lib.fpm_run(self._h, C.byref(cs), C.byref(hc), _ptr(leds_flat),
+        _check(self._lib.fpm_run(self._h, C.byref(cs), C.byref(hc), ids.ctypes.data,
                                  sizes.ctypes.data, int(sizes.size), _ptr(gamma), _ptr(meas_amp),
                                  _stream()))
         state.t = cs.t

@@ -55,10 +55,10 @@ def simulate(prob: Problem, seed: int = 0, device="cuda"):
     z_true = inputs.true_defocus(w, seed)
     P_true = plan.pupil(None, torch.tensor([z_true], dtype=torch.float32, device=device))
     A = torch.empty((w.n_led, w.n_lr, w.n_lr), dtype=torch.float32, device=device)
-    all_leds = torch.arange(w.n_led, dtype=torch.int32, device=device)
+    all_leds = np.arange(w.n_led, dtype=np.int32)
     for start in range(0, w.n_led, plan.max_batch):
         leds = all_leds[start:start + plan.max_batch]
-        A[start:start + leds.numel()] = plan.forward(O_true, P_true, leds)
+        A[start:start + leds.size] = plan.forward(O_true, P_true, leds)
     q = torch.as_tensor(np.where(prob.bright, w.q_bright, w.q_dark).astype(np.float32),
                         device=device).view(-1, 1, 1)
     gen = torch.Generator(device=device)
@@ -93,32 +93,32 @@ def hparams(w: inputs.Workload) -> fpm.HParams:
 
 
 @dataclass
-class DeviceSchedule:
-    flat: object            # torch int32 [sum of batch sizes], all batches back to back
+class Schedule:
+    """All batches of a solve back to back (host int32; the library takes host ids)."""
+    flat: np.ndarray        # int32 [sum of batch sizes]
     sizes: np.ndarray       # int32 [n_steps]
-    offsets: np.ndarray     # int64 [n_steps] start of each batch in flat
+    offsets: np.ndarray     # int64 [n_steps + 1]
 
-    def view(self, i: int):
-        return self.flat[int(self.offsets[i]):int(self.offsets[i]) + int(self.sizes[i])]
+    def view(self, i: int) -> np.ndarray:
+        return self.flat[self.offsets[i]:self.offsets[i + 1]]
 
     def span(self, start: int, stop: int):
-        """(flat ids, sizes) of steps start..stop-1, for Plan.run."""
-        a = int(self.offsets[start]) if start < len(self.sizes) else int(self.flat.numel())
-        b = int(self.offsets[stop]) if stop < len(self.sizes) else int(self.flat.numel())
-        return self.flat[a:b], self.sizes[start:stop]
+        """(ids, sizes) of steps start..stop-1, for Plan.run."""
+        return self.flat[self.offsets[start]:self.offsets[stop]], self.sizes[start:stop]
+
+    def __len__(self):
+        return len(self.sizes)
 
 
-def upload_schedule(batches, device="cuda") -> DeviceSchedule:
-    """All batches as one device array (no host-to-device copy per step)."""
-    import torch
+def flatten_schedule(batches) -> Schedule:
     sizes = np.array([len(b) for b in batches], np.int32)
-    offsets = np.concatenate([[0], np.cumsum(sizes)[:-1]]).astype(np.int64)
-    flat = torch.as_tensor(np.concatenate(batches).astype(np.int32), device=device)
-    return DeviceSchedule(flat, sizes, offsets)
+    offsets = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    flat = np.ascontiguousarray(np.concatenate(batches).astype(np.int32))
+    return Schedule(flat, sizes, offsets)
 
 
-def solve(prob: Problem, state: fpm.State, hp: fpm.HParams, sched: DeviceSchedule, gamma=None):
+def solve(prob: Problem, state: fpm.State, hp: fpm.HParams, sched: Schedule, gamma=None):
     """Run every random-batch update of the schedule in one library call."""
-    flat, sizes = sched.span(0, len(sched.sizes))
+    flat, sizes = sched.span(0, len(sched))
     prob.plan.run(state, hp, flat, sizes, prob.meas_amp, gamma)
     return state

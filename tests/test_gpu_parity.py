@@ -128,7 +128,7 @@ def test_forward_matches_oracle(dev, n_lr, B):
                  fo.defocus_phase_per_um(opt)).astype(np.complex64)
     gamma = inputs.random_real((w.n_led,), seed=2, lo=0.7, hi=1.3)
     leds = inputs.random_indices(w.n_led, B, seed=B)
-    a, f = plan.forward(T(O, dev), T(P, dev), T(leds, dev), T(gamma, dev), with_field=True)
+    a, f = plan.forward(T(O, dev), T(P, dev), leds, T(gamma, dev), with_field=True)
     torch.cuda.synchronize()
     want_a = fo.forward_amplitudes(O.astype(np.complex128), P.astype(np.complex128), shifts,
                                    leds, gamma.astype(np.float64))
@@ -144,7 +144,7 @@ def _backward_case(dev, w, O, P, leds, A, gamma, with_gP=True):
     gO = torch.zeros((w.m_hr, w.m_hr), dtype=torch.complex64, device=dev)
     gP = torch.zeros((w.n_lr, w.n_lr), dtype=torch.complex64, device=dev) if with_gP else None
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
-    plan.backward(T(O, dev), T(P, dev), T(leds, dev), T(A, dev), gO, gP, loss,
+    plan.backward(T(O, dev), T(P, dev), leds, T(A, dev), gO, gP, loss,
                   None if gamma is None else T(gamma, dev))
     torch.cuda.synchronize()
     ref = fo.loss_and_grads(O.astype(np.complex128), P.astype(np.complex128), shifts, leds,
@@ -229,7 +229,7 @@ def test_single_step_matches_oracle(dev):
     st = _gpu_state(plan, pr.O0, dev)
     hp = problem.hparams(w)
     leds = inputs.random_indices(w.n_led, w.batch, seed=21)
-    plan.step(st, hp, T(leds, dev), T(pr.A, dev))
+    plan.step(st, hp, leds, T(pr.A, dev))
     torch.cuda.synchronize()
     ost = fo.init_state(pr.O0)
     cfg = fo.SolveConfig(lr_object=w.lr_object)
@@ -252,7 +252,7 @@ def test_step_pupil_parameter_gradients_match_oracle(dev):
     leds = inputs.random_indices(w.n_led, w.batch, seed=41)
     P = fo.pupil(pr.mask, pr.zern, c0.astype(np.float64), 1.5, pr.kappa)
     assert np.abs(H(st.P) - P).max() <= 2e-6
-    plan.step(st, hp, T(leds, dev), T(pr.A, dev))
+    plan.step(st, hp, leds, T(pr.A, dev))
     torch.cuda.synchronize()
     ref = fo.loss_and_grads(pr.O0.astype(np.complex128), P, pr.shifts, leds, pr.A.astype(np.float64))
     g_c, g_z, g_theta = fo.pupil_param_grads(ref.g_P, P, pr.zern, pr.kappa)
@@ -272,7 +272,7 @@ def test_step_is_deterministic(dev):
     say("deterministic reductions")
     pr = oracle_problem(w, seed=1)
     plan = make_plan(w, pr.shifts, w.batch)
-    leds = T(inputs.random_indices(w.n_led, w.batch, seed=3), dev)
+    leds = inputs.random_indices(w.n_led, w.batch, seed=3)
     A = T(pr.A, dev)
     outs = []
     for _ in range(2):
@@ -297,7 +297,7 @@ def test_step_with_zernike_learning_matches_oracle(dev):
     A64 = pr.A.astype(np.float64)
     for i in range(2):
         leds = inputs.random_indices(w.n_led, w.batch, seed=30 + i)
-        plan.step(st, hp, T(leds, dev), T(pr.A, dev))
+        plan.step(st, hp, leds, T(pr.A, dev))
         fo.step(ost, cfg, pr.mask, pr.zern, pr.kappa, pr.shifts, leds, A64)
     torch.cuda.synchronize()
     # Adam's first steps are nearly lr * sign(g): a component whose gradient is within
@@ -311,7 +311,7 @@ def test_step_with_zernike_learning_matches_oracle(dev):
 
 def _gradient_at_gpu_state(dev, plan, pr, st, leds, P):
     gO = torch.zeros_like(st.O)
-    plan.backward(st.O, P, T(np.asarray(leds, np.int32), dev), T(pr.A, dev), gO)
+    plan.backward(st.O, P, np.asarray(leds, np.int32), T(pr.A, dev), gO)
     torch.cuda.synchronize()
     ref = fo.loss_and_grads(H(st.O).astype(np.complex128), H(P).astype(np.complex128),
                             pr.shifts, leds, pr.A.astype(np.float64))
@@ -329,7 +329,7 @@ def test_small_solve_matches_oracle(dev):
     st = _gpu_state(plan, pr.O0, dev)
     hp = problem.hparams(w)
     P = plan.pupil()
-    ds = problem.upload_schedule(problem.schedule(perms, w.batch), dev)
+    ds = problem.flatten_schedule(problem.schedule(perms, w.batch))
     A = T(pr.A, dev)
     # first half through fpm_run, per-step gradient at the GPU's own state, second half stepwise
     flat, sizes = ds.span(0, 70)
@@ -392,19 +392,31 @@ def test_edge_cases(dev):
     gO = torch.zeros_like(O)
     loss = torch.zeros(1, dtype=torch.float64, device=dev)
     # empty batch: nothing happens
-    plan.backward(O, P, torch.zeros(0, dtype=torch.int32, device=dev), A, gO, None, loss)
+    plan.backward(O, P, np.zeros(0, np.int32), A, gO, None, loss)
     torch.cuda.synchronize()
     assert float(H(loss)[0]) == 0.0 and not torch.any(gO != 0)
-    # an out-of-range LED id contributes nothing; the valid ones are unaffected
-    leds = np.array([3, 999, 17, -1], np.int32)
-    plan.backward(O, P, T(leds, dev), A, gO, None, loss)
+    # an out-of-range LED id is refused before anything runs
+    for bad_ids in ([3, 999, 17], [-1], [49]):
+        with pytest.raises(fpm.FpmError):
+            plan.backward(O, P, np.array(bad_ids, np.int32), A, gO, None, loss)
+        with pytest.raises(fpm.FpmError):
+            plan.run(fpm.State(plan, O), problem.hparams(w), np.array([0, 1] + bad_ids, np.int32),
+                     [2, len(bad_ids)], A)
+    torch.cuda.synchronize()
+    assert float(H(loss)[0]) == 0.0 and not torch.any(gO != 0)
+    # a ragged batch of 5 (not a multiple of 8 XCD slots) with repeated LEDs
+    leds = np.array([3, 17, 3, 40, 17], np.int32)
+    plan.backward(O, P, leds, A, gO, None, loss)
     torch.cuda.synchronize()
     ref = fo.loss_and_grads(pr.O0.astype(np.complex128), H(P).astype(np.complex128), pr.shifts,
-                            [3, 17], pr.A.astype(np.float64))
+                            leds, pr.A.astype(np.float64))
     assert rel_l2(H(gO), ref.g_O) <= GRAD_TOL
+    assert abs(float(H(loss)[0]) - ref.loss) <= 1e-5 * ref.loss
     # batch larger than the plan allows
     with pytest.raises(fpm.FpmError):
-        plan.backward(O, P, torch.zeros(9, dtype=torch.int32, device=dev), A, gO)
+        plan.backward(O, P, np.zeros(9, np.int32), A, gO)
+    with pytest.raises(fpm.FpmError):
+        fpm.Plan(w.n_lr, w.upsample, pr.shifts, 65, w.wavelength_um, w.na, w.mag, w.pixel_um)
     # a window leaving the HR grid is refused at plan creation
     bad = pr.shifts.copy()
     bad[0] = (w.m_hr, 0)

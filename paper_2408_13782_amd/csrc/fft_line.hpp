@@ -277,6 +277,23 @@ struct Stages {
   }
 };
 
+// LDS layout of one line in the row passes: one padding slot after every 16
+// elements, so the first Stockham stage's writes (stride 16) and the strided
+// reads hit distinct banks.
+template <int N> struct RowLds {
+  static constexpr int kStride = N + N / 16;   // slots per line
+  __device__ __forceinline__ static int at(int n) { return n + (n >> 4); }
+};
+
+// Copy the twiddle table into LDS (call at kernel start, before the first
+// transform; the first stage needs no twiddles and its exchange barrier
+// orders these writes before any twiddle read).
+template <int N>
+__device__ __forceinline__ void stage_twiddles(float2* __restrict__ lds_tw,
+                                               const float2* __restrict__ tw) {
+  for (int i = threadIdx.x; i < N; i += blockDim.x) lds_tw[i] = tw[i];
+}
+
 // Radix plans: thread count T per line and stage radices for each size.
 template <int N> struct Plan1D;
 template <> struct Plan1D<64> {

@@ -281,7 +281,7 @@ hr_rows(HrArgs a, const float2* __restrict__ tw) {
   constexpr int E = M / T;
   constexpr int L = HrRowLines<M>::value;
   constexpr int DIR = (MODE == kRowFwd || MODE == kRowInit) ? -1 : +1;
-  __shared__ float2 lds[L * (M + 1)];
+  __shared__ float2 lds[L * RowLds<M>::kStride];
   const int line = threadIdx.x / T, t = threadIdx.x % T;
   const int row = blockIdx.x * L + line;   // grid covers M rows exactly
   float2 v[E];
@@ -324,7 +324,7 @@ hr_rows(HrArgs a, const float2* __restrict__ tw) {
       v[m] = val;
     }
   }
-  Plan1D<M>::template run<DIR>(v, t, lds + line * (M + 1), [](int n) { return n; }, tw);
+  Plan1D<M>::template run<DIR>(v, t, lds + line * RowLds<M>::kStride, [](int n) { return RowLds<M>::at(n); }, tw);
   float2* orow = a.out + (size_t)row * M;
   if constexpr (DIR < 0) {
 #pragma unroll

@@ -214,10 +214,12 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch b
   constexpr int T = Plan1D<N>::T;
   constexpr int E = N / T;
   constexpr int L = kRowThreads / T;
-  __shared__ float2 lds[L * (N + 1)];
+  __shared__ float2 lds[L * RowLds<N>::kStride];
+  __shared__ float2 lds_tw[N];
   if (commit && blockIdx.x == 0) commit_scalars(staging, scal, threadIdx.x);
   int b, c;
   if (!xcd_map(blockIdx.x, chunks, bt.B, b, c)) return;
+  stage_twiddles<N>(lds_tw, tw);
   const int line = threadIdx.x / T;
   const int t = threadIdx.x % T;
   const int rr = c * L + line;
@@ -234,7 +236,7 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch b
     const bool in = active && kx >= ext.x && kx <= ext.y;
     v[m] = in ? cmul(orow[kx], prow[kx]) : make_float2(0.f, 0.f);
   }
-  Plan1D<N>::template run<+1>(v, t, lds + line * (N + 1), [](int n) { return n; }, tw);
+  Plan1D<N>::template run<+1>(v, t, lds + line * RowLds<N>::kStride, [](int n) { return RowLds<N>::at(n); }, lds_tw);
   if (active) {
     float2* xr = X + ((size_t)b * N + ky) * N;
 #pragma unroll
@@ -254,8 +256,10 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
   constexpr int E = N / T;
   constexpr int L = ColLines<N>::value;
   __shared__ float2 lds[N * (L + 1)];
+  __shared__ float2 lds_tw[N];
   int b, g;
   const bool live = xcd_map(blockIdx.x, groups, bt.B, b, g);
+  if (live) stage_twiddles<N>(lds_tw, tw);
   const int line = threadIdx.x % L;
   const int t = threadIdx.x / L;
   const int x = g * L + line;
@@ -277,7 +281,7 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
     }
     const float sg = gamma ? sqrtf(gamma[led]) : 1.0f;
     auto lay = [line](int n) { return n * (L + 1) + line; };
-    Plan1D<N>::template run<+1>(v, t, lds, lay, tw);
+    Plan1D<N>::template run<+1>(v, t, lds, lay, lds_tw);
     if constexpr (kForward) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
@@ -297,7 +301,7 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
         const float f = a > 0.f ? 2.f * sg * e / a : 0.f;
         v[m] = cscale(psi, f);
       }
-      Plan1D<N>::template run<-1>(v, t, lds, lay, tw);
+      Plan1D<N>::template run<-1>(v, t, lds, lay, lds_tw);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int ky = half_shift<N>(t + m * T);
@@ -330,9 +334,11 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
   constexpr int E = N / T;
   constexpr int L = kRowThreads / T;
   constexpr bool kNeedC = MODE == kGradOP || MODE == kPatchZern;
-  __shared__ float2 lds[L * (N + 1)];
+  __shared__ float2 lds[L * RowLds<N>::kStride];
+  __shared__ float2 lds_tw[N];
   int b, c;
   const bool live = xcd_map(blockIdx.x, chunks, bt.B, b, c);
+  if (live) stage_twiddles<N>(lds_tw, tw);
   const int line = threadIdx.x / T;
   const int t = threadIdx.x % T;
   const int rr = c * L + line;
@@ -358,7 +364,7 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
       pv[m] = in ? prow[kx] : make_float2(0.f, 0.f);
       if constexpr (kNeedC) cv[m] = in ? O[orow + kx] : make_float2(0.f, 0.f);
     }
-    Plan1D<N>::template run<-1>(v, t, lds + line * (N + 1), [](int n) { return n; }, tw);
+    Plan1D<N>::template run<-1>(v, t, lds + line * RowLds<N>::kStride, [](int n) { return RowLds<N>::at(n); }, lds_tw);
     if (active) {
       const int uy = ky - N / 2;
       const float ir = (float)pg.inv_r;

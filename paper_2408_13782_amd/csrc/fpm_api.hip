@@ -344,6 +344,18 @@ int cols_grid_of(const fpm_plan* p, int B) {
 
 int pupil_wgs(const fpm_plan* p) { return (p->N * p->N + kPupilPerWg - 1) / kPupilPerWg; }
 
+int launch_update(fpm_plan* p, const UpdateArgs& a, int grid, hipStream_t st) {
+  switch (p->N) {
+    case 64: update<64><<<grid, 256, 0, st>>>(a); break;
+    case 128: update<128><<<grid, 256, 0, st>>>(a); break;
+    case 256: update<256><<<grid, 256, 0, st>>>(a); break;
+    case 512: update<512><<<grid, 256, 0, st>>>(a); break;
+    default: return fail(FPM_EUNSUPPORTED, "unsupported N");
+  }
+  FPM_HIP(hipGetLastError());
+  return FPM_OK;
+}
+
 template <int M>
 int launch_hr(fpm_plan* p, HrArgs a, int row_mode, int dir, hipStream_t st) {
   constexpr int Lr = HrRowLines<M>::value;
@@ -626,8 +638,7 @@ int fpm_backward(fpm_plan* p, const fpm_c32* O, const fpm_c32* P, const int32_t*
     a.n_loss = cols_grid_of(p, B);
     a.loss = loss;
     Timed tm(p, kAdamObject, st);
-    update<<<1, 256, 0, st>>>(a);
-    FPM_HIP(hipGetLastError());
+    if (int rc = launch_update(p, a, 1, st)) return rc;
   }
   return FPM_OK;
 }
@@ -727,7 +738,7 @@ int step_launches(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_
   const int extra = learn_p ? pupil_wgs(p) : 1;   // must match the kernel's n_pw
   {
     Timed tm(p, kAdamObject, st);
-    update<<<p->n_tiles + extra, 256, 0, st>>>(a);
+    if (int rc = launch_update(p, a, p->n_tiles + extra, st)) return rc;
   }
   FPM_HIP(hipGetLastError());
   s->t = t;

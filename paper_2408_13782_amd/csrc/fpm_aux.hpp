@@ -115,41 +115,65 @@ constexpr int kPupilPerWg = 1024;   // pupil points rebuilt per workgroup
 
 // Gradient of the spectrum at 4 consecutive pixels (row r, columns c0..c0+3):
 // the sum, in batch order, of the patches of the LEDs whose disk covers them.
+template <int N>
 __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int c0, int tile_r0,
                                                 int tile_c0, float2 (&g)[4]) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) g[q] = make_float2(0.f, 0.f);
+  // slots whose disk bounding box meets this 32 x 32 tile (uniform over the workgroup)
+  unsigned long long hit = 0ull;
   for (int b = 0; b < a.bt.B; ++b) {
     const int wr = a.bt.win[b].x, wc = a.bt.win[b].y;
-    // whole-tile test against the disk's bounding box (uniform over the workgroup)
-    if (tile_r0 + 31 < wr + a.dk.ky_lo || tile_r0 > wr + a.dk.ky_hi ||
-        tile_c0 + 31 < wc + a.dk.ky_lo || tile_c0 > wc + a.dk.ky_hi)
-      continue;
-    const int ky = r - wr;
-    if (ky < a.dk.ky_lo || ky > a.dk.ky_hi) continue;
-    const int2 e = a.dk.rowext[ky];
-    const float2* xr = a.X + ((size_t)b * a.n + ky) * a.n - wc;
+    const bool meets = !(tile_r0 + 31 < wr + a.dk.ky_lo || tile_r0 > wr + a.dk.ky_hi ||
+                         tile_c0 + 31 < wc + a.dk.ky_lo || tile_c0 > wc + a.dk.ky_hi);
+    if (meets) hit |= 1ull << b;
+  }
+  while (hit) {
+    // two slots per round: all loads issued (at addresses clamped into the disk)
+    // before the masked, in-order accumulation
+    int bs[2];
+    bs[0] = __ffsll((long long)hit) - 1;
+    hit &= hit - 1;
+    bs[1] = hit ? __ffsll((long long)hit) - 1 : -1;
+    if (hit) hit &= hit - 1;
+    float2 val[2][4];
+    bool ok[2][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int kx = c0 + q - wc;
-      if (kx >= e.x && kx <= e.y) {
-        const float2 v = xr[c0 + q];
-        g[q].x += v.x;
-        g[q].y += v.y;
+    for (int u = 0; u < 2; ++u) {
+      const int b = bs[u] < 0 ? bs[0] : bs[u];
+      const int wr = a.bt.win[b].x, wc = a.bt.win[b].y;
+      const int ky = r - wr;
+      const int kyc = min(max(ky, a.dk.ky_lo), a.dk.ky_hi);
+      const int2 e = disk_extent<N>(a.dk, kyc);
+      const float2* xr = a.X + ((size_t)b * N + kyc) * N;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int kx = c0 + q - wc;
+        ok[u][q] = bs[u] >= 0 && ky == kyc && kx >= e.x && kx <= e.y;
+        val[u][q] = xr[min(max(kx, e.x), e.y)];
       }
     }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (ok[u][q]) {
+          g[q].x += val[u][q].x;
+          g[q].y += val[u][q].y;
+        }
   }
 }
 
+template <int N>
 __global__ void __launch_bounds__(256) update(UpdateArgs a) {
-  const int n_pw = a.pupil ? (a.n * a.n + kPupilPerWg - 1) / kPupilPerWg : 1;
+  const int n_pw = a.pupil ? (N * N + kPupilPerWg - 1) / kPupilPerWg : 1;
   if ((int)blockIdx.x >= n_pw) {
     const int2 tl = a.tiles[blockIdx.x - n_pw];
     const int r = tl.x * 32 + (threadIdx.x >> 3);
     const int col = tl.y * 32 + (threadIdx.x & 7) * 4;         // complex column
     const size_t f = ((size_t)r * a.M + col) * 2;                // float offset
     float2 g[4];
-    gather_gradient(a, r, col, tl.x * 32, tl.y * 32, g);
+    gather_gradient<N>(a, r, col, tl.x * 32, tl.y * 32, g);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       float4* po = reinterpret_cast<float4*>(a.O + f) + h;
@@ -228,13 +252,12 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     if (pw == 0 && threadIdx.x < kScal) a.staging[threadIdx.x] = next[threadIdx.x];
     if (pw == 0 && threadIdx.x < kPar && a.g_par) a.g_par[threadIdx.x] += red[threadIdx.x];
     // rebuild this workgroup's share of the pupil from the new parameters (FP64)
-    const int n = a.pg.n;
-    const int end = min((pw + 1) * kPupilPerWg, n * n);
+    const int end = min((pw + 1) * kPupilPerWg, N * N);
     for (int idx = pw * kPupilPerWg + threadIdx.x; idx < end; idx += 256) {
-      const int ky = idx / n, kx = idx - ky * n;
-      const int2 e = a.rowext[ky];
+      const int ky = idx / N, kx = idx - ky * N;
+      const int2 e = disk_extent<N>(a.dk, ky);
       if (kx < e.x || kx > e.y) continue;   // off the disk P stays zero
-      const double ux = kx - n / 2, uy = ky - n / 2;
+      const double ux = kx - N / 2, uy = ky - N / 2;
       double z[kZern];
       zernike15(ux * a.pg.inv_r, uy * a.pg.inv_r, z);
       double th = 0.0;

@@ -229,12 +229,22 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch b
   const int2 w = bt.win[b];
   const float2* orow = O + (size_t)(w.x + ky) * bt.M + w.y;
   const float2* prow = P + (size_t)ky * N;
+  // Unconditional loads at addresses clamped into the disk (the same cache lines
+  // as the neighbouring disk pixels), then masked: every load of the thread is
+  // in flight at once instead of one branch-guarded load after another.
+  float2 ov[E], pvv[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) {
+    const int kx = min(max(half_shift<N>(t + m * T), ext.x), ext.y);
+    ov[m] = orow[kx];
+    pvv[m] = prow[kx];
+  }
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int kx = half_shift<N>(t + m * T);
     const bool in = active && kx >= ext.x && kx <= ext.y;
-    v[m] = in ? cmul(orow[kx], prow[kx]) : make_float2(0.f, 0.f);
+    v[m] = in ? cmul(ov[m], pvv[m]) : make_float2(0.f, 0.f);
   }
   Plan1D<N>::template run<+1>(v, t, lds + line * RowLds<N>::kStride, [](int n) { return RowLds<N>::at(n); }, lds_tw);
   if (active) {
@@ -354,19 +364,24 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
     const size_t orow = (size_t)(w.x + ky) * bt.M + w.y;
     const float2* prow = P + (size_t)ky * N;
     float2 v[E], pv[E], cv[kNeedC ? E : 1];
+    float kap[MODE == kPatchZern ? E : 1];
 #pragma unroll
-    for (int m = 0; m < E; ++m) v[m] = active ? xr[t + m * T] : make_float2(0.f, 0.f);
-    // the pupil and the cropped spectrum at this thread's output columns, fetched early
+    for (int m = 0; m < E; ++m) v[m] = xr[t + m * T];   // rows past the disk are never used
+    // the pupil, the cropped spectrum and kappa at this thread's output columns,
+    // fetched before the transform at addresses clamped into the disk
+    const int uy = ky - N / 2;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
-      const int kx = half_shift<N>(t + m * T);
-      const bool in = active && kx >= ext.x && kx <= ext.y;
-      pv[m] = in ? prow[kx] : make_float2(0.f, 0.f);
-      if constexpr (kNeedC) cv[m] = in ? O[orow + kx] : make_float2(0.f, 0.f);
+      const int kx = min(max(half_shift<N>(t + m * T), ext.x), ext.y);
+      pv[m] = prow[kx];
+      if constexpr (kNeedC) cv[m] = O[orow + kx];
+      if constexpr (MODE == kPatchZern) {
+        const int ux = kx - N / 2;
+        kap[m] = kappa_tab[ux * ux + uy * uy];
+      }
     }
     Plan1D<N>::template run<-1>(v, t, lds + line * RowLds<N>::kStride, [](int n) { return RowLds<N>::at(n); }, lds_tw);
     if (active) {
-      const int uy = ky - N / 2;
       const float ir = (float)pg.inv_r;
       // row moments S_a = sum g_theta x^a (a <= 4) and sum g_theta kappa
       float S0 = 0.f, S1 = 0.f, S2 = 0.f, S3 = 0.f, S4 = 0.f, SK = 0.f;
@@ -394,7 +409,7 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
             S2 += gx2;
             S3 += gx3;
             S4 += gx3 * xx;
-            SK += gth * kappa_tab[ux * ux + uy * uy];
+            SK += gth * kap[m];
           }
         }
       }

@@ -128,18 +128,20 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
                          tile_c0 + 31 < wc + a.dk.ky_lo || tile_c0 > wc + a.dk.ky_hi);
     if (meets) hit |= 1ull << b;
   }
+  constexpr int kRound = 4;
   while (hit) {
-    // two slots per round: all loads issued (at addresses clamped into the disk)
-    // before the masked, in-order accumulation
-    int bs[2];
-    bs[0] = __ffsll((long long)hit) - 1;
-    hit &= hit - 1;
-    bs[1] = hit ? __ffsll((long long)hit) - 1 : -1;
-    if (hit) hit &= hit - 1;
-    float2 val[2][4];
-    bool ok[2][4];
+    // kRound slots per round: all loads issued (at addresses clamped into the
+    // disk) before the masked, in-order accumulation
+    int bs[kRound];
 #pragma unroll
-    for (int u = 0; u < 2; ++u) {
+    for (int u = 0; u < kRound; ++u) {
+      bs[u] = hit ? __ffsll((long long)hit) - 1 : -1;
+      if (hit) hit &= hit - 1;
+    }
+    float2 val[kRound][4];
+    bool ok[kRound][4];
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) {
       const int b = bs[u] < 0 ? bs[0] : bs[u];
       const int wr = a.bt.win[b].x, wc = a.bt.win[b].y;
       const int ky = r - wr;
@@ -154,7 +156,7 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
       }
     }
 #pragma unroll
-    for (int u = 0; u < 2; ++u)
+    for (int u = 0; u < kRound; ++u)
 #pragma unroll
       for (int q = 0; q < 4; ++q)
         if (ok[u][q]) {
@@ -166,28 +168,38 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
 
 template <int N>
 __global__ void __launch_bounds__(256) update(UpdateArgs a) {
+  FPM_PROBE(3, 0);
   const int n_pw = a.pupil ? (N * N + kPupilPerWg - 1) / kPupilPerWg : 1;
   if ((int)blockIdx.x >= n_pw) {
     const int2 tl = a.tiles[blockIdx.x - n_pw];
     const int r = tl.x * 32 + (threadIdx.x >> 3);
     const int col = tl.y * 32 + (threadIdx.x & 7) * 4;         // complex column
     const size_t f = ((size_t)r * a.M + col) * 2;                // float offset
+    float4* po = reinterpret_cast<float4*>(a.O + f);
+    float4* pm = reinterpret_cast<float4*>(a.mO + f);
+    float4* pv = reinterpret_cast<float4*>(a.vO + f);
+    float4 o[2], m[2], v[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {   // in flight while the gradient is gathered
+      o[h] = po[h];
+      m[h] = pm[h];
+      v[h] = pv[h];
+    }
     float2 g[4];
     gather_gradient<N>(a, r, col, tl.x * 32, tl.y * 32, g);
+    FPM_PROBE(3, 1);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
-      float4* po = reinterpret_cast<float4*>(a.O + f) + h;
-      float4* pm = reinterpret_cast<float4*>(a.mO + f) + h;
-      float4* pv = reinterpret_cast<float4*>(a.vO + f) + h;
-      float4 o = *po, m = *pm, v = *pv;
-      adam1(o.x, m.x, v.x, g[2 * h].x, a.c);
-      adam1(o.y, m.y, v.y, g[2 * h].y, a.c);
-      adam1(o.z, m.z, v.z, g[2 * h + 1].x, a.c);
-      adam1(o.w, m.w, v.w, g[2 * h + 1].y, a.c);
-      *po = o;
-      *pm = m;
-      *pv = v;
+      adam1(o[h].x, m[h].x, v[h].x, g[2 * h].x, a.c);
+      adam1(o[h].y, m[h].y, v[h].y, g[2 * h].y, a.c);
+      adam1(o[h].z, m[h].z, v[h].z, g[2 * h + 1].x, a.c);
+      adam1(o[h].w, m[h].w, v[h].w, g[2 * h + 1].y, a.c);
+      po[h] = o[h];
+      pm[h] = m[h];
+      pv[h] = v[h];
     }
+    FPM_PROBE(3, 2);
+    FPM_PROBE(3, 3);
     return;
   }
   const int pw = blockIdx.x;
@@ -199,13 +211,14 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     // (independent loads in flight, then a fixed summation order)
     const int j = threadIdx.x & (kPar - 1);
     double sj = 0.0;
-    constexpr int kStride = 256 / kPar, kUnroll = 8;
+    constexpr int kStride = 256 / kPar, kUnroll = 24;
     for (int i0 = threadIdx.x / kPar; i0 < a.n_zpart; i0 += kStride * kUnroll) {
       double vals[kUnroll];
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) {
         const int i = i0 + u * kStride;
-        vals[u] = i < a.n_zpart ? a.zpart[(size_t)i * kPar + j] : 0.0;
+        vals[u] = a.zpart[(size_t)min(i, a.n_zpart - 1) * kPar + j];
+        if (i >= a.n_zpart) vals[u] = 0.0;
       }
 #pragma unroll
       for (int u = 0; u < kUnroll; ++u) sj += vals[u];
@@ -251,6 +264,7 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     __syncthreads();
     if (pw == 0 && threadIdx.x < kScal) a.staging[threadIdx.x] = next[threadIdx.x];
     if (pw == 0 && threadIdx.x < kPar && a.g_par) a.g_par[threadIdx.x] += red[threadIdx.x];
+    FPM_PROBE(3, 1);
     // rebuild this workgroup's share of the pupil from the new parameters (FP64)
     const int end = min((pw + 1) * kPupilPerWg, N * N);
     for (int idx = pw * kPupilPerWg + threadIdx.x; idx < end; idx += 256) {
@@ -269,6 +283,7 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
       a.P[idx] = make_float2((float)cs, (float)sn);
     }
   }
+  FPM_PROBE(3, 2);
   if (pw == 0 && a.loss && threadIdx.x < 64) {
     double s = 0.0;
     for (int i = threadIdx.x; i < a.n_loss; i += 64) s += a.loss_part[i];
@@ -276,6 +291,7 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (threadIdx.x == 0) *a.loss += s;
   }
+  FPM_PROBE(3, 3);
 }
 
 // ---------------------------------------------------------------------------

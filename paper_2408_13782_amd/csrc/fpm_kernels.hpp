@@ -32,6 +32,11 @@
 #include "fft_line.hpp"
 #include "fpm_optics.hpp"
 
+// Timeline probes for development builds (they compile to nothing here).
+#ifndef FPM_PROBE
+#define FPM_PROBE(kernel, point)
+#endif
+
 namespace fpm {
 
 constexpr int kRowThreads = 128;   // threads per workgroup in the row passes
@@ -103,8 +108,34 @@ struct Reduction {
   unsigned* counter;
 };
 
+// Data-parallel-primitive (DPP) lane moves of a double, out-of-row lanes read 0.
+template <int kCtrl>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), kCtrl, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), kCtrl, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum of v over the 64 lanes of the wave, the same value in every lane: an
+// in-row prefix sum with row_shr 1, 2, 4, 8 (lane 15 of each row of 16 then
+// holds the row's total), then the four row totals added in order.
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0x111>(v);
+  v += dpp_move<0x112>(v);
+  v += dpp_move<0x114>(v);
+  v += dpp_move<0x118>(v);
+  return ((read_lane(v, 15) + read_lane(v, 31)) + read_lane(v, 47)) + read_lane(v, 63);
+}
+
 // Sum K per-thread values over the workgroup; thread k < K stores total k into
-// part[blockIdx.x * K + k]. No ordering with other workgroups is implied.
+// part[blockIdx.x * K + k]. Fixed summation order. No ordering with other
+// workgroups is implied.
 template <int K, class V>
 __device__ __forceinline__ void block_partials(const V* vals, double* part) {
   __shared__ double wsum[16][K];
@@ -112,9 +143,7 @@ __device__ __forceinline__ void block_partials(const V* vals, double* part) {
   const int nwaves = (blockDim.x + 63) >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
-    double v = vals[k];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    const double v = wave_sum((double)vals[k]);
     if (lane == 0) wsum[wave][k] = v;
   }
   __syncthreads();
@@ -216,6 +245,7 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch b
   constexpr int L = kRowThreads / T;
   __shared__ float2 lds[L * RowLds<N>::kStride];
   __shared__ float2 lds_tw[N];
+  FPM_PROBE(0, 0);
   if (commit && blockIdx.x == 0) commit_scalars(staging, scal, threadIdx.x);
   int b, c;
   if (!xcd_map(blockIdx.x, chunks, bt.B, b, c)) return;
@@ -246,12 +276,15 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch b
     const bool in = active && kx >= ext.x && kx <= ext.y;
     v[m] = in ? cmul(ov[m], pvv[m]) : make_float2(0.f, 0.f);
   }
+  FPM_PROBE(0, 1);
   Plan1D<N>::template run<+1>(v, t, lds + line * RowLds<N>::kStride, [](int n) { return RowLds<N>::at(n); }, lds_tw);
+  FPM_PROBE(0, 2);
   if (active) {
     float2* xr = X + ((size_t)b * N + ky) * N;
 #pragma unroll
     for (int m = 0; m < E; ++m) xr[t + m * T] = v[m];
   }
+  FPM_PROBE(0, 3);
 }
 
 // Column pass: inverse DFT along k_y, amplitude loss, residual, forward DFT.
@@ -267,6 +300,7 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
   constexpr int L = ColLines<N>::value;
   __shared__ float2 lds[N * (L + 1)];
   __shared__ float2 lds_tw[N];
+  if (!kForward) FPM_PROBE(1, 0);
   int b, g;
   const bool live = xcd_map(blockIdx.x, groups, bt.B, b, g);
   if (live) stage_twiddles<N>(lds_tw, tw);
@@ -291,6 +325,7 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
     }
     const float sg = gamma ? sqrtf(gamma[led]) : 1.0f;
     auto lay = [line](int n) { return n * (L + 1) + line; };
+    if (!kForward) FPM_PROBE(1, 1);
     Plan1D<N>::template run<+1>(v, t, lds, lay, lds_tw);
     if constexpr (kForward) {
 #pragma unroll
@@ -312,6 +347,7 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
         v[m] = cscale(psi, f);
       }
       Plan1D<N>::template run<-1>(v, t, lds, lay, lds_tw);
+      FPM_PROBE(1, 2);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int ky = half_shift<N>(t + m * T);
@@ -321,6 +357,7 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
   }
   if constexpr (!kForward) {
     if (loss_part) block_partials<1>(&acc, loss_part);
+    FPM_PROBE(1, 3);
   }
 }
 
@@ -346,6 +383,7 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
   constexpr bool kNeedC = MODE == kGradOP || MODE == kPatchZern;
   __shared__ float2 lds[L * RowLds<N>::kStride];
   __shared__ float2 lds_tw[N];
+  FPM_PROBE(2, 0);
   int b, c;
   const bool live = xcd_map(blockIdx.x, chunks, bt.B, b, c);
   if (live) stage_twiddles<N>(lds_tw, tw);
@@ -380,7 +418,9 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
         kap[m] = kappa_tab[ux * ux + uy * uy];
       }
     }
+    FPM_PROBE(2, 1);
     Plan1D<N>::template run<-1>(v, t, lds + line * RowLds<N>::kStride, [](int n) { return RowLds<N>::at(n); }, lds_tw);
+    FPM_PROBE(2, 2);
     if (active) {
       const float ir = (float)pg.inv_r;
       // row moments S_a = sum g_theta x^a (a <= 4) and sum g_theta kappa
@@ -425,6 +465,7 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
     }
   }
   if constexpr (MODE == kPatchZern) block_partials<kPar>(zacc, zpart);
+  FPM_PROBE(2, 3);
 }
 
 }  // namespace fpm

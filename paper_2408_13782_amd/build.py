@@ -23,6 +23,9 @@ HEADERS = ["fft_line.hpp", "fpm_kernels.hpp", "fpm_aux.hpp"]
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",
+    # gfx950 preloads the first kernel arguments into SGPRs: one scalar-load
+    # round trip less at the start of every kernel
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-command-line-argument",
 ]

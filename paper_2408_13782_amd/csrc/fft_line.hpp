@@ -294,49 +294,37 @@ __device__ __forceinline__ void stage_twiddles(float2* __restrict__ lds_tw,
   for (int i = threadIdx.x; i < N; i += blockDim.x) lds_tw[i] = tw[i];
 }
 
-// Radix plans: thread count T per line and stage radices for each size.
-template <int N> struct Plan1D;
-template <> struct Plan1D<64> {
-  static constexpr int T = 8;
-  template <int DIR, class Lay>
-  __device__ __forceinline__ static void run(float2 (&v)[64 / T], int t, float2* lds, Lay lay, const float2* tw) {
-    Stages<64, T, DIR, 1, 8, 8>::run(v, t, lds, lay, tw);
-  }
-};
-template <> struct Plan1D<128> {
-  static constexpr int T = 8;
-  template <int DIR, class Lay>
-  __device__ __forceinline__ static void run(float2 (&v)[128 / T], int t, float2* lds, Lay lay, const float2* tw) {
-    Stages<128, T, DIR, 1, 16, 8>::run(v, t, lds, lay, tw);
-  }
-};
-template <> struct Plan1D<256> {
-  static constexpr int T = 16;
-  template <int DIR, class Lay>
-  __device__ __forceinline__ static void run(float2 (&v)[256 / T], int t, float2* lds, Lay lay, const float2* tw) {
-    Stages<256, T, DIR, 1, 16, 16>::run(v, t, lds, lay, tw);
-  }
-};
-template <> struct Plan1D<512> {
-  static constexpr int T = 64;
-  template <int DIR, class Lay>
-  __device__ __forceinline__ static void run(float2 (&v)[512 / T], int t, float2* lds, Lay lay, const float2* tw) {
-    Stages<512, T, DIR, 1, 8, 8, 8>::run(v, t, lds, lay, tw);
-  }
-};
-template <> struct Plan1D<1024> {
-  static constexpr int T = 64;
-  template <int DIR, class Lay>
-  __device__ __forceinline__ static void run(float2 (&v)[1024 / T], int t, float2* lds, Lay lay, const float2* tw) {
-    Stages<1024, T, DIR, 1, 16, 8, 8>::run(v, t, lds, lay, tw);
-  }
-};
-template <> struct Plan1D<2048> {
-  static constexpr int T = 128;
-  template <int DIR, class Lay>
-  __device__ __forceinline__ static void run(float2 (&v)[2048 / T], int t, float2* lds, Lay lay, const float2* tw) {
-    Stages<2048, T, DIR, 1, 16, 16, 8>::run(v, t, lds, lay, tw);
-  }
-};
+// Radix plans: stage radices for a transform of length N done by T threads.
+template <int N, int T> struct PlanT;
+
+#define FPM_PLAN(N_, T_, ...)                                                            \
+  template <> struct PlanT<N_, T_> {                                                     \
+    static constexpr int T = T_;                                                         \
+    template <int DIR, class Lay>                                                        \
+    __device__ __forceinline__ static void run(float2 (&v)[N_ / T_], int t, float2* lds, \
+                                               Lay lay, const float2* tw) {              \
+      Stages<N_, T_, DIR, 1, __VA_ARGS__>::run(v, t, lds, lay, tw);                      \
+    }                                                                                    \
+  };
+
+FPM_PLAN(64, 4, 16, 4)
+FPM_PLAN(64, 8, 8, 8)
+FPM_PLAN(64, 16, 4, 4, 4)
+FPM_PLAN(128, 8, 16, 8)
+FPM_PLAN(128, 16, 8, 4, 4)
+FPM_PLAN(128, 32, 4, 4, 4, 2)
+FPM_PLAN(256, 16, 16, 16)
+FPM_PLAN(256, 32, 8, 8, 4)
+FPM_PLAN(256, 64, 4, 4, 4, 4)
+FPM_PLAN(512, 32, 16, 16, 2)
+FPM_PLAN(512, 64, 8, 8, 8)
+FPM_PLAN(512, 128, 4, 4, 4, 4, 2)
+FPM_PLAN(1024, 64, 16, 8, 8)
+FPM_PLAN(2048, 128, 16, 16, 8)
+#undef FPM_PLAN
+
+// Default threads per line: 16 elements per thread where the radices allow.
+template <int N> struct DefaultT { static constexpr int value = N <= 128 ? 8 : N == 256 ? 16 : N == 512 ? 64 : N / 16; };
+template <int N> using Plan1D = PlanT<N, DefaultT<N>::value>;
 
 }  // namespace fpm

@@ -251,7 +251,7 @@ int launch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t
   }
   {
     Timed tm(p, kCols, st);
-    cols<N, false><<<gr.cols(), ColLines<N>::value * Plan1D<N>::T, 0, st>>>(
+    cols<N, false><<<gr.cols(), ColLines<N>::value * ColPlan<N>::T, 0, st>>>(
         p->X, A, gamma, bt, dk, gr.col_groups, o.loss ? p->part_loss : nullptr, nullptr, nullptr,
         p->twN, 1.0f / p->M);
   }
@@ -295,7 +295,7 @@ int launch_forward(fpm_plan* p, const float2* O, const float2* P, const int32_t*
   }
   {
     Timed tm(p, kCols, st);
-    cols<N, true><<<gr.cols(), ColLines<N>::value * Plan1D<N>::T, 0, st>>>(
+    cols<N, true><<<gr.cols(), ColLines<N>::value * ColPlan<N>::T, 0, st>>>(
         p->X, nullptr, gamma, bt, dk, gr.col_groups, nullptr, amp, field, p->twN, 1.0f / p->M);
   }
   FPM_HIP(hipGetLastError());

@@ -128,7 +128,10 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
                          tile_c0 + 31 < wc + a.dk.ky_lo || tile_c0 > wc + a.dk.ky_hi);
     if (meets) hit |= 1ull << b;
   }
-  constexpr int kRound = 4;
+#ifndef FPM_GATHER_ROUND
+#define FPM_GATHER_ROUND 4
+#endif
+  constexpr int kRound = FPM_GATHER_ROUND;
   while (hit) {
     // kRound slots per round: all loads issued (at addresses clamped into the
     // disk) before the masked, in-order accumulation

@@ -45,6 +45,20 @@ constexpr int kXcds = 8;
 template <int N> struct ColLines { static constexpr int value = 16; };
 template <> struct ColLines<512> { static constexpr int value = 8; };
 
+// Threads per column transform in the column pass (more threads per column
+// than the row passes: with B = 16 the pass has about one wave per SIMD at 16
+// elements per thread, and more waves hide the LDS and dependency latency).
+#ifndef FPM_COL_T256
+#define FPM_COL_T256 32
+#endif
+template <int N> struct ColT { static constexpr int value = DefaultT<N>::value; };
+template <> struct ColT<256> { static constexpr int value = FPM_COL_T256; };
+template <int N> using ColPlan = PlanT<N, ColT<N>::value>;
+// LDS slots between consecutive elements of one column (padding by radix).
+template <int N> struct ColStride {
+  static constexpr int value = ColLines<N>::value + (N / ColT<N>::value >= 16 ? 1 : 2);
+};
+
 // (n + N/2) mod N: the index shift between centred and DFT order.
 template <int N>
 __device__ __forceinline__ int half_shift(int n) {
@@ -290,15 +304,15 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch b
 // Column pass: inverse DFT along k_y, amplitude loss, residual, forward DFT.
 // kForward: write amplitudes (and fields) instead of the residual transform.
 template <int N, bool kForward>
-__global__ void __launch_bounds__(ColLines<N>::value * Plan1D<N>::T)
+__global__ void __launch_bounds__(ColLines<N>::value * ColPlan<N>::T)
 cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restrict__ gamma,
      Batch bt, Disk dk, int groups, double* __restrict__ loss_part,
      float* __restrict__ amp_out, float2* __restrict__ field_out, const float2* __restrict__ tw,
      float inv_m) {
-  constexpr int T = Plan1D<N>::T;
+  constexpr int T = ColPlan<N>::T;
   constexpr int E = N / T;
   constexpr int L = ColLines<N>::value;
-  __shared__ float2 lds[N * (L + 1)];
+  __shared__ float2 lds[N * ColStride<N>::value];
   __shared__ float2 lds_tw[N];
   if (!kForward) FPM_PROBE(1, 0);
   int b, g;
@@ -324,9 +338,9 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
       for (int m = 0; m < E; ++m) a_meas[m] = ab[(size_t)(t + m * T) * N + x];   // prefetch
     }
     const float sg = gamma ? sqrtf(gamma[led]) : 1.0f;
-    auto lay = [line](int n) { return n * (L + 1) + line; };
+    auto lay = [line](int n) { return n * ColStride<N>::value + line; };
     if (!kForward) FPM_PROBE(1, 1);
-    Plan1D<N>::template run<+1>(v, t, lds, lay, lds_tw);
+    ColPlan<N>::template run<+1>(v, t, lds, lay, lds_tw);
     if constexpr (kForward) {
 #pragma unroll
       for (int m = 0; m < E; ++m) {
@@ -346,7 +360,7 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
         const float f = a > 0.f ? 2.f * sg * e / a : 0.f;
         v[m] = cscale(psi, f);
       }
-      Plan1D<N>::template run<-1>(v, t, lds, lay, lds_tw);
+      ColPlan<N>::template run<-1>(v, t, lds, lay, lds_tw);
       FPM_PROBE(1, 2);
 #pragma unroll
       for (int m = 0; m < E; ++m) {

@@ -20,8 +20,7 @@ notation of the paper:
 * Adam-family optimiser .......................... Sec. 2.2 (optimisers named)
 * digital refocusing of a reconstruction ......... Abstract, Sec. 3.3, Sec. 4
 
-Readings taken where the paper is silent or garbled (each one is listed in
-the design notes with its reason):
+Readings taken where the paper is silent or garbled:
 
 * the learned tensor is the centred HR spectrum with orthonormal scaling,
   O = fftshift(fft2(o)) / M, so sum|O|^2 = sum|o|^2;
@@ -363,6 +362,158 @@ def pupil_param_grads(g_P, P, zern, kappa):
     g_c = np.tensordot(zern, g_theta, axes=([1, 2], [0, 1]))
     g_z = float(np.sum(g_theta * kappa))
     return g_c, g_z, g_theta
+
+
+# ---------------------------------------------------------------------------
+# Sub-pixel LED offsets and the LED-array geometry (Sec. 2.1 k_m; Sec. 2.2:
+# LED position errors corrected jointly with the other system parameters)
+# ---------------------------------------------------------------------------
+
+
+def crop_bilinear(O: np.ndarray, n: int, shift):
+    """Spectrum sampled at the fractional window (M/2 - N/2) + s + u, bilinearly.
+
+    Returns (C, taps, frac, rows0, cols0): C[u], the four neighbour arrays
+    O[f + u + t] for t in (0,0) (0,1) (1,0) (1,1), the fractional part a of the
+    window corner f + a, and the integer row/column indices of tap (0,0).
+    Indices wrap modulo M.
+    """
+    m = O.shape[0]
+    w = (m // 2 - n // 2) + np.asarray(shift, dtype=np.float64)
+    f = np.floor(w).astype(np.int64)
+    a = w - f
+    r0 = (f[0] + np.arange(n)) % m
+    r1 = (r0 + 1) % m
+    c0 = (f[1] + np.arange(n)) % m
+    c1 = (c0 + 1) % m
+    t00, t01 = O[np.ix_(r0, c0)], O[np.ix_(r0, c1)]
+    t10, t11 = O[np.ix_(r1, c0)], O[np.ix_(r1, c1)]
+    C = ((1 - a[0]) * (1 - a[1]) * t00 + (1 - a[0]) * a[1] * t01
+         + a[0] * (1 - a[1]) * t10 + a[0] * a[1] * t11)
+    return C, (t00, t01, t10, t11), a, r0, c0
+
+
+def scatter_bilinear(g_O, g_C, a, r0, c0):
+    """Adjoint of crop_bilinear: g_O[f + u + t] += w_t g_C[u] for the four taps t."""
+    m = g_O.shape[0]
+    r1, c1 = (r0 + 1) % m, (c0 + 1) % m
+    for rows, cols, wgt in ((r0, c0, (1 - a[0]) * (1 - a[1])), (r0, c1, (1 - a[0]) * a[1]),
+                            (r1, c0, a[0] * (1 - a[1])), (r1, c1, a[0] * a[1])):
+        np.add.at(g_O, np.ix_(rows, cols), wgt * g_C)
+
+
+@dataclass
+class GeneralGrads:
+    loss: float
+    g_O: np.ndarray
+    g_P: np.ndarray
+    g_gamma: np.ndarray      # per batch position
+    g_shift: np.ndarray      # [B, 2] dL/ds_b (row, col)
+
+
+def loss_and_grads_subpixel(O, P, shifts, leds, meas_amp, gamma=None) -> GeneralGrads:
+    """Loss and gradients with fractional LED offsets (bilinear crop).
+
+    Same loss as loss_and_grads; with integer offsets the two agree. Also the
+    gradient with respect to each LED's offset: dL/ds = sum_u Re(conj(g_C) dC/ds),
+    a one-sided derivative where the offset crosses an integer.
+    """
+    n = P.shape[0]
+    m = O.shape[0]
+    g_O = np.zeros_like(O, dtype=np.complex128)
+    g_P = np.zeros((n, n), dtype=np.complex128)
+    g_gamma = np.zeros(len(leds))
+    g_shift = np.zeros((len(leds), 2))
+    total = 0.0
+    for b, led in enumerate(leds):
+        C, (t00, t01, t10, t11), a, r0, c0 = crop_bilinear(O, n, shifts[led])
+        psi = (n * n / m) * np.fft.ifft2(np.fft.ifftshift(C * P))
+        amp = np.abs(psi)
+        sg = 1.0 if gamma is None else math.sqrt(float(gamma[led]))
+        e = sg * amp - np.asarray(meas_amp[led], dtype=np.float64)
+        total += float(np.sum(e * e))
+        unit = np.zeros_like(psi)
+        nz = amp > 0
+        unit[nz] = psi[nz] / amp[nz]
+        g_psi = 2.0 * sg * e * unit
+        g_C, g_Pb = field_adjoint(g_psi, P, C, m)
+        scatter_bilinear(g_O, g_C, a, r0, c0)
+        g_P += g_Pb
+        g_gamma[b] = float(np.sum(e * amp)) / sg
+        dC_dy = (1 - a[1]) * (t10 - t00) + a[1] * (t11 - t01)
+        dC_dx = (1 - a[0]) * (t01 - t00) + a[0] * (t11 - t10)
+        g_shift[b, 0] = float(np.sum(np.real(np.conj(g_C) * dC_dy)))
+        g_shift[b, 1] = float(np.sum(np.real(np.conj(g_C) * dC_dx)))
+    return GeneralGrads(total, g_O, g_P, g_gamma, g_shift)
+
+
+GEOMETRY_NAMES = ("shift_x_mm", "shift_y_mm", "rot_rad", "dh_mm")
+
+
+def led_shifts_and_jacobian(optics: Optics, n_side: int, pitch_mm: float, height_mm: float,
+                            geom=(0.0, 0.0, 0.0, 0.0), roi_x_mm: float = 0.0,
+                            roi_y_mm: float = 0.0):
+    """Fractional offsets s [n_led, 2] (row, col) and ds/d(geom) [n_led, 2, 4].
+
+    geom = (shift_x_mm, shift_y_mm, rot_rad, dh_mm). With D the LED-to-sample
+    distance, k = (dy, dx) / (lambda D) and s = k / dk, differentiated by hand:
+    dk_x/dx = (D^2 - dx^2)/(lambda D^3), dk_x/dy = -dx dy/(lambda D^3),
+    dk_x/dH = -dx H/(lambda D^3) (and symmetrically), while a rotation moves the
+    LED by (dx, dy) -> (-y', x') with (x', y') its rotated grid offset.
+    """
+    dx_mm, dy_mm, rot, dh = (float(g) for g in geom)
+    x, y, h = led_positions(n_side, pitch_mm, height_mm, dx_mm, dy_mm, rot, dh)
+    X = x - roi_x_mm
+    Y = y - roi_y_mm
+    D = np.sqrt(X * X + Y * Y + h * h)
+    lam = optics.wavelength_um
+    s = np.stack([Y / D / lam, X / D / lam], 1) / optics.dk
+    D3 = lam * D ** 3
+    dkx = np.stack([(D * D - X * X) / D3, -X * Y / D3, -X * h / D3], 1)   # d/d(X, Y, H)
+    dky = np.stack([-X * Y / D3, (D * D - Y * Y) / D3, -Y * h / D3], 1)
+    # d(X, Y, H) / d(shift_x, shift_y, rot, dh)
+    xr = x - dx_mm      # rotated grid offsets before the lateral shift
+    yr = y - dy_mm
+    dXYH = np.zeros((x.size, 3, 4))
+    dXYH[:, 0, 0] = 1.0
+    dXYH[:, 1, 1] = 1.0
+    dXYH[:, 0, 2] = -yr
+    dXYH[:, 1, 2] = xr
+    dXYH[:, 2, 3] = 1.0
+    J = np.empty((x.size, 2, 4))
+    J[:, 0, :] = np.einsum("nk,nkp->np", dky, dXYH) / optics.dk
+    J[:, 1, :] = np.einsum("nk,nkp->np", dkx, dXYH) / optics.dk
+    return s, J
+
+
+@dataclass
+class MultiGrads:
+    loss: float
+    g_O: np.ndarray
+    g_coeffs: np.ndarray
+    g_z: float
+    g_geom: np.ndarray       # [4]
+    g_gamma: np.ndarray      # [n_led] (zero for LEDs outside the batch)
+
+
+def multiparam_loss_and_grads(O, coeffs, z_um, geom, gamma, leds, meas_amp, optics: Optics,
+                              n_side, pitch_mm, height_mm, mask, zern, kappa) -> MultiGrads:
+    """Loss of one batch as a function of every learned group (Sec. 2.2, Eq. 3).
+
+    Object spectrum, pupil Zernike coefficients and defocus, LED-array geometry
+    (lateral shift, rotation, height) and LED intensities; gradients by the
+    chain rule through the sub-pixel crop.
+    """
+    P = pupil(mask, zern, coeffs, z_um, kappa)
+    s, J = led_shifts_and_jacobian(optics, n_side, pitch_mm, height_mm, geom)
+    gr = loss_and_grads_subpixel(O, P, s, leds, meas_amp, gamma)
+    g_c, g_z, _ = pupil_param_grads(gr.g_P, P, zern, kappa)
+    g_geom = np.zeros(4)
+    g_gamma = np.zeros(len(s))
+    for b, led in enumerate(leds):
+        g_geom += J[led].T @ gr.g_shift[b]
+        g_gamma[led] += gr.g_gamma[b]
+    return MultiGrads(gr.loss, gr.g_O, g_c, g_z, g_geom, g_gamma)
 
 
 # ---------------------------------------------------------------------------

@@ -19,7 +19,8 @@ LIB = os.path.join(PKG, "libfpm.so")
 SOURCES = ["fpm_api.hip"]
 HEADERS = ["fft_line.hpp", "fpm_kernels.hpp", "fpm_aux.hpp"]
 
-# Packed FP32 instructions are disabled on purpose (see the design notes).
+# Packed FP32 instructions are disabled on purpose (some of their forms have given
+# unreliable results on this target).
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-munsafe-fp-atomics",

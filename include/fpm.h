@@ -226,6 +226,43 @@ int fpm_run(fpm_plan* plan, fpm_state* state, const fpm_hparams* hp, const int32
             const int32_t* batch_sizes, int32_t n_steps, const float* gamma,
             const float* meas_amp, void* stream);
 
+/* Learned parameters of the multi-parameter model (device memory). */
+typedef struct {
+  const fpm_c32* O;        /* [M][M] spectrum (required) */
+  const float* coeffs;     /* [15] Zernike coefficients, or NULL (zero) */
+  const float* z_um;       /* [1] defocus, or NULL (zero) */
+  const double* geom;      /* [4] LED-array errors added to grid's: shift_x_mm,
+                              shift_y_mm, rot_rad, dh_mm; NULL: the plan's integer
+                              LED table (no geometry gradient) */
+  const float* gamma;      /* [n_led] LED intensity factors, or NULL (ones) */
+} fpm_params;
+
+/* Gradient accumulators (device memory, +=); each may be NULL. */
+typedef struct {
+  fpm_c32* g_O;            /* [M][M] */
+  double* g_par;           /* [16]: coeffs[0..14], z */
+  double* g_geom;          /* [4] */
+  double* g_gamma;         /* [n_led] */
+  double* loss;            /* [1] */
+  int32_t* oob;            /* [1] += number of windows that left the HR grid */
+} fpm_grads;
+
+/*
+ * Loss and gradients of one batch for every parameter group (Sec. 2.1
+ * Eq. 3, Sec. 2.2): spectrum, pupil Zernike coefficients and defocus, the
+ * LED-array geometry and the LED intensities. LED offsets are fractional,
+ * s_b = k_b(geometry)/dk computed in FP64 on the device from `grid` (HOST
+ * struct: the nominal array) plus params->geom; the crop samples the spectrum
+ * bilinearly at the fractional window (the loss is piecewise smooth in s_b;
+ * the offset gradient is the one-sided derivative where s_b crosses an
+ * integer). A window that would leave the HR grid is clamped and counted in
+ * grads->oob. All sums are in a fixed order (deterministic). Requires
+ * grid->n_side^2 == n_led.
+ */
+int fpm_loss_grad(fpm_plan* plan, const fpm_led_grid* grid, const fpm_params* params,
+                  const int32_t* leds, int32_t B, const float* meas_amp, fpm_grads* grads,
+                  void* stream);
+
 /*
  * HR object <-> spectrum (Sec. 2.1, Eq. 1) with the orthonormal scaling:
  *   direction +1: O = fftshift(fft2(o)) / M;   direction -1: o = ifft2(ifftshift(O)) * M.

@@ -11,6 +11,7 @@
 #include "fpm.h"
 #include "fpm_aux.hpp"
 #include "fpm_kernels.hpp"
+#include "fpm_subpixel.hpp"
 
 using namespace fpm;
 
@@ -92,6 +93,10 @@ struct fpm_plan {
   double* part_z = nullptr;
   double* part_pg = nullptr;
   float* staging = nullptr;   // next pupil-parameter state, written by the update kernel
+  double* part_lg = nullptr;  // partials of fpm_loss_grad (column pass | row pass)
+  SubSlot* sub = nullptr;     // [max_batch] sub-pixel offsets of fpm_loss_grad
+  float2* P_ws = nullptr;     // [N][N] pupil built by fpm_loss_grad
+  int* oob_ws = nullptr;      // window-clamp counter when the caller passes none
   unsigned* counters = nullptr;  // completion counter of pupil_grad's reduction
   bool timing = false;
   std::vector<TimedLaunch> timed;
@@ -150,6 +155,10 @@ void plan_free(fpm_plan* p) {
   (void)hipFree(p->tiles);
   (void)hipFree(p->part);
   (void)hipFree(p->staging);
+  (void)hipFree(p->part_lg);
+  (void)hipFree(p->sub);
+  (void)hipFree(p->P_ws);
+  (void)hipFree(p->oob_ws);
   (void)hipFree(p->counters);
   delete p;
 }
@@ -344,6 +353,78 @@ int cols_grid_of(const fpm_plan* p, int B) {
 
 int pupil_wgs(const fpm_plan* p) { return (p->N * p->N + kPupilPerWg - 1) / kPupilPerWg; }
 
+template <int N>
+int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr,
+                     const int32_t* leds, int B, const float* A, fpm_grads* gr, hipStream_t st) {
+  const Grids g = grids_of<N>(p, B);
+  const Batch bt = batch_of(p, leds, B);
+  const Disk dk = disk_of(p);
+  const PupilGeom pg = pupil_geom(p);
+  {
+    Timed tm(p, kPupilBuild, st);
+    pupil_build<<<(p->N * p->N + 255) / 256, 256, 0, st>>>(pg, p->rowext, pr->coeffs,
+                                                             pr->coeffs ? kZern : 0, pr->z_um,
+                                                             p->P_ws);
+  }
+  GeomArgs ga;
+  ga.n_side = grid->n_side;
+  ga.pitch_mm = grid->pitch_mm;
+  ga.height_mm = grid->height_mm;
+  ga.roi_x_mm = grid->roi_x_mm;
+  ga.roi_y_mm = grid->roi_y_mm;
+  ga.base_dx = grid->shift_x_mm;
+  ga.base_dy = grid->shift_y_mm;
+  ga.base_rot = grid->rot_rad;
+  ga.base_dh = grid->dh_mm;
+  ga.inv_dk = 1.0 / p->dk;
+  ga.lambda = p->lambda;
+  ga.N = p->N;
+  ga.M = p->M;
+  led_subpixel<<<1, kMaxSlots, 0, st>>>(ga, pr->geom, bt, p->sub, gr->oob ? gr->oob : p->oob_ws);
+  const float2* O = reinterpret_cast<const float2*>(pr->O);
+  double* col_part = p->part_lg;
+  double* row_part = p->part_lg + (size_t)g.cols() * 2;
+  {
+    Timed tm(p, kRowsForward, st);
+    rows_forward_sub<N><<<g.rows(), kRowThreads, 0, st>>>(O, p->P_ws, bt, dk, p->sub,
+                                                          g.row_chunks, p->X, p->twN);
+  }
+  {
+    Timed tm(p, kCols, st);
+    cols<N, false, true><<<g.cols(), ColLines<N>::value * ColPlan<N>::T, 0, st>>>(
+        p->X, A, pr->gamma, bt, dk, g.col_groups, col_part, nullptr, nullptr, p->twN,
+        1.0f / p->M);
+  }
+  {
+    Timed tm(p, kRowsBackward, st);
+    rows_backward_sub<N><<<g.rows(), kRowThreads, 0, st>>>(p->X, O, p->P_ws, bt, dk, pg, p->sub,
+                                                           g.row_chunks, row_part, p->kappa_tab,
+                                                           p->twN);
+  }
+  if (gr->g_O) {
+    Timed tm(p, kAdamObject, st);
+    gather_dense<N><<<(p->M / 32) * (p->M / 32), 256, 0, st>>>(p->X, bt, dk, p->sub,
+                                                               reinterpret_cast<float2*>(gr->g_O));
+  }
+  ReduceArgs ra;
+  ra.col_part = col_part;
+  ra.col_wgs = g.cols();
+  ra.col_chunks = g.col_groups;
+  ra.row_part = row_part;
+  ra.row_wgs = g.rows();
+  ra.row_chunks = g.row_chunks;
+  ra.sub = p->sub;
+  ra.bt = bt;
+  ra.gamma = pr->gamma;
+  ra.loss = gr->loss;
+  ra.g_par = gr->g_par;
+  ra.g_geom = pr->geom ? gr->g_geom : nullptr;
+  ra.g_gamma = gr->g_gamma;
+  loss_grad_reduce<<<1, 256, 0, st>>>(ra);
+  FPM_HIP(hipGetLastError());
+  return FPM_OK;
+}
+
 int launch_update(fpm_plan* p, const UpdateArgs& a, int grid, hipStream_t st) {
   switch (p->N) {
     case 64: update<64><<<grid, 256, 0, st>>>(a); break;
@@ -510,6 +591,13 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
   if ((rc = upload<double>(&p->part, nullptr, n_part)) ||
       (rc = upload<float>(&p->staging, nullptr, kScal)) ||
       (rc = upload<unsigned>(&p->counters, nullptr, kCounters))) {
+    plan_free(p);
+    return rc;
+  }
+  if ((rc = upload<double>(&p->part_lg, nullptr, (size_t)cols_grid * 2 + (size_t)rows_grid * kSubPar)) ||
+      (rc = upload<SubSlot>(&p->sub, nullptr, (size_t)p->max_batch)) ||
+      (rc = upload<float2>(&p->P_ws, nullptr, (size_t)p->N * p->N)) ||
+      (rc = upload<int>(&p->oob_ws, nullptr, 1))) {
     plan_free(p);
     return rc;
   }
@@ -791,6 +879,26 @@ int fpm_run(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_t* led
   }
   if (learn_p && n_steps > 0) return commit_launch(p, s, st);
   return FPM_OK;
+}
+
+int fpm_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr,
+                  const int32_t* leds, int32_t B, const float* meas_amp, fpm_grads* gr,
+                  void* stream) {
+  FPM_REQUIRE(p && grid && pr && gr && pr->O && meas_amp,
+              "plan, grid, params, grads, params->O and meas_amp must not be NULL");
+  FPM_REQUIRE(grid->n_side >= 1 && grid->n_side * grid->n_side == p->n_led,
+              "grid->n_side^2 must equal the plan's n_led");
+  if (int rc = check_batch(p, leds, B)) return rc;
+  if (int rc = check_device(p)) return rc;
+  if (B == 0) return FPM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  switch (p->N) {
+    case 64: return launch_loss_grad<64>(p, grid, pr, leds, B, meas_amp, gr, st);
+    case 128: return launch_loss_grad<128>(p, grid, pr, leds, B, meas_amp, gr, st);
+    case 256: return launch_loss_grad<256>(p, grid, pr, leds, B, meas_amp, gr, st);
+    case 512: return launch_loss_grad<512>(p, grid, pr, leds, B, meas_amp, gr, st);
+  }
+  return fail(FPM_EUNSUPPORTED, "unsupported N");
 }
 
 int fpm_hr_transform(fpm_plan* p, const fpm_c32* in, fpm_c32* out, int32_t direction,

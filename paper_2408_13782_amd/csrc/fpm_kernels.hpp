@@ -303,7 +303,7 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch b
 
 // Column pass: inverse DFT along k_y, amplitude loss, residual, forward DFT.
 // kForward: write amplitudes (and fields) instead of the residual transform.
-template <int N, bool kForward>
+template <int N, bool kForward, bool kGamma = false>
 __global__ void __launch_bounds__(ColLines<N>::value * ColPlan<N>::T)
 cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restrict__ gamma,
      Batch bt, Disk dk, int groups, double* __restrict__ loss_part,
@@ -321,7 +321,7 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
   const int line = threadIdx.x % L;
   const int t = threadIdx.x / L;
   const int x = g * L + line;
-  float acc = 0.f;
+  float acc = 0.f, acc_ea = 0.f;   // sum e^2, sum e |psi| (the latter for dL/dgamma)
   if (live) {
     const int led = bt.led[b];
     float2* xb = X + (size_t)b * N * N;
@@ -357,6 +357,7 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
         const float a = sqrtf(psi.x * psi.x + psi.y * psi.y);
         const float e = sg * a - a_meas[m];
         acc += e * e;
+        if constexpr (kGamma) acc_ea += e * a;
         const float f = a > 0.f ? 2.f * sg * e / a : 0.f;
         v[m] = cscale(psi, f);
       }
@@ -370,7 +371,12 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
     }
   }
   if constexpr (!kForward) {
-    if (loss_part) block_partials<1>(&acc, loss_part);
+    if constexpr (kGamma) {
+      const float both[2] = {acc, acc_ea};
+      block_partials<2>(both, loss_part);
+    } else {
+      if (loss_part) block_partials<1>(&acc, loss_part);
+    }
     FPM_PROBE(1, 3);
   }
 }

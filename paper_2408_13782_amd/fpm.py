@@ -57,6 +57,16 @@ class _State(C.Structure):
                 ("t", C.c_int32)]
 
 
+class _Params(C.Structure):
+    _fields_ = [("O", C.c_void_p), ("coeffs", C.c_void_p), ("z_um", C.c_void_p),
+                ("geom", C.c_void_p), ("gamma", C.c_void_p)]
+
+
+class _Grads(C.Structure):
+    _fields_ = [("g_O", C.c_void_p), ("g_par", C.c_void_p), ("g_geom", C.c_void_p),
+                ("g_gamma", C.c_void_p), ("loss", C.c_void_p), ("oob", C.c_void_p)]
+
+
 EXPORTS = {
     "fpm_plan_create": [C.POINTER(_Desc), C.c_void_p, C.POINTER(C.c_void_p)],
     "fpm_plan_destroy": [C.c_void_p],
@@ -74,6 +84,8 @@ EXPORTS = {
                  C.c_void_p, C.c_void_p, C.c_void_p],
     "fpm_run": [C.c_void_p, C.POINTER(_State), C.POINTER(_HParams), C.c_void_p, C.c_void_p,
                 C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
+    "fpm_loss_grad": [C.c_void_p, C.POINTER(_Grid), C.POINTER(_Params), C.c_void_p, C.c_int32,
+                      C.c_void_p, C.POINTER(_Grads), C.c_void_p],
     "fpm_hr_transform": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
     "fpm_init_spectrum": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "fpm_refocus": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
@@ -155,6 +167,24 @@ def led_shifts(n_lr: int, wavelength_um: float, mag: float, pixel_um: float, n_s
     _check(lib.fpm_led_shifts(C.byref(d), C.byref(g), k.ctypes.data, s.ctypes.data,
                               nearest.ctypes.data))
     return k, s, nearest
+
+
+@dataclass
+class LedGrid:
+    """Nominal square LED array (host description); learned errors are added to it."""
+    n_side: int
+    pitch_mm: float
+    height_mm: float
+    shift_x_mm: float = 0.0
+    shift_y_mm: float = 0.0
+    rot_rad: float = 0.0
+    dh_mm: float = 0.0
+    roi_x_mm: float = 0.0
+    roi_y_mm: float = 0.0
+
+    def c(self) -> _Grid:
+        return _Grid(self.n_side, self.pitch_mm, self.height_mm, self.shift_x_mm,
+                     self.shift_y_mm, self.rot_rad, self.dh_mm, self.roi_x_mm, self.roi_y_mm)
 
 
 @dataclass
@@ -340,6 +370,41 @@ class Plan:
                                  sizes.ctypes.data, int(sizes.size), _ptr(gamma), _ptr(meas_amp),
                                  _stream()))
         state.t = cs.t
+
+    def loss_grad(self, grid: LedGrid, O, leds, meas_amp, coeffs=None, z_um=None, geom=None,
+                  gamma=None, grads=None):
+        """Loss and gradients of one batch for every parameter group (fpm_loss_grad).
+
+        grads: dict of preallocated accumulators (added to); missing entries are
+        allocated zeroed. Returns the dict with 'loss', 'g_O', 'g_par', 'g_geom',
+        'g_gamma', 'oob'.
+        """
+        import torch
+        self._spectrum(O)
+        ids, B = self._leds(leds)
+        self._images(meas_amp, gamma)
+        _need(coeffs, "coeffs", torch.float32, (N_ZERN,), optional=True)
+        _need(z_um, "z_um", torch.float32, (1,), optional=True)
+        _need(geom, "geom", torch.float64, (4,), optional=True)
+        dev = O.device
+        g = {} if grads is None else dict(grads)
+        g.setdefault("loss", torch.zeros(1, dtype=torch.float64, device=dev))
+        g.setdefault("g_O", torch.zeros((self.M, self.M), dtype=torch.complex64, device=dev))
+        g.setdefault("g_par", torch.zeros(N_PAR, dtype=torch.float64, device=dev))
+        g.setdefault("g_geom", torch.zeros(4, dtype=torch.float64, device=dev))
+        g.setdefault("g_gamma", torch.zeros(self.n_led, dtype=torch.float64, device=dev))
+        g.setdefault("oob", torch.zeros(1, dtype=torch.int32, device=dev))
+        self._spectrum(g["g_O"], "g_O")
+        pr = _Params(O.data_ptr(), None if coeffs is None else coeffs.data_ptr(),
+                     None if z_um is None else z_um.data_ptr(),
+                     None if geom is None else geom.data_ptr(),
+                     None if gamma is None else gamma.data_ptr())
+        gr = _Grads(g["g_O"].data_ptr(), g["g_par"].data_ptr(), g["g_geom"].data_ptr(),
+                    g["g_gamma"].data_ptr(), g["loss"].data_ptr(), g["oob"].data_ptr())
+        gc = grid.c()
+        _check(self._lib.fpm_loss_grad(self._h, C.byref(gc), C.byref(pr), ids.ctypes.data, B,
+                                       _ptr(meas_amp), C.byref(gr), _stream()))
+        return g
 
     def hr_transform(self, x, direction: int, out=None):
         import torch

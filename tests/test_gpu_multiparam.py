@@ -1,0 +1,287 @@
+"""GPU parity of the multi-parameter path (object, pupil Zernikes, defocus,
+LED-array shift/rotation/height, LED intensities) against the FP64 oracle,
+plus central finite differences through the torch.autograd.Function.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import fpm_oracle as fo
+from paper_2408_13782_amd import fpm, inputs
+
+from cases import optics_of, rel_l2
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GRAD_TOL = 2e-5
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def dev():
+    assert torch.cuda.is_available()
+    fpm.load()
+    return torch.device("cuda:0")
+
+
+def T(x, dev):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(dev)
+
+
+def H(t):
+    return t.detach().cpu().numpy()
+
+
+class Case:
+    """The multi-parameter workload (7x7 LEDs, 64^2 -> 256^2) with seeded true
+    geometry errors; data simulated by the oracle's sub-pixel forward model."""
+
+    def __init__(self, n_side=7, seed=0):
+        w = inputs.workload("multiparam", n_side=n_side)
+        opt = optics_of(w)
+        self.w, self.opt = w, opt
+        self.grid = fpm.LedGrid(n_side, w.pitch_mm, w.height_mm)
+        self.geom_true = np.array(inputs.true_geometry(w, seed))
+        self.z_true = inputs.true_defocus(w, seed)
+        amp, ph = inputs.truth_object(w.m_hr, seed)
+        self.O_true = fo.spectrum(fo.transmission(amp, ph))
+        self.mask = fo.pupil_mask(opt)
+        self.zern = fo.zernike_basis(opt)
+        self.kappa = fo.defocus_phase_per_um(opt)
+        s, _ = fo.led_shifts_and_jacobian(opt, n_side, w.pitch_mm, w.height_mm, self.geom_true)
+        P = fo.pupil(self.mask, self.zern, np.zeros(15), self.z_true, self.kappa)
+        n, m = w.n_lr, w.m_hr
+        I = np.stack([np.abs((n * n / m) * np.fft.ifft2(np.fft.ifftshift(
+            fo.crop_bilinear(self.O_true, n, s[l])[0] * P))) ** 2 for l in range(w.n_led)])
+        self.A = inputs.poisson_amplitudes(I, np.full(w.n_led, w.q_bright), seed)
+        centre = (n_side // 2) * n_side + n_side // 2
+        self.O0 = fo.initial_spectrum(self.A[centre], w.upsample).astype(np.complex64)
+        k = fo.led_wavevectors(opt, n_side, w.pitch_mm, w.height_mm)
+        self.shifts = fo.nearest_shifts(fo.led_shifts(opt, k))
+
+    def plan(self, max_batch=16):
+        w = self.w
+        return fpm.Plan(w.n_lr, w.upsample, self.shifts, max_batch, w.wavelength_um, w.na, w.mag,
+                        w.pixel_um)
+
+    def oracle(self, O, c, z, geom, gamma, leds):
+        w = self.w
+        return fo.multiparam_loss_and_grads(O, c, z, geom, gamma, leds, self.A.astype(np.float64),
+                                            self.opt, w.n_side, w.pitch_mm, w.height_mm,
+                                            self.mask, self.zern, self.kappa)
+
+
+@pytest.fixture(scope="module")
+def case():
+    return Case()
+
+
+def test_loss_grad_matches_oracle(dev, case):
+    say("multi-parameter loss and gradients vs oracle")
+    w = case.w
+    plan = case.plan()
+    c = inputs.random_real((15,), seed=12, lo=-0.2, hi=0.2).astype(np.float32)
+    z = np.array([1.5], np.float32)
+    geom = 0.5 * case.geom_true
+    gamma = inputs.random_real((w.n_led,), seed=13, lo=0.8, hi=1.2)
+    leds = inputs.random_indices(w.n_led, 12, seed=14)
+    s, J = fo.led_shifts_and_jacobian(case.opt, w.n_side, w.pitch_mm, w.height_mm, geom)
+    frac = np.abs((s + (w.m_hr // 2 - w.n_lr // 2)) - np.round(s + (w.m_hr // 2 - w.n_lr // 2)))
+    assert frac[leds].min() > 1e-4      # no floor decision within rounding of an integer
+    g = plan.loss_grad(case.grid, T(case.O0, dev), leds, T(case.A, dev), coeffs=T(c, dev),
+                       z_um=T(z, dev), geom=T(geom, dev), gamma=T(gamma, dev))
+    torch.cuda.synchronize()
+    O64 = case.O0.astype(np.complex128)
+    ref = case.oracle(O64, c.astype(np.float64), float(z[0]), geom, gamma.astype(np.float64), leds)
+    assert int(H(g["oob"])[0]) == 0
+    assert abs(float(H(g["loss"])[0]) - ref.loss) <= 1e-5 * ref.loss
+    assert rel_l2(H(g["g_O"]), ref.g_O) <= GRAD_TOL
+    # scalar groups are sums that cancel: judge them against the sum of their terms
+    P = fo.pupil(case.mask, case.zern, c.astype(np.float64), float(z[0]), case.kappa)
+    sub = fo.loss_and_grads_subpixel(O64, P, s, leds, case.A.astype(np.float64),
+                                     gamma.astype(np.float64))
+    _, _, g_theta = fo.pupil_param_grads(sub.g_P, P, case.zern, case.kappa)
+    g_par = H(g["g_par"])
+    for j in range(15):
+        assert abs(g_par[j] - ref.g_coeffs[j]) <= GRAD_TOL * np.sum(np.abs(g_theta * case.zern[j])), j
+    assert abs(g_par[15] - ref.g_z) <= GRAD_TOL * np.sum(np.abs(g_theta * case.kappa))
+    scale = np.zeros(4)
+    for b, led in enumerate(leds):
+        scale += np.abs(J[led].T) @ np.abs(sub.g_shift[b])
+    assert np.all(np.abs(H(g["g_geom"]) - ref.g_geom) <= 1e-4 * scale)
+    np.testing.assert_allclose(H(g["g_gamma"]), ref.g_gamma, rtol=1e-5, atol=1e-6 * np.abs(ref.g_gamma).max())
+
+
+def test_loss_grad_without_geometry_matches_the_nearest_path(dev, case):
+    say("loss_grad with the plan's integer LED table vs fpm_backward")
+    w = case.w
+    plan = case.plan()
+    leds = inputs.random_indices(w.n_led, 16, seed=3)
+    O, A = T(case.O0, dev), T(case.A, dev)
+    P = plan.pupil()
+    g = plan.loss_grad(case.grid, O, leds, A)
+    gO = torch.zeros_like(O)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    plan.backward(O, P, leds, A, gO, None, loss)
+    torch.cuda.synchronize()
+    assert rel_l2(H(g["g_O"]), H(gO)) <= 1e-6
+    assert abs(float(H(g["loss"])[0]) - float(H(loss)[0])) <= 1e-9 * float(H(loss)[0])
+    assert np.all(H(g["g_geom"]) == 0)
+
+
+def test_windows_leaving_the_grid_are_counted_not_read(dev, case):
+    say("geometry pushing windows off the HR grid")
+    w = case.w
+    plan = case.plan()
+    geom = np.array([120.0, -120.0, 0.0, 0.0])     # LED array moved by 12 cm
+    leds = np.arange(8, dtype=np.int32)
+    s, _ = fo.led_shifts_and_jacobian(case.opt, w.n_side, w.pitch_mm, w.height_mm, geom)
+    corner = np.floor(s[leds] + (w.m_hr // 2 - w.n_lr // 2))
+    want = int(np.sum(np.any((corner < 0) | (corner > w.m_hr - w.n_lr - 1), axis=1)))
+    assert want > 0
+    g = plan.loss_grad(case.grid, T(case.O0, dev), leds, T(case.A, dev), geom=T(geom, dev))
+    torch.cuda.synchronize()
+    assert int(H(g["oob"])[0]) == want
+    assert np.isfinite(float(H(g["loss"])[0]))
+
+
+def test_autograd_function_matches_float32_finite_differences(dev, case):
+    """Central differences of the float32 loss (h = 1e-4 on the largest entries of a
+    64 x 64 subset of the spectrum, steps of each scalar group's scale otherwise);
+    a coarse check of the whole chain."""
+    from paper_2408_13782_amd.autograd import FPMLoss, LossContext
+    say("autograd.Function vs float32 central differences")
+    w = case.w
+    plan = case.plan()
+    leds = inputs.random_indices(w.n_led, 10, seed=21)
+    ctx = LossContext(plan, case.grid, leds, T(case.A, dev))
+    O = T(case.O0, dev).requires_grad_(True)
+    c = T(inputs.random_real((15,), seed=22, lo=-0.1, hi=0.1), dev).requires_grad_(True)
+    z = torch.tensor([0.8], dtype=torch.float32, device=dev, requires_grad=True)
+    geom = T(0.3 * case.geom_true, dev).requires_grad_(True)
+    gamma = T(inputs.random_real((w.n_led,), seed=23, lo=0.9, hi=1.1), dev).requires_grad_(True)
+    loss = FPMLoss.apply(O, c, z, geom, gamma, ctx)
+    loss.backward()
+
+    def L(**kw):
+        args = dict(O=O.detach(), c=c.detach(), z=z.detach(), geom=geom.detach(),
+                    gamma=gamma.detach())
+        args.update(kw)
+        with torch.no_grad():
+            return float(FPMLoss.apply(args["O"], args["c"], args["z"], args["geom"],
+                                       args["gamma"], ctx))
+
+    h = 1e-4
+    m = w.m_hr
+    sub = O.grad[m // 2 - 32:m // 2 + 32, m // 2 - 32:m // 2 + 32]
+    flat = torch.argsort(sub.abs().flatten(), descending=True)[:6].cpu().numpy()
+    for idx in flat:
+        i, j = divmod(int(idx), 64)
+        i += m // 2 - 32
+        j += m // 2 - 32
+        for unit in (1.0, 1j):
+            E = torch.zeros_like(O.detach())
+            E[i, j] = unit
+            Op, Om = O.detach() + h * E, O.detach() - h * E
+            part = (lambda x: x.real) if unit == 1.0 else (lambda x: x.imag)
+            # the float32 steps actually taken (h is below the spacing of large entries)
+            step = float(part(Op[i, j] - Om[i, j]))
+            fd = (L(O=Op) - L(O=Om)) / step
+            an = float(part(O.grad[i, j]))
+            big = float(sub.abs().max())
+            assert abs(fd - an) <= 3e-2 * big, (i, j, unit, fd, an)
+    # Scalars: steps sized to each parameter's scale, so that the float32 rounding
+    # of the loss (about 1e-6 of it) stays well below the difference; geometry steps
+    # must not move any window corner across an integer (the bilinear crop has a
+    # kink there).
+    L0 = abs(float(loss.detach()))
+    steps = dict(c=1e-3, z=1e-2, geom=1e-4, gamma=1e-3)
+    corner0 = w.m_hr // 2 - w.n_lr // 2
+    for name, tensor in (("c", c), ("z", z), ("geom", geom), ("gamma", gamma)):
+        gvec = tensor.grad.detach().cpu().numpy().ravel()
+        picks = np.argsort(-np.abs(gvec))[:3]
+        for k in picks:
+            e = torch.zeros_like(tensor.detach()).flatten()
+            e[int(k)] = steps[name]
+            e = e.view_as(tensor)
+            tp, tm = tensor.detach() + e, tensor.detach() - e
+            if name == "geom":
+                fl = [np.floor(fo.led_shifts_and_jacobian(case.opt, w.n_side, w.pitch_mm, w.height_mm,
+                                                          H(t))[0][leds] + corner0) for t in (tp, tm)]
+                if not np.array_equal(fl[0], fl[1]):
+                    continue
+            step = float((tp - tm).flatten()[int(k)])
+            fd = (L(**{name: tp}) - L(**{name: tm})) / step
+            tol = 3e-2 * np.abs(gvec).max() + 4e-6 * L0 / step
+            assert abs(fd - gvec[k]) <= tol, (name, k, fd, gvec[k], tol)
+
+
+def test_torch_adam_solve_through_the_autograd_function_matches_oracle(dev, case):
+    """Ten joint updates (object, Zernikes, defocus, geometry) with torch Adam over the
+    library's gradients, against the same updates with the oracle's FP64 gradients."""
+    from paper_2408_13782_amd.autograd import FPMLoss, LossContext
+    say("multi-parameter torch-Adam solve vs oracle")
+    w = case.w
+    plan = case.plan()
+    perms = inputs.led_permutations(w.n_led, 2, seed=5)
+    sched = fo.batches_from_permutations(perms, w.batch)[:10]
+    lrs = dict(O=w.lr_object, c=w.lr_zernike, z=w.lr_z, geom=1e-3)
+    # GPU: torch tensors on the device
+    O = T(case.O0, dev).requires_grad_(True)
+    c = torch.zeros(15, dtype=torch.float32, device=dev, requires_grad=True)
+    z = torch.zeros(1, dtype=torch.float32, device=dev, requires_grad=True)
+    geom = torch.zeros(4, dtype=torch.float64, device=dev, requires_grad=True)
+    opt = torch.optim.Adam([dict(params=[O], lr=lrs["O"]), dict(params=[c], lr=lrs["c"]),
+                            dict(params=[z], lr=lrs["z"]), dict(params=[geom], lr=lrs["geom"])])
+    A = T(case.A, dev)
+    for leds in sched:
+        opt.zero_grad()
+        loss = FPMLoss.apply(O, c, z, geom, None, LossContext(plan, case.grid, np.array(leds, np.int32), A))
+        loss.backward()
+        c.grad[0] = 0.0      # piston: a global phase, held fixed
+        opt.step()
+    # oracle: the same updates in float64 on the CPU
+    O_r = torch.tensor(case.O0.astype(np.complex128), requires_grad=True)
+    c_r = torch.zeros(15, dtype=torch.float64, requires_grad=True)
+    z_r = torch.zeros(1, dtype=torch.float64, requires_grad=True)
+    g_r = torch.zeros(4, dtype=torch.float64, requires_grad=True)
+    opt_r = torch.optim.Adam([dict(params=[O_r], lr=lrs["O"]), dict(params=[c_r], lr=lrs["c"]),
+                              dict(params=[z_r], lr=lrs["z"]), dict(params=[g_r], lr=lrs["geom"])])
+    for leds in sched:
+        gr = case.oracle(O_r.detach().numpy(), c_r.detach().numpy(), float(z_r.detach()[0]),
+                         g_r.detach().numpy(), None, leds)
+        O_r.grad = torch.tensor(gr.g_O)
+        c_r.grad = torch.tensor(gr.g_coeffs)
+        c_r.grad[0] = 0.0
+        z_r.grad = torch.tensor([gr.g_z], dtype=torch.float64)
+        g_r.grad = torch.tensor(gr.g_geom)
+        opt_r.step()
+    torch.cuda.synchronize()
+    # Adam moves each scalar by about lr per step whatever the gradient's size: a
+    # disagreement shows as a fraction of lr
+    assert rel_l2(H(O), O_r.detach().numpy()) <= 1e-3
+    np.testing.assert_allclose(H(c), c_r.detach().numpy(), atol=0.2 * lrs["c"])
+    np.testing.assert_allclose(H(geom), g_r.detach().numpy(), atol=0.2 * lrs["geom"])
+    np.testing.assert_allclose(H(z), z_r.detach().numpy(), atol=0.2 * lrs["z"])
+
+
+def test_refocus_sweep_16_distances_over_1024(dev):
+    """Digital refocusing of a 1024 x 1024 reconstruction at 16 distances in [-40, 40] um."""
+    w = inputs.workload("paper")
+    say("refocus sweep 16 z over 1024^2")
+    opt = optics_of(w)
+    plan = fpm.Plan(w.n_lr, w.upsample, np.zeros((1, 2), np.int32), 1, w.wavelength_um, w.na,
+                    w.mag, w.pixel_um)
+    amp, ph = inputs.truth_object(w.m_hr, seed=9)
+    O = fo.spectrum(fo.transmission(amp, ph)).astype(np.complex64)
+    z = np.linspace(-40.0, 40.0, 16).astype(np.float32)
+    out = H(plan.refocus(T(O, dev), T(z, dev)))
+    want = fo.refocus(O.astype(np.complex128), z.astype(np.float64), opt)
+    for i in range(len(z)):
+        assert rel_l2(out[i], want[i]) <= GRAD_TOL, i

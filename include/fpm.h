@@ -5,7 +5,8 @@
  * Conventions shared by every entry point
  * ---------------------------------------
  * Sizes.  N = n_lr is the low-resolution (LR) image side, s = upsample,
- *   M = s*N the high-resolution (HR) side. Supported N: 64, 128, 256, 512.
+ *   M = s*N the high-resolution (HR) side. Supported N: 64, 128, 192, 256,
+ *   384, 512.
  *
  * Spectrum O.  complex [M][M] row-major (row = k_y, column = k_x), centred
  *   (zero frequency at [M/2][M/2]) and orthonormally scaled:
@@ -90,6 +91,7 @@ typedef struct {
   int32_t adam_tiles;      /* 32 x 32 HR tiles covering the union of windows */
   double pupil_radius_px;  /* NA / lambda / dk */
   double dk;               /* spectral pitch, 1/um */
+  int64_t device_bytes;    /* device memory the plan holds (its scratch and tables) */
 } fpm_info;
 
 /*

@@ -16,13 +16,13 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfpm.so")
 
-SOURCES = ["fpm_api.hip"]
-HEADERS = ["fft_line.hpp", "fpm_kernels.hpp", "fpm_aux.hpp"]
+SOURCES = ["fpm_api.hip", "fpm_serve.hip"]
+HEADERS = ["fft_line.hpp", "fpm_kernels.hpp", "fpm_aux.hpp", "fpm_subpixel.hpp"]
 
 # Packed FP32 instructions are disabled on purpose (some of their forms have given
 # unreliable results on this target).
 HIPCC_FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared", "-pthread",
     "-munsafe-fp-atomics",
     # gfx950 preloads the first kernel arguments into SGPRs: one scalar-load
     # round trip less at the start of every kernel

@@ -321,10 +321,22 @@ FPM_PLAN(512, 64, 8, 8, 8)
 FPM_PLAN(512, 128, 4, 4, 4, 4, 2)
 FPM_PLAN(1024, 64, 16, 8, 8)
 FPM_PLAN(2048, 128, 16, 16, 8)
+// 3 * 2^k sizes: 12 elements per thread (24 for 1536), one radix-12 stage
+FPM_PLAN(192, 16, 12, 4, 4)
+FPM_PLAN(384, 32, 12, 4, 4, 2)
+FPM_PLAN(768, 64, 12, 4, 4, 4)
+FPM_PLAN(1536, 64, 12, 8, 4, 4)
 #undef FPM_PLAN
 
-// Default threads per line: 16 elements per thread where the radices allow.
-template <int N> struct DefaultT { static constexpr int value = N <= 128 ? 8 : N == 256 ? 16 : N == 512 ? 64 : N / 16; };
+// Default threads per line: 16 elements per thread where the radices allow,
+// 12 (or 24) for the sizes with a factor 3.
+template <int N> struct DefaultT {
+  static constexpr int value = N <= 128 ? 8 : N == 256 ? 16 : N == 512 ? 64 : N / 16;
+};
+template <> struct DefaultT<192> { static constexpr int value = 16; };
+template <> struct DefaultT<384> { static constexpr int value = 32; };
+template <> struct DefaultT<768> { static constexpr int value = 64; };
+template <> struct DefaultT<1536> { static constexpr int value = 64; };
 template <int N> using Plan1D = PlanT<N, DefaultT<N>::value>;
 
 }  // namespace fpm

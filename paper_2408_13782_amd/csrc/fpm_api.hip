@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "fpm.h"
@@ -15,14 +16,21 @@
 
 using namespace fpm;
 
-namespace {
+namespace fpm {
 
 thread_local std::string g_last_error;
 
-int fail(int code, const std::string& msg) {
+// Record the message of a failure for fpm_last_error() on this thread.
+int set_error(int code, const std::string& msg) {
   g_last_error = msg;
   return code;
 }
+
+}  // namespace fpm
+
+namespace {
+
+int fail(int code, const std::string& msg) { return fpm::set_error(code, msg); }
 
 #define FPM_HIP(call)                                                              \
   do {                                                                             \
@@ -36,8 +44,30 @@ int fail(int code, const std::string& msg) {
     if (!(cond)) return fail(FPM_EINVAL, msg); \
   } while (0)
 
-bool lr_supported(int n) { return n == 64 || n == 128 || n == 256 || n == 512; }
-bool hr_supported(int m) { return m == 256 || m == 512 || m == 1024 || m == 2048; }
+bool lr_supported(int n) {
+  return n == 64 || n == 128 || n == 192 || n == 256 || n == 384 || n == 512;
+}
+bool hr_supported(int m) {
+  return m == 256 || m == 512 || m == 768 || m == 1024 || m == 1536 || m == 2048;
+}
+
+const char* const kHrSizes = "HR transforms support M in {256, 512, 768, 1024, 1536, 2048}";
+
+template <int V> using Size = std::integral_constant<int, V>;
+
+// f(Size<N>{}) for the supported LR image sizes N (the kernels are templates on N).
+template <class F>
+int with_lr_size(int n, F&& f) {
+  switch (n) {
+    case 64: return f(Size<64>{});
+    case 128: return f(Size<128>{});
+    case 192: return f(Size<192>{});
+    case 256: return f(Size<256>{});
+    case 384: return f(Size<384>{});
+    case 512: return f(Size<512>{});
+  }
+  return fail(FPM_EUNSUPPORTED, "unsupported N");
+}
 
 std::vector<float2> twiddles(int n) {
   std::vector<float2> tw(n);
@@ -48,12 +78,14 @@ std::vector<float2> twiddles(int n) {
   return tw;
 }
 
+// Allocate count elements (adding their bytes to *total) and copy src if given.
 template <class T>
-int upload(T** dst, const T* src, size_t count) {
+int upload(size_t* total, T** dst, const T* src, size_t count) {
   if (hipMalloc((void**)dst, count * sizeof(T)) != hipSuccess) {
     *dst = nullptr;
     return fail(FPM_ENOMEM, "hipMalloc failed");
   }
+  *total += count * sizeof(T);
   if (src) FPM_HIP(hipMemcpy(*dst, src, count * sizeof(T), hipMemcpyHostToDevice));
   return FPM_OK;
 }
@@ -80,6 +112,7 @@ struct fpm_plan {
   int ky_lo = 0, ky_hi = -1, nrows = 0, support_px = 0;
   int n_tiles = 0;
   bool hr_ok = false;
+  size_t device_bytes = 0;    // everything the plan allocated
   std::vector<int2> shifts_h;
   int2* rowext = nullptr;     // [N] (first, last) disk column of each pupil row
   float2* twN = nullptr;      // [N]
@@ -314,41 +347,27 @@ int launch_forward(fpm_plan* p, const float2* O, const float2* P, const int32_t*
 int dispatch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t* leds, int B,
                       const float* gamma, const float* A, float2* gO, const BackwardOut& o,
                       hipStream_t st) {
-  switch (p->N) {
-    case 64: return launch_backward<64>(p, O, P, leds, B, gamma, A, gO, o, st);
-    case 128: return launch_backward<128>(p, O, P, leds, B, gamma, A, gO, o, st);
-    case 256: return launch_backward<256>(p, O, P, leds, B, gamma, A, gO, o, st);
-    case 512: return launch_backward<512>(p, O, P, leds, B, gamma, A, gO, o, st);
-  }
-  return fail(FPM_EUNSUPPORTED, "unsupported N");
+  return with_lr_size(p->N, [&](auto n) {
+    return launch_backward<decltype(n)::value>(p, O, P, leds, B, gamma, A, gO, o, st);
+  });
 }
 
 // Grid sizes of the reducing kernels at B = max_batch (sizes the partial buffers).
 void reduce_grids(const fpm_plan* p, int& rows_grid, int& cols_grid) {
-  switch (p->N) {
-    case 64: { auto g = grids_of<64>(p, p->max_batch); rows_grid = g.rows(); cols_grid = g.cols(); break; }
-    case 128: { auto g = grids_of<128>(p, p->max_batch); rows_grid = g.rows(); cols_grid = g.cols(); break; }
-    case 256: { auto g = grids_of<256>(p, p->max_batch); rows_grid = g.rows(); cols_grid = g.cols(); break; }
-    default: { auto g = grids_of<512>(p, p->max_batch); rows_grid = g.rows(); cols_grid = g.cols(); break; }
-  }
+  with_lr_size(p->N, [&](auto n) {
+    const Grids g = grids_of<decltype(n)::value>(p, p->max_batch);
+    rows_grid = g.rows();
+    cols_grid = g.cols();
+    return 0;
+  });
 }
 
 int rows_grid_of(const fpm_plan* p, int B) {
-  switch (p->N) {
-    case 64: return grids_of<64>(p, B).rows();
-    case 128: return grids_of<128>(p, B).rows();
-    case 256: return grids_of<256>(p, B).rows();
-    default: return grids_of<512>(p, B).rows();
-  }
+  return with_lr_size(p->N, [&](auto n) { return grids_of<decltype(n)::value>(p, B).rows(); });
 }
 
 int cols_grid_of(const fpm_plan* p, int B) {
-  switch (p->N) {
-    case 64: return grids_of<64>(p, B).cols();
-    case 128: return grids_of<128>(p, B).cols();
-    case 256: return grids_of<256>(p, B).cols();
-    default: return grids_of<512>(p, B).cols();
-  }
+  return with_lr_size(p->N, [&](auto n) { return grids_of<decltype(n)::value>(p, B).cols(); });
 }
 
 int pupil_wgs(const fpm_plan* p) { return (p->N * p->N + kPupilPerWg - 1) / kPupilPerWg; }
@@ -426,13 +445,11 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
 }
 
 int launch_update(fpm_plan* p, const UpdateArgs& a, int grid, hipStream_t st) {
-  switch (p->N) {
-    case 64: update<64><<<grid, 256, 0, st>>>(a); break;
-    case 128: update<128><<<grid, 256, 0, st>>>(a); break;
-    case 256: update<256><<<grid, 256, 0, st>>>(a); break;
-    case 512: update<512><<<grid, 256, 0, st>>>(a); break;
-    default: return fail(FPM_EUNSUPPORTED, "unsupported N");
-  }
+  if (int rc = with_lr_size(p->N, [&](auto n) {
+        update<decltype(n)::value><<<grid, 256, 0, st>>>(a);
+        return 0;
+      }))
+    return rc;
   FPM_HIP(hipGetLastError());
   return FPM_OK;
 }
@@ -464,10 +481,12 @@ int dispatch_hr(fpm_plan* p, HrArgs a, int row_mode, int dir, hipStream_t st) {
   switch (p->M) {
     case 256: return launch_hr<256>(p, a, row_mode, dir, st);
     case 512: return launch_hr<512>(p, a, row_mode, dir, st);
+    case 768: return launch_hr<768>(p, a, row_mode, dir, st);
     case 1024: return launch_hr<1024>(p, a, row_mode, dir, st);
+    case 1536: return launch_hr<1536>(p, a, row_mode, dir, st);
     case 2048: return launch_hr<2048>(p, a, row_mode, dir, st);
   }
-  return fail(FPM_EUNSUPPORTED, "HR transforms support M in {256, 512, 1024, 2048}");
+  return fail(FPM_EUNSUPPORTED, kHrSizes);
 }
 
 }  // namespace
@@ -490,7 +509,7 @@ const char* fpm_last_error(void) { return g_last_error.c_str(); }
 int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** out) {
   FPM_REQUIRE(d && shifts_host && out, "desc, shifts_host and plan must not be NULL");
   *out = nullptr;
-  if (!lr_supported(d->n_lr)) return fail(FPM_EUNSUPPORTED, "n_lr must be 64, 128, 256 or 512");
+  if (!lr_supported(d->n_lr)) return fail(FPM_EUNSUPPORTED, "n_lr must be 64, 128, 192, 256, 384 or 512");
   FPM_REQUIRE(d->upsample >= 1 && (int64_t)d->upsample * d->n_lr <= 4096, "upsample out of range");
   FPM_REQUIRE(d->n_led >= 1 && d->max_batch >= 1, "n_led and max_batch must be >= 1");
   FPM_REQUIRE(d->max_batch <= kMaxSlots, "max_batch must be <= 64");
@@ -575,12 +594,12 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
   }
   int rc = FPM_OK;
   const auto twn = twiddles(p->N);
-  if ((rc = upload(&p->rowext, ext.data(), ext.size())) ||
-      (rc = upload(&p->twN, twn.data(), twn.size())) ||
-      (rc = upload<float2>(&p->X, nullptr, (size_t)p->max_batch * p->N * p->N)) ||
-      (rc = upload<float2>(&p->gP, nullptr, (size_t)p->N * p->N)) ||
-      (rc = upload(&p->kappa_tab, kap.data(), kap.size())) ||
-      (rc = upload(&p->tiles, tiles.data(), std::max<size_t>(tiles.size(), 1)))) {
+  if ((rc = upload(&p->device_bytes, &p->rowext, ext.data(), ext.size())) ||
+      (rc = upload(&p->device_bytes, &p->twN, twn.data(), twn.size())) ||
+      (rc = upload<float2>(&p->device_bytes, &p->X, nullptr, (size_t)p->max_batch * p->N * p->N)) ||
+      (rc = upload<float2>(&p->device_bytes, &p->gP, nullptr, (size_t)p->N * p->N)) ||
+      (rc = upload(&p->device_bytes, &p->kappa_tab, kap.data(), kap.size())) ||
+      (rc = upload(&p->device_bytes, &p->tiles, tiles.data(), std::max<size_t>(tiles.size(), 1)))) {
     plan_free(p);
     return rc;
   }
@@ -588,16 +607,16 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
   reduce_grids(p, rows_grid, cols_grid);
   const int pg_grid = (p->N * p->N + 255) / 256;
   const size_t n_part = (size_t)cols_grid + (size_t)rows_grid * kPar + (size_t)pg_grid * kPar;
-  if ((rc = upload<double>(&p->part, nullptr, n_part)) ||
-      (rc = upload<float>(&p->staging, nullptr, kScal)) ||
-      (rc = upload<unsigned>(&p->counters, nullptr, kCounters))) {
+  if ((rc = upload<double>(&p->device_bytes, &p->part, nullptr, n_part)) ||
+      (rc = upload<float>(&p->device_bytes, &p->staging, nullptr, kScal)) ||
+      (rc = upload<unsigned>(&p->device_bytes, &p->counters, nullptr, kCounters))) {
     plan_free(p);
     return rc;
   }
-  if ((rc = upload<double>(&p->part_lg, nullptr, (size_t)cols_grid * 2 + (size_t)rows_grid * kSubPar)) ||
-      (rc = upload<SubSlot>(&p->sub, nullptr, (size_t)p->max_batch)) ||
-      (rc = upload<float2>(&p->P_ws, nullptr, (size_t)p->N * p->N)) ||
-      (rc = upload<int>(&p->oob_ws, nullptr, 1))) {
+  if ((rc = upload<double>(&p->device_bytes, &p->part_lg, nullptr, (size_t)cols_grid * 2 + (size_t)rows_grid * kSubPar)) ||
+      (rc = upload<SubSlot>(&p->device_bytes, &p->sub, nullptr, (size_t)p->max_batch)) ||
+      (rc = upload<float2>(&p->device_bytes, &p->P_ws, nullptr, (size_t)p->N * p->N)) ||
+      (rc = upload<int>(&p->device_bytes, &p->oob_ws, nullptr, 1))) {
     plan_free(p);
     return rc;
   }
@@ -610,7 +629,7 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
   }
   if (p->hr_ok) {
     const auto twm = twiddles(p->M);
-    if ((rc = upload(&p->twM, twm.data(), twm.size()))) {
+    if ((rc = upload(&p->device_bytes, &p->twM, twm.data(), twm.size()))) {
       plan_free(p);
       return rc;
     }
@@ -640,6 +659,7 @@ int fpm_plan_info(const fpm_plan* p, fpm_info* info) {
   info->adam_tiles = p->n_tiles;
   info->pupil_radius_px = p->radius;
   info->dk = p->dk;
+  info->device_bytes = (int64_t)p->device_bytes;
   return FPM_OK;
 }
 
@@ -694,13 +714,9 @@ int fpm_forward(fpm_plan* p, const fpm_c32* O, const fpm_c32* P, const int32_t* 
   const auto* pp = reinterpret_cast<const float2*>(P);
   auto* f = reinterpret_cast<float2*>(field_out);
   hipStream_t st = (hipStream_t)stream;
-  switch (p->N) {
-    case 64: return launch_forward<64>(p, o, pp, leds, B, gamma, amp_out, f, st);
-    case 128: return launch_forward<128>(p, o, pp, leds, B, gamma, amp_out, f, st);
-    case 256: return launch_forward<256>(p, o, pp, leds, B, gamma, amp_out, f, st);
-    case 512: return launch_forward<512>(p, o, pp, leds, B, gamma, amp_out, f, st);
-  }
-  return fail(FPM_EUNSUPPORTED, "unsupported N");
+  return with_lr_size(p->N, [&](auto n) {
+    return launch_forward<decltype(n)::value>(p, o, pp, leds, B, gamma, amp_out, f, st);
+  });
 }
 
 int fpm_backward(fpm_plan* p, const fpm_c32* O, const fpm_c32* P, const int32_t* leds, int32_t B,
@@ -892,20 +908,16 @@ int fpm_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr,
   if (int rc = check_device(p)) return rc;
   if (B == 0) return FPM_OK;
   hipStream_t st = (hipStream_t)stream;
-  switch (p->N) {
-    case 64: return launch_loss_grad<64>(p, grid, pr, leds, B, meas_amp, gr, st);
-    case 128: return launch_loss_grad<128>(p, grid, pr, leds, B, meas_amp, gr, st);
-    case 256: return launch_loss_grad<256>(p, grid, pr, leds, B, meas_amp, gr, st);
-    case 512: return launch_loss_grad<512>(p, grid, pr, leds, B, meas_amp, gr, st);
-  }
-  return fail(FPM_EUNSUPPORTED, "unsupported N");
+  return with_lr_size(p->N, [&](auto n) {
+    return launch_loss_grad<decltype(n)::value>(p, grid, pr, leds, B, meas_amp, gr, st);
+  });
 }
 
 int fpm_hr_transform(fpm_plan* p, const fpm_c32* in, fpm_c32* out, int32_t direction,
                      void* stream) {
   FPM_REQUIRE(p && in && out, "plan, in and out must not be NULL");
   FPM_REQUIRE(direction == 1 || direction == -1, "direction must be +1 or -1");
-  if (!p->hr_ok) return fail(FPM_EUNSUPPORTED, "HR transforms support M in {256, 512, 1024, 2048}");
+  if (!p->hr_ok) return fail(FPM_EUNSUPPORTED, kHrSizes);
   if (int rc = check_device(p)) return rc;
   HrArgs a{};
   a.in = reinterpret_cast<const float2*>(in);
@@ -916,7 +928,7 @@ int fpm_hr_transform(fpm_plan* p, const fpm_c32* in, fpm_c32* out, int32_t direc
 
 int fpm_init_spectrum(fpm_plan* p, const float* centre_amp, fpm_c32* O_out, void* stream) {
   FPM_REQUIRE(p && centre_amp && O_out, "plan, centre_amp and O_out must not be NULL");
-  if (!p->hr_ok) return fail(FPM_EUNSUPPORTED, "HR transforms support M in {256, 512, 1024, 2048}");
+  if (!p->hr_ok) return fail(FPM_EUNSUPPORTED, kHrSizes);
   if (int rc = check_device(p)) return rc;
   HrArgs a{};
   a.img = centre_amp;
@@ -930,7 +942,7 @@ int fpm_refocus(fpm_plan* p, const fpm_c32* O, const float* z_um, int32_t nz, fp
                 void* stream) {
   FPM_REQUIRE(p && O && out && (nz == 0 || z_um), "plan, O, z_um and out must not be NULL");
   FPM_REQUIRE(nz >= 0, "nz must be >= 0");
-  if (!p->hr_ok) return fail(FPM_EUNSUPPORTED, "HR transforms support M in {256, 512, 1024, 2048}");
+  if (!p->hr_ok) return fail(FPM_EUNSUPPORTED, kHrSizes);
   if (int rc = check_device(p)) return rc;
   if (nz == 0) return FPM_OK;
   for (int i = 0; i < nz; ++i) {

@@ -301,7 +301,8 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
 // High-resolution 2-D transforms, split into a row pass and a column pass.
 
 template <int M> struct HrRowLines { static constexpr int value = (128 / Plan1D<M>::T) > 0 ? 128 / Plan1D<M>::T : 1; };
-template <int M> struct HrColLines { static constexpr int value = M >= 2048 ? 8 : 16; };
+// columns per workgroup of the HR column pass: M x (L + 1) complex slots of LDS
+template <int M> struct HrColLines { static constexpr int value = M > 1024 ? 8 : 16; };
 
 enum HrRowMode { kRowFwd = 0, kRowInv = 1, kRowInit = 2, kRowRefocus = 3 };
 

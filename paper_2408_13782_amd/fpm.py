@@ -34,7 +34,8 @@ class _Info(C.Structure):
     _fields_ = [("n_lr", C.c_int32), ("m_hr", C.c_int32), ("n_led", C.c_int32),
                 ("max_batch", C.c_int32), ("support_px", C.c_int32),
                 ("support_rows", C.c_int32), ("adam_tiles", C.c_int32),
-                ("pupil_radius_px", C.c_double), ("dk", C.c_double)]
+                ("pupil_radius_px", C.c_double), ("dk", C.c_double),
+                ("device_bytes", C.c_int64)]
 
 
 class _Grid(C.Structure):

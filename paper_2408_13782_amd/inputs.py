@@ -96,6 +96,37 @@ def workload(name: str, **overrides) -> Workload:
     return replace(WORKLOADS[name], **overrides)
 
 
+# Tile reconstructions of a serving stream: LR sizes and LED grids of uneven
+# size, 4x upsampling, object + Zernike pupil, B = 16, 20 epochs each.
+SERVING_SIZES = (128, 192, 256, 384, 512)
+SERVING_GRIDS = (7, 11, 15)
+
+
+def serving_shapes():
+    """Every (N, grid) combination of the serving stream, as Workloads."""
+    return [Workload(name=f"tile{n}x{g}", n_side=g, n_lr=n, batch=16, epochs=20,
+                     q_bright=1e4, q_dark=1e2, learn_zernike=True, true_defocus_um=10.0,
+                     **_OPTICS)
+            for n in SERVING_SIZES for g in SERVING_GRIDS]
+
+
+def serving_stream(n_requests: int, seed: int = 0):
+    """Shape index (into serving_shapes()) and schedule seed of each request:
+    N and grid drawn uniformly and independently."""
+    rng = np.random.default_rng([seed, 5])
+    n = rng.integers(0, len(SERVING_SIZES), n_requests)
+    g = rng.integers(0, len(SERVING_GRIDS), n_requests)
+    shape = n * len(SERVING_GRIDS) + g
+    seeds = rng.integers(0, 2**31 - 1, n_requests)
+    return shape.astype(np.int64), seeds.astype(np.int64)
+
+
+def poisson_arrivals_ms(rate_per_s: float, n: int, seed: int = 0) -> np.ndarray:
+    """Arrival times (ms from 0) of a Poisson process of the given rate."""
+    rng = np.random.default_rng([seed, 6])
+    return np.cumsum(rng.exponential(1e3 / rate_per_s, n))
+
+
 # ---------------------------------------------------------------------------
 # truth object
 

@@ -1,0 +1,110 @@
+// Scheduling checks of the tile server against the stand-ins in fake_fpm.cpp:
+// every request completes with its own result, admission is first-in
+// first-out, the footprint budget caps the requests in flight, invalid
+// requests are refused, destroy waits for queued work.
+#include <atomic>
+#include <cstdio>
+#include <vector>
+
+#include "fpm_serve.h"
+
+extern std::atomic<int> peak;
+
+#define CHECK(c)                                          \
+  do {                                                    \
+    if (!(c)) {                                           \
+      std::printf("FAILED %s (line %d)\n", #c, __LINE__); \
+      return 1;                                           \
+    }                                                     \
+  } while (0)
+
+int main() {
+  fpm_desc d{64, 4, 9, 4, 0.5, 0.1, 4, 6.5};
+  std::vector<int32_t> shifts(18, 0);
+  int64_t fp = 0;
+  CHECK(fpm_request_footprint(&d, shifts.data(), &fp) == FPM_OK && fp > 0);
+  fpm_server_desc sd{4, 3 * fp};   // four lanes, memory for three requests
+  fpm_server* sv = nullptr;
+  CHECK(fpm_server_create(&sd, &sv) == FPM_OK);
+  std::vector<float> amp(9 * 64 * 64);
+  const int R = 50;
+  std::vector<std::vector<fpm_c32>> outs(R, std::vector<fpm_c32>(256 * 256));
+  std::vector<double> loss(R);
+  std::vector<int32_t> leds(40), sizes(10, 4);
+  for (int i = 0; i < 40; ++i) leds[i] = i % 9;
+  for (int i = 0; i < R; ++i) {
+    fpm_request r{};
+    r.desc = d;
+    r.shifts_host = shifts.data();
+    r.meas_amp = amp.data();
+    r.centre_led = 4;
+    leds[0] = i % 9;   // copied at submit: later edits must not reach request i
+    r.leds = leds.data();
+    r.batch_sizes = sizes.data();
+    r.n_steps = 10;
+    r.O_out = outs[i].data();
+    r.loss_out = &loss[i];
+    r.tag = i;
+    CHECK(fpm_server_submit(sv, &r) == FPM_OK);
+  }
+  fpm_request bad{};
+  bad.desc = d;
+  bad.shifts_host = shifts.data();
+  bad.meas_amp = amp.data();
+  bad.O_out = outs[0].data();
+  bad.centre_led = 99;
+  CHECK(fpm_server_submit(sv, &bad) == FPM_EINVAL);
+  bad.centre_led = 0;
+  bad.n_steps = 1;
+  bad.leds = leds.data();
+  int32_t big_batch = 5;   // > max_batch
+  bad.batch_sizes = &big_batch;
+  CHECK(fpm_server_submit(sv, &bad) == FPM_EINVAL);
+  fpm_desc wide = d;
+  wide.n_led = 9;
+  wide.n_lr = 128;   // footprint above the budget
+  bad.desc = wide;
+  bad.n_steps = 0;
+  CHECK(fpm_server_submit(sv, &bad) == FPM_EINVAL);
+
+  CHECK(fpm_server_drain(sv) == FPM_OK);
+  std::vector<fpm_completion> c(R + 5);
+  int32_t n = 0;
+  CHECK(fpm_server_poll(sv, c.data(), R + 5, &n, 0) == FPM_OK && n == R);
+  int32_t q, run, mr, sl;
+  int64_t done, used;
+  CHECK(fpm_server_stats(sv, &q, &run, &done, &used, &mr, &sl) == FPM_OK);
+  CHECK(q == 0 && run == 0 && done == R && used == 0);
+  CHECK(mr == 3 && peak.load() == 3);   // the budget, not the lanes, bounded concurrency
+  CHECK(sl == 3);                       // slots reused across requests
+  for (int i = 0; i < R; ++i) {
+    CHECK(outs[i][0].re == 1.0f && outs[i][0].im == (float)(i % 9) && loss[i] == 10.0);
+  }
+  std::vector<double> adm(R, -1.0);
+  for (int i = 0; i < n; ++i) {
+    CHECK(c[i].status == FPM_OK && c[i].footprint_bytes == fp);
+    CHECK(c[i].t_submit_ms <= c[i].t_admit_ms && c[i].t_admit_ms <= c[i].t_done_ms);
+    adm[c[i].tag] = c[i].t_admit_ms;
+  }
+  for (int i = 1; i < R; ++i) CHECK(adm[i] >= adm[i - 1]);
+
+  // destroy with work still queued waits for it
+  for (int i = 0; i < 8; ++i) {
+    fpm_request r{};
+    r.desc = d;
+    r.shifts_host = shifts.data();
+    r.meas_amp = amp.data();
+    r.centre_led = 4;
+    r.leds = leds.data();
+    r.batch_sizes = sizes.data();
+    r.n_steps = 10;
+    r.O_out = outs[i].data();
+    r.loss_out = &loss[i];
+    loss[i] = 0.0;
+    CHECK(fpm_server_submit(sv, &r) == FPM_OK);
+  }
+  CHECK(fpm_server_destroy(sv) == FPM_OK);
+  for (int i = 0; i < 8; ++i) CHECK(loss[i] == 10.0);
+  std::printf("OK\n");
+  return 0;
+}

@@ -18,8 +18,11 @@ HEADER = os.path.join(ROOT, "include", "fpm.h")
 PKG = os.path.join(ROOT, "paper_2408_13782_amd")
 
 
-def declared_functions():
-    src = open(HEADER).read()
+SERVE_HEADER = os.path.join(ROOT, "include", "fpm_serve.h")
+
+
+def declared_functions(header=HEADER):
+    src = open(header).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(fpm_[a-z_0-9]+)\s*\(", src)))
 
@@ -34,9 +37,16 @@ def test_header_declares_the_boundary():
 
 def test_library_loads_and_exports_every_declared_symbol():
     lib = fpm.load()
-    for name in declared_functions():
-        assert hasattr(lib, name), name
+    for header in (HEADER, SERVE_HEADER):
+        for name in declared_functions(header):
+            assert hasattr(lib, name), name
     assert set(declared_functions()) == set(fpm.EXPORTS)
+
+
+def test_server_binding_covers_the_server_header():
+    from paper_2408_13782_amd import serving
+    bound = set(serving._SIGS) | {"fpm_server_clock_ms"}
+    assert set(declared_functions(SERVE_HEADER)) == bound
 
 
 def test_error_strings():

@@ -60,7 +60,7 @@ def oracle_shifts(w):
 # building blocks
 
 
-@pytest.mark.parametrize("n_lr", [64, 256, 512])
+@pytest.mark.parametrize("n_lr", [64, 192, 256, 384, 512])
 def test_hr_transforms_match_oracle(dev, n_lr):
     w = inputs.workload("small", n_lr=n_lr)
     say(f"hr_transform M={w.m_hr}")
@@ -80,7 +80,7 @@ def test_hr_transforms_match_oracle(dev, n_lr):
     assert rel_l2(H(x), want) <= GRAD_TOL
 
 
-@pytest.mark.parametrize("n_lr", [64, 256])
+@pytest.mark.parametrize("n_lr", [64, 192, 256])
 def test_initial_spectrum_matches_oracle(dev, n_lr):
     w = inputs.workload("small", n_lr=n_lr)
     say(f"init_spectrum N={n_lr}")
@@ -91,7 +91,7 @@ def test_initial_spectrum_matches_oracle(dev, n_lr):
     assert rel_l2(H(O0), fo.initial_spectrum(img.astype(np.float64), w.upsample)) <= GRAD_TOL
 
 
-@pytest.mark.parametrize("n_lr", [64, 128, 256, 512])
+@pytest.mark.parametrize("n_lr", [64, 128, 192, 256, 384, 512])
 def test_pupil_matches_oracle(dev, n_lr):
     w = inputs.workload("small", n_lr=n_lr)
     say(f"pupil N={n_lr}")
@@ -114,7 +114,8 @@ def test_pupil_matches_oracle(dev, n_lr):
 # forward model and adjoint
 
 
-@pytest.mark.parametrize("n_lr,B", [(64, 8), (64, 11), (128, 5), (256, 16), (512, 3)])
+@pytest.mark.parametrize("n_lr,B", [(64, 8), (64, 11), (128, 5), (192, 16), (256, 16), (384, 7),
+                                    (512, 3)])
 def test_forward_matches_oracle(dev, n_lr, B):
     w = inputs.workload("small", n_lr=n_lr, n_side=9 if n_lr <= 128 else 7)
     say(f"forward N={n_lr} B={B}")
@@ -265,6 +266,44 @@ def test_step_pupil_parameter_gradients_match_oracle(dev):
     assert c1[0] == c0[0] and np.all(c1[1:] != c0[1:]) and z1 != 1.5
     P1 = fo.pupil(pr.mask, pr.zern, c1, z1, pr.kappa)
     assert np.abs(H(st.P) - P1).max() <= 2e-6
+
+
+@pytest.mark.parametrize("n_lr,n_side,B", [(192, 11, 16), (384, 7, 13)])
+def test_factor_three_sizes_backward_and_step_match_oracle(dev, n_lr, n_side, B):
+    """LR sizes 3 * 2^k (radix-12 transforms, HR 768 / 1536): gradients, loss and one
+    object + Zernike step against the oracle."""
+    w = inputs.workload("small", n_lr=n_lr, n_side=n_side, learn_zernike=True)
+    say(f"factor-3 size N={n_lr} grid {n_side}x{n_side} B={B}")
+    pr = oracle_problem(w, seed=2)
+    c0 = inputs.random_real((15,), seed=n_lr, lo=-0.2, hi=0.2)
+    c0[0] = 0.0
+    P = fo.pupil(pr.mask, pr.zern, c0.astype(np.float64), 0.0, pr.kappa)
+    leds = inputs.random_indices(w.n_led, B, seed=n_side)
+    plan, gO, gP, loss, ref = _backward_case(dev, w, pr.O0, P.astype(np.complex64), leds, pr.A,
+                                             None)
+    m = pr.mask.astype(bool)
+    assert rel_l2(gO, ref.g_O) <= GRAD_TOL
+    assert rel_l2(gP[m], ref.g_P[m]) <= GRAD_TOL
+    assert abs(loss - ref.loss) <= 1e-5 * ref.loss
+    st = fpm.State(plan, T(pr.O0, dev), c0, 0.0)
+    plan.step(st, problem.hparams(w), leds, T(pr.A, dev))
+    torch.cuda.synchronize()
+    ost = fo.init_state(pr.O0, coeffs0=c0.astype(np.float64))
+    cfg = fo.SolveConfig(lr_object=w.lr_object, lr_zernike=w.lr_zernike, learn_pupil=True)
+    oloss = fo.step(ost, cfg, pr.mask, pr.zern, pr.kappa, pr.shifts, leds, pr.A.astype(np.float64))
+    assert abs(float(H(st.loss)[0]) - oloss) <= 1e-5 * oloss
+    # Adam's first step is lr * sign(g) per real component: where the gradient is at
+    # its rounding level the sign may differ (a move of 2 lr); elsewhere the updates agree
+    def ri(z):
+        return np.stack([z.real, z.imag], -1).astype(np.float64)
+
+    O1, O1_ref, g = ri(H(st.O)), ri(ost.O), ri(ref.g_O)
+    decided = np.abs(g) > 1e-4 * np.abs(g).max()
+    diff = np.abs(O1 - O1_ref)
+    assert np.all(diff[decided] <= 1e-6 + 1e-5 * np.abs(O1_ref[decided]))
+    assert np.all(diff[~decided] <= 2 * w.lr_object * (1 + 1e-5))
+    assert np.count_nonzero(diff[~decided] > 1e-6) <= 1e-3 * diff.size
+    np.testing.assert_allclose(H(st.coeffs)[1:], ost.coeffs[1:], atol=1e-3 * w.lr_zernike)
 
 
 def test_step_is_deterministic(dev):

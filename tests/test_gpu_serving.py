@@ -1,0 +1,145 @@
+"""GPU tests of the tile server: results equal to a direct solve, bitwise the same
+alone and in a mix, FIFO admission within the HBM budget, argument checks."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2408_13782_amd import fpm, inputs, problem
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def say(msg):
+    print(f"[gpu] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def serving():
+    assert torch.cuda.is_available()
+    fpm.load()
+    from paper_2408_13782_amd import serving as sv
+    return sv
+
+
+@pytest.fixture(scope="module")
+def tiles(serving):
+    shapes = {(w.n_lr, w.n_side): w for w in inputs.serving_shapes()}
+    picked = [shapes[(128, 7)], shapes[(192, 7)], shapes[(256, 11)], shapes[(384, 7)]]
+    out = [serving.Tile(w, seed=i) for i, w in enumerate(picked)]
+    torch.cuda.synchronize()
+    return out
+
+
+def _outputs(tile):
+    M = tile.w.m_hr
+    return (torch.zeros((M, M), dtype=torch.complex64, device="cuda"),
+            torch.zeros(15, dtype=torch.float32, device="cuda"),
+            torch.zeros(1, dtype=torch.float64, device="cuda"))
+
+
+def _direct_solve(tile, req):
+    """The same solve through Plan.run on the default stream."""
+    w = tile.w
+    plan = fpm.Plan(w.n_lr, w.upsample, tile.shifts, w.batch, w.wavelength_um, w.na, w.mag,
+                    w.pixel_um)
+    O0 = plan.init_spectrum(tile.meas_amp[tile.centre].contiguous())
+    st = fpm.State(plan, O0)
+    plan.run(st, tile.hp, req.leds, req.sizes, tile.meas_amp)
+    torch.cuda.synchronize()
+    return st
+
+
+def test_result_equals_direct_solve_and_is_the_same_alone_and_in_a_mix(serving, tiles):
+    target = tiles[1]
+    say(f"alone vs mix, target N={target.w.n_lr} grid {target.w.n_side}")
+    O_a, c_a, l_a = _outputs(target)
+    with serving.Server(lanes=1) as sv:
+        req = serving.Request(target, seed=5, tag=0, O_out=O_a, coeffs_out=c_a, loss_out=l_a)
+        sv.submit(req)
+        sv.drain()
+        comps = sv.poll(0)
+    assert len(comps) == 1 and comps[0].status == 0 and comps[0].tag == 0
+    st = _direct_solve(target, req)
+    np.testing.assert_array_equal(O_a.cpu().numpy(), st.O.cpu().numpy())
+    np.testing.assert_array_equal(c_a.cpu().numpy(), st.coeffs.cpu().numpy())
+    np.testing.assert_array_equal(l_a.cpu().numpy(), st.loss.cpu().numpy())
+
+    O_m, c_m, l_m = _outputs(target)
+    with serving.Server(lanes=4) as sv:
+        others = []
+        for i in range(7):
+            t = tiles[i % len(tiles)]
+            O_o, c_o, l_o = _outputs(t)
+            others.append(serving.Request(t, seed=100 + i, tag=1 + i, O_out=O_o))
+        for r in others[:3]:
+            sv.submit(r)
+        sv.submit(serving.Request(target, seed=5, tag=99, O_out=O_m, coeffs_out=c_m,
+                                  loss_out=l_m))
+        for r in others[3:]:
+            sv.submit(r)
+        sv.drain()
+        comps = {c.tag: c for c in sv.poll(0)}
+        st_max = sv.stats()["max_running"]
+    assert len(comps) == 8 and all(c.status == 0 for c in comps.values())
+    assert st_max > 1                      # requests did overlap on the device
+    np.testing.assert_array_equal(O_m.cpu().numpy(), O_a.cpu().numpy())
+    np.testing.assert_array_equal(c_m.cpu().numpy(), c_a.cpu().numpy())
+    np.testing.assert_array_equal(l_m.cpu().numpy(), l_a.cpu().numpy())
+
+
+def test_admission_keeps_footprints_within_budget_in_fifo_order(serving, tiles):
+    t = tiles[0]
+    fp = serving.request_footprint(t)
+    say(f"admission: footprint {fp} bytes, budget 2.5x")
+    with serving.Server(lanes=4, budget_bytes=int(2.5 * fp)) as sv:
+        reqs = [serving.Request(t, seed=i, tag=i) for i in range(6)]
+        for r in reqs:
+            sv.submit(r)
+        sv.drain()
+        comps = sorted(sv.poll(0), key=lambda c: c.tag)
+        stats = sv.stats()
+        assert stats["max_running"] == 2
+        assert stats["bytes_in_use"] == 0 and stats["running"] == 0
+        assert all(c.status == 0 and c.footprint_bytes == fp for c in comps)
+        admits = [c.t_admit_ms for c in comps]
+        assert admits == sorted(admits)                    # first in, first out
+        # never more than 2 at once: sweep over admissions and completions
+        events = sorted([(c.t_admit_ms, 1) for c in comps] + [(c.t_done_ms, -1) for c in comps])
+        live = peak = 0
+        for _, step in events:
+            live += step
+            peak = max(peak, live)
+        assert peak == 2
+        with pytest.raises(fpm.FpmError):
+            big = tiles[3]
+            sv.submit(serving.Request(big, seed=0, tag=50))   # larger than the budget
+
+
+def test_invalid_request_is_refused_and_nothing_is_queued(serving, tiles):
+    t = tiles[0]
+    say("invalid requests")
+    with serving.Server(lanes=2) as sv:
+        bad = serving.Request(t, seed=1, tag=7)
+        bad.leds[3] = t.w.n_led          # LED id out of range
+        with pytest.raises(fpm.FpmError):
+            sv.submit(bad)
+        bad2 = serving.Request(t, seed=1, tag=8)
+        bad2.c.centre_led = -1
+        with pytest.raises(fpm.FpmError):
+            sv.submit(bad2)
+        assert sv.stats()["queued"] == 0 and sv.stats()["completed"] == 0
+
+
+def test_measure_reports_latency_and_throughput(serving):
+    say("serving measurement, 30 requests at rho = 0.9")
+    res = serving.measure(rates=(0.9,), n_requests=30, lanes=4, calib_requests=8)
+    assert res["mu_seq_per_s"] > 0
+    row = res["rates"][0]
+    for name in ("server", "sequential"):
+        r = row[name]
+        assert 0 < r["p50_ms"] <= r["p99_ms"] <= r["max_ms"]
+        assert r["requests_per_s"] > 0
+    assert row["sequential"]["max_running"] == 1

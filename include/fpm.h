@@ -298,6 +298,16 @@ int fpm_refocus(fpm_plan* plan, const fpm_c32* O, const float* z_um, int32_t nz,
  * and counts[k], then clears the record. All arrays are HOST memory.
  */
 int fpm_timing_enable(fpm_plan* plan, int32_t enable);
+/*
+ * While timing is enabled, issue every launch of kernel kind `kind` (the
+ * index of its name in fpm_timing_collect's list; -1: none) `reps` times back
+ * to back inside one event bracket, so that the bracket divided by reps is
+ * the kernel's own duration on the step's real operands (the count reported
+ * for the bracket is reps). Only fpm_step / fpm_run honour it. The repeated
+ * launches recompute or re-apply their step: the state they leave is not a
+ * valid optimisation state, so use a state whose results are discarded.
+ */
+int fpm_timing_repeat(fpm_plan* plan, int32_t kind, int32_t reps);
 int fpm_timing_collect(fpm_plan* plan, int32_t max_kinds, const char** names, double* total_ms,
                        int32_t* counts, int32_t* n_kinds);
 

@@ -100,6 +100,7 @@ constexpr size_t kMaxTimed = 65536;
 
 struct TimedLaunch {
   int kind;
+  int reps;     // launches inside the bracket
   hipEvent_t start, stop;
 };
 
@@ -132,6 +133,7 @@ struct fpm_plan {
   int* oob_ws = nullptr;      // window-clamp counter when the caller passes none
   unsigned* counters = nullptr;  // completion counter of pupil_grad's reduction
   bool timing = false;
+  int repeat_kind = -1, repeat_n = 1;   // timing: launches of this kind issued repeat_n times
   std::vector<TimedLaunch> timed;
   std::vector<hipEvent_t> event_pool;
 };
@@ -149,13 +151,17 @@ hipEvent_t pool_event(fpm_plan* p) {
   return e;
 }
 
-// Brackets one launch with events when the plan's timing is on.
+// Brackets one launch with events when the plan's timing is on. With a repeat
+// set for this kind (fpm_timing_repeat), the launch site issues the kernel
+// `reps` times back to back inside the bracket.
 struct Timed {
   fpm_plan* p;
   int kind;
   hipStream_t st;
   hipEvent_t start = nullptr;
+  int reps = 1;
   Timed(fpm_plan* plan, int k, hipStream_t s) : p(plan), kind(k), st(s) {
+    if (p->timing && p->repeat_kind == k) reps = p->repeat_n;
     if (p->timing && p->timed.size() < kMaxTimed) {
       start = pool_event(p);
       if (start && hipEventRecord(start, st) != hipSuccess) start = nullptr;
@@ -165,7 +171,7 @@ struct Timed {
     if (!start) return;
     hipEvent_t stop = pool_event(p);
     if (stop && hipEventRecord(stop, st) == hipSuccess) {
-      p->timed.push_back({kind, start, stop});
+      p->timed.push_back({kind, reps, start, stop});
     } else {
       p->event_pool.push_back(start);
       if (stop) p->event_pool.push_back(stop);
@@ -288,19 +294,21 @@ int launch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t
   const Disk dk = disk_of(p);
   {
     Timed tm(p, kRowsForward, st);
-    rows_forward<N><<<gr.rows(), kRowThreads, 0, st>>>(O, P, bt, dk, gr.row_chunks, p->X,
-                                                         p->twN, o.commit, p->staging, o.scal);
+    for (int r = 0; r < tm.reps; ++r)
+      rows_forward<N><<<gr.rows(), kRowThreads, 0, st>>>(O, P, bt, dk, gr.row_chunks, p->X,
+                                                           p->twN, o.commit, p->staging, o.scal);
   }
   {
     Timed tm(p, kCols, st);
-    cols<N, false><<<gr.cols(), ColLines<N>::value * ColPlan<N>::T, 0, st>>>(
-        p->X, A, gamma, bt, dk, gr.col_groups, o.loss ? p->part_loss : nullptr, nullptr, nullptr,
-        p->twN, 1.0f / p->M);
+    for (int r = 0; r < tm.reps; ++r)
+      cols<N, false><<<gr.cols(), ColLines<N>::value * ColPlan<N>::T, 0, st>>>(
+          p->X, A, gamma, bt, dk, gr.col_groups, o.loss ? p->part_loss : nullptr, nullptr,
+          nullptr, p->twN, 1.0f / p->M);
   }
   {
     Timed tm(p, kRowsBackward, st);
     const PupilGeom pg = pupil_geom(p);
-    switch (o.mode) {
+    for (int r = 0; r < tm.reps; ++r) switch (o.mode) {
       case kGradO:
         rows_backward<N, kGradO><<<gr.rows(), kRowThreads, 0, st>>>(
             p->X, O, P, bt, dk, pg, gr.row_chunks, gO, nullptr, nullptr, nullptr, p->twN);
@@ -842,7 +850,8 @@ int step_launches(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_
   const int extra = learn_p ? pupil_wgs(p) : 1;   // must match the kernel's n_pw
   {
     Timed tm(p, kAdamObject, st);
-    if (int rc = launch_update(p, a, p->n_tiles + extra, st)) return rc;
+    for (int r = 0; r < tm.reps; ++r)
+      if (int rc = launch_update(p, a, p->n_tiles + extra, st)) return rc;
   }
   FPM_HIP(hipGetLastError());
   s->t = t;
@@ -963,6 +972,15 @@ int fpm_timing_enable(fpm_plan* p, int32_t enable) {
   return FPM_OK;
 }
 
+int fpm_timing_repeat(fpm_plan* p, int32_t kind, int32_t reps) {
+  FPM_REQUIRE(p, "plan must not be NULL");
+  FPM_REQUIRE(kind >= -1 && kind < kKinds, "kind must be -1 or a kernel kind index");
+  FPM_REQUIRE(reps >= 1 && reps <= 1000, "reps must be in [1, 1000]");
+  p->repeat_kind = kind;
+  p->repeat_n = reps;
+  return FPM_OK;
+}
+
 int fpm_timing_collect(fpm_plan* p, int32_t max_kinds, const char** names, double* total_ms,
                        int32_t* counts, int32_t* n_kinds) {
   FPM_REQUIRE(p && names && total_ms && counts && n_kinds, "arguments must not be NULL");
@@ -981,7 +999,7 @@ int fpm_timing_collect(fpm_plan* p, int32_t max_kinds, const char** names, doubl
       rc = fail(FPM_EHIP, "reading a timing event failed");
     if (t.kind < n) {
       total_ms[t.kind] += ms;
-      counts[t.kind] += 1;
+      counts[t.kind] += t.reps;
     }
     p->event_pool.push_back(t.start);
     p->event_pool.push_back(t.stop);

@@ -91,6 +91,7 @@ EXPORTS = {
     "fpm_init_spectrum": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "fpm_refocus": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
     "fpm_timing_enable": [C.c_void_p, C.c_int32],
+    "fpm_timing_repeat": [C.c_void_p, C.c_int32, C.c_int32],
     "fpm_timing_collect": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                            C.POINTER(C.c_int32)],
 }
@@ -264,6 +265,7 @@ class Plan:
         _check(lib.fpm_plan_info(h, C.byref(info)))
         self.info = info
         self._lib = lib
+        self._kinds = self._read_kernel_kinds()
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
@@ -427,6 +429,27 @@ class Plan:
 
     def timing(self, enable: bool):
         _check(self._lib.fpm_timing_enable(self._h, int(bool(enable))))
+
+    def kernel_kinds(self) -> list:
+        """Names of the kernel kinds the timing calls report, in index order."""
+        return list(self._kinds)
+
+    def _read_kernel_kinds(self) -> list:
+        # a collection with nothing recorded: only the names come back
+        kmax = 32
+        names = (C.c_char_p * kmax)()
+        total = np.zeros(kmax, np.float64)
+        counts = np.zeros(kmax, np.int32)
+        nk = C.c_int32(0)
+        _check(self._lib.fpm_timing_collect(self._h, kmax, C.cast(names, C.c_void_p),
+                                            total.ctypes.data, counts.ctypes.data, C.byref(nk)))
+        return [names[i].decode() for i in range(nk.value)]
+
+    def timing_repeat(self, kind, reps: int):
+        """Issue launches of kernel `kind` (a name, or None for none) `reps` times
+        back to back while timing (fpm_timing_repeat); the state is not kept valid."""
+        idx = -1 if kind is None else self.kernel_kinds().index(kind)
+        _check(self._lib.fpm_timing_repeat(self._h, idx, int(reps)))
 
     def timing_collect(self) -> dict:
         """{kernel name: (total ms, launches)} since the last collection."""

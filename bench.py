@@ -126,6 +126,69 @@ def cpu_baseline(w, seconds: float):
                       f"numpy single thread, {dt:.1f} s"}
 
 
+def _psnr(x, ref) -> float:
+    import numpy as np
+    mse = float(np.mean((x - ref) ** 2))
+    peak = float(np.max(np.abs(ref)))
+    return float("inf") if mse == 0 else 10.0 * math.log10(peak * peak / mse)
+
+
+def ring_order(prob) -> "np.ndarray":
+    """LEDs from the centre outwards (by |k|, then by angle): the fixed order of
+    the sequential one-image-per-update baseline (Eq. 7)."""
+    import numpy as np
+    k = prob.k
+    return np.lexsort((np.arctan2(k[:, 0], k[:, 1]), np.round(np.hypot(k[:, 0], k[:, 1]), 9)))
+
+
+def batch_sweep(w, batches, epochs: int, log) -> dict:
+    """Random batches of several sizes (Eqs. 13-14) and the sequential fixed-order
+    loop (Eq. 7) on the same synthetic data: quality of the object after each
+    epoch against wall-clock time on the GPU (evaluation not timed)."""
+    import numpy as np
+    import torch
+    from paper_2408_13782_amd import fpm, inputs, problem
+    prob = problem.make_plan(w, max_batch=max(batches))
+    problem.simulate(prob, seed=0)
+    plan = prob.plan
+    o_true = plan.hr_transform(prob.O_true, -1).cpu().numpy()
+    O0 = problem.initial_spectrum(prob)
+    hp = problem.hparams(w)
+    runs = [("random", b) for b in batches] + [("sequential", 1)]
+    out = []
+    for mode, B in runs:
+        if mode == "random":
+            perms = inputs.led_permutations(w.n_led, epochs, seed=0)
+        else:
+            perms = np.tile(ring_order(prob), (epochs, 1)).astype(np.int32)
+        per_epoch = -(-w.n_led // B)
+        sched = problem.flatten_schedule(problem.schedule(perms, B))
+        st = fpm.State(plan, O0)
+        t_ms, amp_db, ph_db, loss = 0.0, [], [], []
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        for ep in range(epochs):
+            st.loss.zero_()
+            torch.cuda.synchronize()
+            flat, sizes = sched.span(ep * per_epoch, (ep + 1) * per_epoch)
+            e0.record()
+            plan.run(st, hp, flat, sizes, prob.meas_amp)
+            e1.record()
+            torch.cuda.synchronize()
+            t_ms += e0.elapsed_time(e1)
+            o = plan.hr_transform(st.O, -1).cpu().numpy()
+            o = o * np.exp(1j * np.angle(np.vdot(o, o_true)))       # global phase
+            amp_db.append(_psnr(np.abs(o), np.abs(o_true)))
+            ph_db.append(_psnr(np.angle(o), np.angle(o_true)))
+            loss.append(float(st.loss.cpu()[0]))
+        row = {"mode": mode, "batch": B, "steps_per_epoch": per_epoch,
+               "ms_per_epoch": t_ms / epochs, "total_ms": t_ms,
+               "amp_psnr_db": amp_db, "phase_psnr_db": ph_db, "epoch_loss": loss}
+        log(f"{mode} B={B}: {t_ms / epochs:.2f} ms/epoch, final amplitude {amp_db[-1]:.2f} dB, "
+            f"phase {ph_db[-1]:.2f} dB")
+        out.append(row)
+    return {"workload": w.name, "epochs": epochs, "runs": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +202,10 @@ def main():
                          "known traffic for calibrating HBM counters)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch-sweep", type=int, nargs="*", default=None,
+                    help="instead of the throughput line: quality vs time for these batch "
+                         "sizes and the sequential loop (e.g. --batch-sweep 1 4 8 16 32 64)")
+    ap.add_argument("--sweep-epochs", type=int, default=30)
     ap.add_argument("--serving-requests", type=int, default=150,
                     help="requests of the tile-serving latency measurement at rho = 0.9 "
                          "(0: skip)")
@@ -157,6 +224,9 @@ def main():
 
     torch.cuda.set_device(0)
     w = inputs.workload(args.workload)
+    if args.batch_sweep:
+        print(json.dumps(batch_sweep(w, args.batch_sweep, args.sweep_epochs, log)), flush=True)
+        return
     log(f"workload {w.name}: {w.n_side}x{w.n_side} LEDs, N={w.n_lr}, M={w.m_hr}, B={w.batch}")
     prob = problem.make_plan(w)
     problem.simulate(prob, seed=0)
@@ -253,6 +323,18 @@ def main():
         "per_kernel_mean_us": {k: v * 1e3 for k, v in timed.items()},
         "support_px": S, "union_px": U,
     }
+    # digital refocusing of the reconstruction: 16 distances in [-40, 40] um
+    z = torch.linspace(-40.0, 40.0, 16, dtype=torch.float32, device="cuda")
+    foc = torch.empty((16, plan.M, plan.M), dtype=torch.complex64, device="cuda")
+    plan.refocus(state.O, z, out=foc)
+    r0, r1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    r0.record()
+    for _ in range(5):
+        plan.refocus(state.O, z, out=foc)
+    r1.record()
+    torch.cuda.synchronize()
+    detail["refocus_16z_ms"] = r0.elapsed_time(r1) / 5
+    del foc
 
     result = {
         "metric": "LED-images fwd+bwd/sec (256²→1024²)" if w.name == "paper" else

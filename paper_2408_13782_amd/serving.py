@@ -246,11 +246,16 @@ def latency_stats(done, t0, requests, arrivals_ms) -> dict:
 
 def sequential_rate(tiles, n: int, seed: int = 1000) -> float:
     """Service rate (requests/s) of one-at-a-time solves on a saturated queue."""
+    return saturated_rate(tiles, n, lanes=1, seed=seed)
+
+
+def saturated_rate(tiles, n: int, lanes: int, seed: int = 1000) -> float:
+    """Requests/s with every request queued at once (the server's capacity)."""
     shapes, seeds = inputs.serving_stream(n, seed)
     reqs = [Request(tiles[s], sd, i) for i, (s, sd) in enumerate(zip(shapes, seeds))]
-    with Server(lanes=1) as sv:
+    with Server(lanes=lanes) as sv:
         for t in tiles:
-            sv.reserve(t, 1)
+            sv.reserve(t, lanes)
         warm_up(sv, tiles)
         for r in reqs:
             sv.submit(r)
@@ -308,12 +313,22 @@ def main(argv=None):
     ap.add_argument("--requests", type=int, default=2000)
     ap.add_argument("--lanes", type=int, default=4)
     ap.add_argument("--calib", type=int, default=60)
+    ap.add_argument("--capacity", type=int, nargs="*", default=None,
+                    help="instead: saturated throughput for these lane counts")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
-    res = measure(args.rates, args.requests, args.lanes, calib_requests=args.calib,
-                  log=lambda s: print(f"[serving] {s}", file=sys.stderr, flush=True))
+    log = lambda s: print(f"[serving] {s}", file=sys.stderr, flush=True)  # noqa: E731
+    if args.capacity:
+        tiles = make_tiles()
+        res = {"requests": args.requests, "capacity_per_s": {}}
+        for lanes in args.capacity:
+            r = saturated_rate(tiles, args.requests, lanes)
+            res["capacity_per_s"][lanes] = r
+            log(f"lanes={lanes}: {r:.1f} requests/s")
+    else:
+        res = measure(args.rates, args.requests, args.lanes, calib_requests=args.calib, log=log)
     line = json.dumps(res)
     if args.out:
         with open(args.out, "w") as f:

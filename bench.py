@@ -12,7 +12,8 @@ bright / dark field). Inputs are resident in HBM before timing starts.
 Prints one JSON line (rank 0):
   value        LED-images per second (fwd + bwd + update), whole job
   roofline     the dominant kernel: algorithmic work per launch / its mean
-               duration (HIP events on the launch stream) vs MI355X peak
+               duration (HIP events on the launch stream around 20 back-to-back
+               launches on a step's operands) vs MI355X peak
   cpu_baseline the FP64 oracle's steps on the same workload, host cores
 """
 from __future__ import annotations

@@ -259,7 +259,7 @@ Disk disk_of(const fpm_plan* p) {
   return d;
 }
 
-template <int N> constexpr int row_lines() { return kRowThreads / Plan1D<N>::T; }
+template <int N> constexpr int row_lines() { return kRowThreads / RowPlan<N>::T; }
 
 struct Grids {
   int slots, row_chunks, col_groups;

@@ -197,9 +197,9 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
       adam1(o[h].y, m[h].y, v[h].y, g[2 * h].y, a.c);
       adam1(o[h].z, m[h].z, v[h].z, g[2 * h + 1].x, a.c);
       adam1(o[h].w, m[h].w, v[h].w, g[2 * h + 1].y, a.c);
-      po[h] = o[h];
-      pm[h] = m[h];
-      pv[h] = v[h];
+      store_next4<N>(po + h, o[h]);
+      store_next4<N>(pm + h, m[h]);
+      store_next4<N>(pv + h, v[h]);
     }
     FPM_PROBE(3, 2);
     FPM_PROBE(3, 3);

@@ -39,8 +39,28 @@
 
 namespace fpm {
 
-constexpr int kRowThreads = 128;   // threads per workgroup in the row passes
+#ifndef FPM_ROW_THREADS
+#define FPM_ROW_THREADS 128
+#endif
+constexpr int kRowThreads = FPM_ROW_THREADS;   // threads per workgroup in the row passes
 constexpr int kXcds = 8;
+
+// Threads per row transform in the row passes (more threads per line than
+// the default plan: more waves in flight for the few rows of a batch).
+#ifndef FPM_ROW_T256
+#define FPM_ROW_T256 32
+#endif
+#ifndef FPM_ROW_T512
+#define FPM_ROW_T512 32
+#endif
+#ifndef FPM_ROW_T128
+#define FPM_ROW_T128 32
+#endif
+template <int N> struct RowT { static constexpr int value = DefaultT<N>::value; };
+template <> struct RowT<128> { static constexpr int value = FPM_ROW_T128; };
+template <> struct RowT<256> { static constexpr int value = FPM_ROW_T256; };
+template <> struct RowT<512> { static constexpr int value = FPM_ROW_T512; };
+template <int N> using RowPlan = PlanT<N, RowT<N>::value>;
 
 template <int N> struct ColLines { static constexpr int value = 16; };
 template <> struct ColLines<512> { static constexpr int value = 8; };
@@ -51,8 +71,16 @@ template <> struct ColLines<512> { static constexpr int value = 8; };
 #ifndef FPM_COL_T256
 #define FPM_COL_T256 32
 #endif
+#ifndef FPM_COL_T512
+#define FPM_COL_T512 64
+#endif
+#ifndef FPM_COL_T128
+#define FPM_COL_T128 32
+#endif
 template <int N> struct ColT { static constexpr int value = DefaultT<N>::value; };
+template <> struct ColT<128> { static constexpr int value = FPM_COL_T128; };
 template <> struct ColT<256> { static constexpr int value = FPM_COL_T256; };
+template <> struct ColT<512> { static constexpr int value = FPM_COL_T512; };
 template <int N> using ColPlan = PlanT<N, ColT<N>::value>;
 // LDS slots between consecutive elements of one column (padding by radix).
 template <int N> struct ColStride {
@@ -77,6 +105,36 @@ __device__ __forceinline__ bool xcd_map(int wg, int chunks, int B, int& b, int& 
   c = q - r * chunks;
   b = xcd + kXcds * r;
   return b < B;
+}
+
+// Stores of data that the next kernel reads (the intermediate rows, the
+// patches, the optimiser state). Up to N = 256 (spectrum state <= 24 MB) they
+// are non-temporal: they do not linger in the L2 as dirty lines to be written
+// back when the kernel ends (0.4 us per step measured at N = 256). At larger
+// sizes plain stores are faster (the state then stays in the memory-side cache
+// for the next step: 10 us per step at N = 512).
+template <int N> struct NtStores { static constexpr bool value = N <= 256; };
+
+template <int N>
+__device__ __forceinline__ void store_next(float2* p, float2 v) {
+  if constexpr (NtStores<N>::value) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+  } else {
+    *p = v;
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void store_next4(float4* p, float4 v) {
+  if constexpr (NtStores<N>::value) {
+    __builtin_nontemporal_store(v.x, &p->x);
+    __builtin_nontemporal_store(v.y, &p->y);
+    __builtin_nontemporal_store(v.z, &p->z);
+    __builtin_nontemporal_store(v.w, &p->w);
+  } else {
+    *p = v;
+  }
 }
 
 __device__ __forceinline__ void atomic_add_c(float2* p, float2 v) {
@@ -145,6 +203,63 @@ __device__ __forceinline__ double wave_sum(double v) {
   v += dpp_move<0x114>(v);
   v += dpp_move<0x118>(v);
   return ((read_lane(v, 15) + read_lane(v, 31)) + read_lane(v, 47)) + read_lane(v, 63);
+}
+
+template <int kCtrl>
+__device__ __forceinline__ float dpp_move_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), kCtrl, 0xF, 0xF, true));
+}
+
+// Zernike/defocus moment partials of one row-pass workgroup. Thread t of the
+// team of T threads that owns row `line` holds the six row sums
+// s = (sum g, sum g x, ..., sum g x^4, sum g kappa) over its elements; the
+// teams' totals are formed with in-row prefix sums (DPP row_shr, FP32), and
+// threads 0..15 expand them with the powers of the rows' y into the 16 moments
+// sum g x^a y^b (a + b <= 4, the monomial order of kZernMono) and sum g kappa,
+// summed over the workgroup's rows in FP64 and stored to part[blockIdx.x][16].
+// Every thread of the workgroup must call this (lanes outside the disk pass 0).
+template <int T, int L>
+__device__ __forceinline__ void row_moment_partials(float (&sv)[6], int row0, const Disk& dk,
+                                                    int half_n, float inv_r, double* part) {
+  static_assert(T == 8 || T == 16 || T == 32 || T == 64, "row team of 8 to 64 threads");
+  constexpr int kRows16 = L * T / 16;            // rows of 16 lanes in the workgroup
+  __shared__ float tot[kRows16 > L ? kRows16 : L][6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    float v = sv[j];
+    v += dpp_move_f<0x111>(v);
+    v += dpp_move_f<0x112>(v);
+    v += dpp_move_f<0x114>(v);
+    if constexpr (T >= 16) v += dpp_move_f<0x118>(v);
+    sv[j] = v;
+  }
+  // T <= 16: the team's last lane holds its total; T > 16: each row of 16 lanes'
+  // last lane holds that row's total
+  constexpr int kSeg = T < 16 ? T : 16;
+  if ((threadIdx.x % kSeg) == kSeg - 1) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) tot[threadIdx.x / kSeg][j] = sv[j];
+  }
+  __syncthreads();
+  const int k = threadIdx.x;
+  if (k < 16) {
+    // monomial k < 15 is x^a y^b with degree d = a + b: k = d (d + 1) / 2 + b
+    int d = 0;
+    while ((d + 1) * (d + 2) / 2 <= k) ++d;
+    const int pb = k < 15 ? k - d * (d + 1) / 2 : 0;
+    const int j = k < 15 ? d - pb : 5;
+    double acc = 0.0;
+    for (int l = 0; l < L; ++l) {
+      if (row0 + l >= dk.nrows) break;
+      double sj = 0.0;
+#pragma unroll
+      for (int q = 0; q < T / kSeg; ++q) sj += (double)tot[l * (T / kSeg) + q][j];
+      const double y = (double)(dk.ky_lo + row0 + l - half_n) * (double)inv_r;
+      for (int e = 0; e < pb; ++e) sj *= y;
+      acc += sj;
+    }
+    part[(size_t)blockIdx.x * 16 + k] = acc;
+  }
 }
 
 // Sum K per-thread values over the workgroup; thread k < K stores total k into
@@ -254,7 +369,7 @@ __global__ void __launch_bounds__(kRowThreads)
 rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch bt, Disk dk,
              int chunks, float2* __restrict__ X, const float2* __restrict__ tw, int commit,
              const float* __restrict__ staging, ScalarState scal) {
-  constexpr int T = Plan1D<N>::T;
+  constexpr int T = RowPlan<N>::T;
   constexpr int E = N / T;
   constexpr int L = kRowThreads / T;
   __shared__ float2 lds[L * RowLds<N>::kStride];
@@ -291,12 +406,12 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch b
     v[m] = in ? cmul(ov[m], pvv[m]) : make_float2(0.f, 0.f);
   }
   FPM_PROBE(0, 1);
-  Plan1D<N>::template run<+1>(v, t, lds + line * RowLds<N>::kStride, [](int n) { return RowLds<N>::at(n); }, lds_tw);
+  RowPlan<N>::template run<+1>(v, t, lds + line * RowLds<N>::kStride, [](int n) { return RowLds<N>::at(n); }, lds_tw);
   FPM_PROBE(0, 2);
   if (active) {
     float2* xr = X + ((size_t)b * N + ky) * N;
 #pragma unroll
-    for (int m = 0; m < E; ++m) xr[t + m * T] = v[m];
+    for (int m = 0; m < E; ++m) store_next<N>(xr + t + m * T, v[m]);
   }
   FPM_PROBE(0, 3);
 }
@@ -366,7 +481,7 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int ky = half_shift<N>(t + m * T);
-        if (ky >= dk.ky_lo && ky <= dk.ky_hi) xb[(size_t)ky * N + x] = cscale(v[m], inv_m);
+        if (ky >= dk.ky_lo && ky <= dk.ky_hi) store_next<N>(xb + (size_t)ky * N + x, cscale(v[m], inv_m));
       }
     }
   }
@@ -397,7 +512,7 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
               const float2* __restrict__ P, Batch bt, Disk dk, PupilGeom pg, int chunks,
               float2* __restrict__ gO, float2* __restrict__ gP, double* __restrict__ zpart,
               const float* __restrict__ kappa_tab, const float2* __restrict__ tw) {
-  constexpr int T = Plan1D<N>::T;
+  constexpr int T = RowPlan<N>::T;
   constexpr int E = N / T;
   constexpr int L = kRowThreads / T;
   constexpr bool kNeedC = MODE == kGradOP || MODE == kPatchZern;
@@ -412,9 +527,7 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
   const int rr = c * L + line;
   const bool active = rr < dk.nrows;
   const int ky = dk.ky_lo + (active ? rr : 0);
-  float zacc[kPar];
-#pragma unroll
-  for (int j = 0; j < kPar; ++j) zacc[j] = 0.f;
+  float zs[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};   // row sums of g_theta x^a, g_theta kappa
   if (live) {
     float2* xr = X + ((size_t)b * N + ky) * N;
     const int2 ext = disk_extent<N>(dk, ky);
@@ -439,7 +552,7 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
       }
     }
     FPM_PROBE(2, 1);
-    Plan1D<N>::template run<-1>(v, t, lds + line * RowLds<N>::kStride, [](int n) { return RowLds<N>::at(n); }, lds_tw);
+    RowPlan<N>::template run<-1>(v, t, lds + line * RowLds<N>::kStride, [](int n) { return RowLds<N>::at(n); }, lds_tw);
     FPM_PROBE(2, 2);
     if (active) {
       const float ir = (float)pg.inv_r;
@@ -454,7 +567,7 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
           if constexpr (MODE == kGradO || MODE == kGradOP) {
             atomic_add_c(gO + orow + kx, cmulc(p, g));
           } else {
-            xr[kx] = cmulc(p, g);   // this row was read whole into registers above
+            store_next<N>(xr + kx, cmulc(p, g));   // this row was read whole into registers above
           }
           if constexpr (MODE == kGradOP) {
             atomic_add_c(gP + (size_t)ky * N + kx, cmulc(cv[m], g));
@@ -474,17 +587,17 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
         }
       }
       if constexpr (MODE == kPatchZern) {
-        // moments sum g x^a y^b of this row, in the monomial order of kZernMono
-        const float y = (float)uy * ir, y2 = y * y, y3 = y2 * y, y4 = y3 * y;
-        zacc[0] = S0;  zacc[1] = S1;  zacc[2] = S0 * y;
-        zacc[3] = S2;  zacc[4] = S1 * y;  zacc[5] = S0 * y2;
-        zacc[6] = S3;  zacc[7] = S2 * y;  zacc[8] = S1 * y2;  zacc[9] = S0 * y3;
-        zacc[10] = S4; zacc[11] = S3 * y; zacc[12] = S2 * y2; zacc[13] = S1 * y3; zacc[14] = S0 * y4;
-        zacc[15] = SK;
+        zs[0] = S0;
+        zs[1] = S1;
+        zs[2] = S2;
+        zs[3] = S3;
+        zs[4] = S4;
+        zs[5] = SK;
       }
     }
   }
-  if constexpr (MODE == kPatchZern) block_partials<kPar>(zacc, zpart);
+  if constexpr (MODE == kPatchZern)
+    row_moment_partials<T, L>(zs, c * L, dk, N / 2, (float)pg.inv_r, zpart);
   FPM_PROBE(2, 3);
 }
 

@@ -115,7 +115,7 @@ __global__ void __launch_bounds__(kRowThreads)
 rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Batch bt, Disk dk,
                  const SubSlot* __restrict__ sub, int chunks, float2* __restrict__ X,
                  const float2* __restrict__ tw) {
-  constexpr int T = Plan1D<N>::T;
+  constexpr int T = RowPlan<N>::T;
   constexpr int E = N / T;
   constexpr int L = kRowThreads / T;
   __shared__ float2 lds[L * RowLds<N>::kStride];
@@ -141,7 +141,7 @@ rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Bat
     const bool in = active && kx0 >= ext.x && kx0 <= ext.y;
     v[m] = in ? cmul(C, prow[kx]) : make_float2(0.f, 0.f);
   }
-  Plan1D<N>::template run<+1>(v, t, lds + line * RowLds<N>::kStride,
+  RowPlan<N>::template run<+1>(v, t, lds + line * RowLds<N>::kStride,
                               [](int n) { return RowLds<N>::at(n); }, lds_tw);
   if (active) {
     float2* xr = X + ((size_t)b * N + ky) * N;
@@ -158,7 +158,7 @@ rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
                   const float2* __restrict__ P, Batch bt, Disk dk, PupilGeom pg,
                   const SubSlot* __restrict__ sub, int chunks, double* __restrict__ part,
                   const float* __restrict__ kappa_tab, const float2* __restrict__ tw) {
-  constexpr int T = Plan1D<N>::T;
+  constexpr int T = RowPlan<N>::T;
   constexpr int E = N / T;
   constexpr int L = kRowThreads / T;
   __shared__ float2 lds[L * RowLds<N>::kStride];
@@ -180,7 +180,7 @@ rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = xr[t + m * T];
-    Plan1D<N>::template run<-1>(v, t, lds + line * RowLds<N>::kStride,
+    RowPlan<N>::template run<-1>(v, t, lds + line * RowLds<N>::kStride,
                                 [](int n) { return RowLds<N>::at(n); }, lds_tw);
     if (active) {
       const float2* prow = P + (size_t)ky * N;

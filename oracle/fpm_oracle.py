@@ -302,19 +302,43 @@ class Grads:
     g_gamma: np.ndarray  # per LED in the batch
 
 
-def loss_and_grads(O, P, shifts, leds, meas_amp, gamma=None) -> Grads:
-    """Amplitude loss of one batch and its real gradients (Eqs. 5 and 13).
+def residual(psi, A, gamma_b: float, loss: str = "amplitude"):
+    """Per-image loss terms of Eq. 5 and the real gradient with respect to psi.
 
-    L = sum_b sum_r (sqrt(gamma_b) |psi_b(r)| - A_b(r))^2, summed (not averaged)
-    over the B images of the batch, as the update of Eq. (13) sums the B
-    per-image gradients. Each image contributes:
+    amplitude (Eq. 5 with L2 on amplitudes):  e = sqrt(gamma)|psi| - A,
+        L_b = sum e^2, g_psi = 2 sqrt(gamma) e psi/|psi| (0 where psi = 0),
+        dL_b/dgamma = sum e |psi| / sqrt(gamma);
+    intensity (Eq. 4): e = gamma |psi|^2 - A^2,
+        L_b = sum e^2, g_psi = 4 gamma e psi, dL_b/dgamma = 2 sum e |psi|^2.
+    Returns (L_b, g_psi, dL_b/dgamma).
+    """
+    A = np.asarray(A, dtype=np.float64)
+    if loss == "amplitude":
+        sg = math.sqrt(gamma_b)
+        a = np.abs(psi)
+        e = sg * a - A
+        unit = np.zeros_like(psi)
+        nz = a > 0
+        unit[nz] = psi[nz] / a[nz]
+        return float(np.sum(e * e)), 2.0 * sg * e * unit, float(np.sum(e * a)) / sg
+    if loss == "intensity":
+        q = np.abs(psi) ** 2
+        e = gamma_b * q - A * A
+        return float(np.sum(e * e)), 4.0 * gamma_b * e * psi, 2.0 * float(np.sum(e * q))
+    raise ValueError(f"unknown loss {loss!r}")
 
-      e     = sqrt(gamma) |psi| - A
-      g_psi = 2 sqrt(gamma) e psi / |psi|          (0 where psi = 0)
+
+def loss_and_grads(O, P, shifts, leds, meas_amp, gamma=None, loss: str = "amplitude") -> Grads:
+    """Loss of one batch and its real gradients (Eqs. 4-5 and 13).
+
+    Amplitude form: L = sum_b sum_r (sqrt(gamma_b) |psi_b(r)| - A_b(r))^2, summed
+    (not averaged) over the B images of the batch, as the update of Eq. (13)
+    sums the B per-image gradients (intensity form: see `residual`). Each image
+    contributes, with g_psi from `residual`:
+
       g_Phi = (1/M) fftshift(fft2(g_psi))          (adjoint of lr_field)
       g_O[w_b + u] += conj(P[u]) g_Phi[u]
       g_P[u]       += conj(C_b[u]) g_Phi[u]
-      dL/dgamma_b   = sum_r e |psi| / sqrt(gamma)
     """
     n = P.shape[0]
     m = O.shape[0]
@@ -326,18 +350,12 @@ def loss_and_grads(O, P, shifts, leds, meas_amp, gamma=None) -> Grads:
         rows, cols = window_indices(m, n, shifts[led])
         C = O[np.ix_(rows, cols)]
         psi = (n * n / m) * np.fft.ifft2(np.fft.ifftshift(C * P))
-        a = np.abs(psi)
-        sg = 1.0 if gamma is None else math.sqrt(float(gamma[led]))
-        e = sg * a - np.asarray(meas_amp[led], dtype=np.float64)
-        total += float(np.sum(e * e))
-        unit = np.zeros_like(psi)
-        nz = a > 0
-        unit[nz] = psi[nz] / a[nz]
-        g_psi = 2.0 * sg * e * unit
+        gb = 1.0 if gamma is None else float(gamma[led])
+        lb, g_psi, g_gamma[b] = residual(psi, meas_amp[led], gb, loss)
+        total += lb
         g_C, g_Pb = field_adjoint(g_psi, P, C, m)
         g_O[np.ix_(rows, cols)] += g_C
         g_P += g_Pb
-        g_gamma[b] = float(np.sum(e * a)) / sg
     return Grads(total, g_O, g_P, g_gamma)
 
 
@@ -411,7 +429,8 @@ class GeneralGrads:
     g_shift: np.ndarray      # [B, 2] dL/ds_b (row, col)
 
 
-def loss_and_grads_subpixel(O, P, shifts, leds, meas_amp, gamma=None) -> GeneralGrads:
+def loss_and_grads_subpixel(O, P, shifts, leds, meas_amp, gamma=None,
+                            loss: str = "amplitude") -> GeneralGrads:
     """Loss and gradients with fractional LED offsets (bilinear crop).
 
     Same loss as loss_and_grads; with integer offsets the two agree. Also the
@@ -428,18 +447,12 @@ def loss_and_grads_subpixel(O, P, shifts, leds, meas_amp, gamma=None) -> General
     for b, led in enumerate(leds):
         C, (t00, t01, t10, t11), a, r0, c0 = crop_bilinear(O, n, shifts[led])
         psi = (n * n / m) * np.fft.ifft2(np.fft.ifftshift(C * P))
-        amp = np.abs(psi)
-        sg = 1.0 if gamma is None else math.sqrt(float(gamma[led]))
-        e = sg * amp - np.asarray(meas_amp[led], dtype=np.float64)
-        total += float(np.sum(e * e))
-        unit = np.zeros_like(psi)
-        nz = amp > 0
-        unit[nz] = psi[nz] / amp[nz]
-        g_psi = 2.0 * sg * e * unit
+        gb = 1.0 if gamma is None else float(gamma[led])
+        lb, g_psi, g_gamma[b] = residual(psi, meas_amp[led], gb, loss)
+        total += lb
         g_C, g_Pb = field_adjoint(g_psi, P, C, m)
         scatter_bilinear(g_O, g_C, a, r0, c0)
         g_P += g_Pb
-        g_gamma[b] = float(np.sum(e * amp)) / sg
         dC_dy = (1 - a[1]) * (t10 - t00) + a[1] * (t11 - t01)
         dC_dx = (1 - a[0]) * (t01 - t00) + a[0] * (t11 - t10)
         g_shift[b, 0] = float(np.sum(np.real(np.conj(g_C) * dC_dy)))
@@ -497,7 +510,8 @@ class MultiGrads:
 
 
 def multiparam_loss_and_grads(O, coeffs, z_um, geom, gamma, leds, meas_amp, optics: Optics,
-                              n_side, pitch_mm, height_mm, mask, zern, kappa) -> MultiGrads:
+                              n_side, pitch_mm, height_mm, mask, zern, kappa,
+                              loss: str = "amplitude") -> MultiGrads:
     """Loss of one batch as a function of every learned group (Sec. 2.2, Eq. 3).
 
     Object spectrum, pupil Zernike coefficients and defocus, LED-array geometry
@@ -506,7 +520,7 @@ def multiparam_loss_and_grads(O, coeffs, z_um, geom, gamma, leds, meas_amp, opti
     """
     P = pupil(mask, zern, coeffs, z_um, kappa)
     s, J = led_shifts_and_jacobian(optics, n_side, pitch_mm, height_mm, geom)
-    gr = loss_and_grads_subpixel(O, P, s, leds, meas_amp, gamma)
+    gr = loss_and_grads_subpixel(O, P, s, leds, meas_amp, gamma, loss)
     g_c, g_z, _ = pupil_param_grads(gr.g_P, P, zern, kappa)
     g_geom = np.zeros(4)
     g_gamma = np.zeros(len(s))
@@ -611,6 +625,7 @@ class SolveConfig:
     lr_z: float = 0.1
     learn_pupil: bool = False   # Zernike coefficients
     learn_z: bool = False
+    loss: str = "amplitude"     # or "intensity" (Eq. 4)
     beta1: float = 0.9
     beta2: float = 0.999
     eps: float = 1e-8
@@ -642,7 +657,7 @@ def step(state: SolveState, cfg: SolveConfig, mask, zern, kappa, shifts, leds, m
          gamma=None):
     """One random-batch update: gradients summed over the batch, then Adam."""
     P = pupil(mask, zern, state.coeffs, state.z_um, kappa)
-    gr = loss_and_grads(state.O, P, shifts, leds, meas_amp, gamma)
+    gr = loss_and_grads(state.O, P, shifts, leds, meas_amp, gamma, cfg.loss)
     state.t += 1
     t = state.t
     state.O, state.m_O, state.v_O = adam_update(state.O, gr.g_O, state.m_O, state.v_O, t,

@@ -476,3 +476,65 @@ def test_refocus_of_a_plane_wave_is_a_phase_shift():
     kz = math.sqrt(1 / opt.wavelength_um ** 2 - k2)
     want = o * np.exp(2j * np.pi * z * (kz - 1 / opt.wavelength_um))
     np.testing.assert_allclose(fo.refocus(fo.spectrum(o), [z], opt)[0], want, atol=1e-11)
+
+
+# ---------------------------------------------------------------------------
+# Intensity-L2 loss (Eq. 4), the loss variant of Eq. 5's family
+
+
+def _iloss(O, P, shifts, leds, A, gamma):
+    return fo.loss_and_grads(O, P, shifts, leds, A, gamma, loss="intensity").loss
+
+
+def test_intensity_loss_value_is_eq4():
+    O, P, mask, shifts, A, gamma, _ = _random_problem(seed=21)
+    leds = [0, 3, 4]
+    I_model = fo.forward_intensities(O, P, shifts, leds, gamma)      # gamma |psi|^2
+    want = float(np.sum((I_model - A[leds] ** 2) ** 2))
+    assert abs(_iloss(O, P, shifts, leds, A, gamma) - want) <= 1e-12 * want
+
+
+def test_intensity_loss_gradients_match_central_differences():
+    O, P, mask, shifts, A, gamma, _ = _random_problem(seed=22)
+    leds = [1, 2, 4]
+    gr = fo.loss_and_grads(O, P, shifts, leds, A, gamma, loss="intensity")
+    rng = np.random.default_rng(3)
+    h = 1e-4
+    for _ in range(3):
+        D = rng.standard_normal(O.shape) + 1j * rng.standard_normal(O.shape)
+        D /= np.linalg.norm(D)
+        fd = (_iloss(O + h * D, P, shifts, leds, A, gamma)
+              - _iloss(O - h * D, P, shifts, leds, A, gamma)) / (2 * h)
+        an = np.real(np.vdot(gr.g_O, D))
+        assert abs(fd - an) <= 1e-6 * abs(an)
+    D = rng.standard_normal(P.shape) + 1j * rng.standard_normal(P.shape)
+    D /= np.linalg.norm(D)
+    fd = (_iloss(O, P + h * D, shifts, leds, A, gamma)
+          - _iloss(O, P - h * D, shifts, leds, A, gamma)) / (2 * h)
+    assert abs(fd - np.real(np.vdot(gr.g_P, D))) <= 1e-6 * abs(fd)
+    for b, led in enumerate(leds):
+        gp = gamma.copy(); gp[led] += h
+        gm = gamma.copy(); gm[led] -= h
+        fd = (_iloss(O, P, shifts, leds, A, gp) - _iloss(O, P, shifts, leds, A, gm)) / (2 * h)
+        assert abs(fd - gr.g_gamma[b]) <= 1e-6 * abs(gr.g_gamma[b])
+
+
+def test_intensity_loss_is_zero_with_zero_gradient_at_the_truth():
+    O, P, mask, shifts, _, gamma, _ = _random_problem(seed=23)
+    A = fo.forward_amplitudes(O, P, shifts, range(5), gamma)
+    gr = fo.loss_and_grads(O, P, shifts, [0, 2, 4], A, gamma, loss="intensity")
+    assert gr.loss < 1e-20
+    assert np.abs(gr.g_O).max() < 1e-10 and np.abs(gr.g_gamma).max() < 1e-10
+
+
+def test_intensity_and_amplitude_gradients_agree_in_direction_near_the_truth():
+    """With e small, 4 gamma e psi = 2 sqrt(gamma)|psi| (sqrt(gamma)|psi| + A) e_amp psi/|psi|
+    ~ 4 A^2 x (amplitude gradient / 2): a slightly perturbed object gives gradients
+    with a positive inner product (both descend towards the truth)."""
+    O, P, mask, shifts, _, gamma, _ = _random_problem(seed=24)
+    A = fo.forward_amplitudes(O, P, shifts, range(5), gamma)
+    O2 = O + 1e-3 * inputs.random_complex(O.shape, seed=25).astype(np.complex128)
+    ga = fo.loss_and_grads(O2, P, shifts, [0, 1, 2], A, gamma).g_O
+    gi = fo.loss_and_grads(O2, P, shifts, [0, 1, 2], A, gamma, loss="intensity").g_O
+    cos = np.real(np.vdot(ga, gi)) / (np.linalg.norm(ga) * np.linalg.norm(gi))
+    assert cos > 0.5

@@ -101,6 +101,16 @@ typedef struct {
  */
 int fpm_plan_create(const fpm_desc* desc, const int32_t* shifts_host, fpm_plan** plan);
 int fpm_plan_destroy(fpm_plan* plan);
+
+/*
+ * Loss of every later call on the plan (Eqs. 4-5; default amplitude):
+ *   FPM_LOSS_AMPLITUDE: L = sum (sqrt(gamma)|psi| - A)^2, as stated below;
+ *   FPM_LOSS_INTENSITY: L = sum (gamma |psi|^2 - A^2)^2 (Eq. 4 with I = A^2),
+ *     g_psi = 4 gamma e psi with e = gamma |psi|^2 - A^2, dL/dgamma = 2 sum e |psi|^2.
+ * The measured input stays the amplitude A = sqrt(I) either way.
+ */
+enum { FPM_LOSS_AMPLITUDE = 0, FPM_LOSS_INTENSITY = 1 };
+int fpm_plan_set_loss(fpm_plan* plan, int32_t kind);
 int fpm_plan_info(const fpm_plan* plan, fpm_info* info);
 const char* fpm_strerror(int code);
 const char* fpm_last_error(void);

@@ -132,6 +132,7 @@ struct fpm_plan {
   float2* P_ws = nullptr;     // [N][N] pupil built by fpm_loss_grad
   int* oob_ws = nullptr;      // window-clamp counter when the caller passes none
   unsigned* counters = nullptr;  // completion counter of pupil_grad's reduction
+  int loss_kind = FPM_LOSS_AMPLITUDE;
   bool timing = false;
   int repeat_kind = -1, repeat_n = 1;   // timing: launches of this kind issued repeat_n times
   std::vector<TimedLaunch> timed;
@@ -240,6 +241,7 @@ Batch batch_of(const fpm_plan* p, const int32_t* leds, int B) {
   Batch bt{};
   bt.B = B;
   bt.M = p->M;
+  bt.intensity = p->loss_kind == FPM_LOSS_INTENSITY;
   const int base = p->M / 2 - p->N / 2;
   for (int b = 0; b < B; ++b) {
     const int2 s = p->shifts_h[leds[b]];
@@ -653,6 +655,14 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
 int fpm_plan_destroy(fpm_plan* p) {
   if (!p) return FPM_OK;
   plan_free(p);
+  return FPM_OK;
+}
+
+int fpm_plan_set_loss(fpm_plan* p, int32_t kind) {
+  FPM_REQUIRE(p, "plan must not be NULL");
+  FPM_REQUIRE(kind == FPM_LOSS_AMPLITUDE || kind == FPM_LOSS_INTENSITY,
+              "kind must be FPM_LOSS_AMPLITUDE or FPM_LOSS_INTENSITY");
+  p->loss_kind = kind;
   return FPM_OK;
 }
 

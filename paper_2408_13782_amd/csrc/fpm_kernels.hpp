@@ -150,6 +150,7 @@ constexpr int kMaxSlots = 64;
 struct Batch {
   int B;
   int M;
+  int intensity;   // 0: amplitude loss (Eq. 5 form), 1: intensity loss (Eq. 4)
   int led[kMaxSlots];
   int2 win[kMaxSlots];
 };
@@ -469,11 +470,22 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const float2 psi = cscale(v[m], inv_m);
-        const float a = sqrtf(psi.x * psi.x + psi.y * psi.y);
-        const float e = sg * a - a_meas[m];
-        acc += e * e;
-        if constexpr (kGamma) acc_ea += e * a;
-        const float f = a > 0.f ? 2.f * sg * e / a : 0.f;
+        const float q = psi.x * psi.x + psi.y * psi.y;
+        float f;
+        if (bt.intensity) {
+          // e = gamma |psi|^2 - A^2, g_psi = 4 gamma e psi; dL/dgamma = 2 sum e |psi|^2
+          const float e = sg * sg * q - a_meas[m] * a_meas[m];
+          acc += e * e;
+          if constexpr (kGamma) acc_ea += e * q;
+          f = 4.f * sg * sg * e;
+        } else {
+          // e = sqrt(gamma) |psi| - A, g_psi = 2 sqrt(gamma) e psi/|psi|
+          const float a = sqrtf(q);
+          const float e = sg * a - a_meas[m];
+          acc += e * e;
+          if constexpr (kGamma) acc_ea += e * a;
+          f = a > 0.f ? 2.f * sg * e / a : 0.f;
+        }
         v[m] = cscale(psi, f);
       }
       ColPlan<N>::template run<-1>(v, t, lds, lay, lds_tw);

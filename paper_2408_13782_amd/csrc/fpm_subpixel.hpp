@@ -276,7 +276,7 @@ gather_dense(const float2* __restrict__ X, Batch bt, Disk dk, const SubSlot* __r
 
 // Final sums of a loss-and-gradient call, in fixed order (one workgroup).
 struct ReduceArgs {
-  const double* col_part;    // [col_wgs][2]: loss, sum e |psi|
+  const double* col_part;    // [col_wgs][2]: loss, sum e |psi| (intensity loss: e |psi|^2)
   int col_wgs, col_chunks;
   const double* row_part;    // [row_wgs][kSubPar]
   int row_wgs, row_chunks;
@@ -344,8 +344,12 @@ __global__ void __launch_bounds__(256) loss_grad_reduce(ReduceArgs a) {
     if (a.g_gamma) {
       for (int b = 0; b < a.bt.B; ++b) {
         const int led = a.bt.led[b];
-        const double sg = a.gamma ? sqrt((double)a.gamma[led]) : 1.0;
-        a.g_gamma[led] += ea[b] / sg;
+        if (a.bt.intensity) {
+          a.g_gamma[led] += 2.0 * ea[b];
+        } else {
+          const double sg = a.gamma ? sqrt((double)a.gamma[led]) : 1.0;
+          a.g_gamma[led] += ea[b] / sg;
+        }
       }
     }
   }

@@ -92,6 +92,7 @@ EXPORTS = {
     "fpm_refocus": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
     "fpm_timing_enable": [C.c_void_p, C.c_int32],
     "fpm_timing_repeat": [C.c_void_p, C.c_int32, C.c_int32],
+    "fpm_plan_set_loss": [C.c_void_p, C.c_int32],
     "fpm_timing_collect": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                            C.POINTER(C.c_int32)],
 }
@@ -266,6 +267,15 @@ class Plan:
         self.info = info
         self._lib = lib
         self._kinds = self._read_kernel_kinds()
+
+    LOSSES = {"amplitude": 0, "intensity": 1}
+
+    def set_loss(self, kind: str):
+        """Loss of later calls: 'amplitude' (default) or 'intensity' (fpm_plan_set_loss)."""
+        if kind not in self.LOSSES:
+            raise FpmError(f"unknown loss {kind!r}")
+        _check(self._lib.fpm_plan_set_loss(self._h, self.LOSSES[kind]))
+        self.loss_kind = kind
 
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:

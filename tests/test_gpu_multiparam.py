@@ -135,6 +135,32 @@ def test_loss_grad_without_geometry_matches_the_nearest_path(dev, case):
     assert np.all(H(g["g_geom"]) == 0)
 
 
+def test_intensity_loss_grad_matches_oracle(dev, case):
+    say("multi-parameter gradients, intensity loss")
+    w = case.w
+    plan = case.plan()
+    plan.set_loss("intensity")
+    c = inputs.random_real((15,), seed=31, lo=-0.2, hi=0.2).astype(np.float32)
+    z = np.array([-0.7], np.float32)
+    geom = 0.4 * case.geom_true
+    gamma = inputs.random_real((w.n_led,), seed=32, lo=0.8, hi=1.2)
+    leds = inputs.random_indices(w.n_led, 9, seed=33)
+    g = plan.loss_grad(case.grid, T(case.O0, dev), leds, T(case.A, dev), coeffs=T(c, dev),
+                       z_um=T(z, dev), geom=T(geom, dev), gamma=T(gamma, dev))
+    torch.cuda.synchronize()
+    ref = fo.multiparam_loss_and_grads(case.O0.astype(np.complex128), c.astype(np.float64),
+                                       float(z[0]), geom, gamma.astype(np.float64), leds,
+                                       case.A.astype(np.float64), case.opt, w.n_side,
+                                       w.pitch_mm, w.height_mm, case.mask, case.zern,
+                                       case.kappa, loss="intensity")
+    assert abs(float(H(g["loss"])[0]) - ref.loss) <= 1e-5 * ref.loss
+    assert rel_l2(H(g["g_O"]), ref.g_O) <= GRAD_TOL
+    np.testing.assert_allclose(H(g["g_gamma"]), ref.g_gamma, rtol=1e-5,
+                               atol=1e-6 * np.abs(ref.g_gamma).max())
+    assert rel_l2(H(g["g_par"])[1:15], ref.g_coeffs[1:]) <= 1e-4
+    assert rel_l2(H(g["g_geom"]), ref.g_geom) <= 1e-4
+
+
 def test_windows_leaving_the_grid_are_counted_not_read(dev, case):
     say("geometry pushing windows off the HR grid")
     w = case.w
@@ -222,23 +248,36 @@ def test_autograd_function_matches_float32_finite_differences(dev, case):
             assert abs(fd - gvec[k]) <= tol, (name, k, fd, gvec[k], tol)
 
 
-def test_torch_adam_solve_through_the_autograd_function_matches_oracle(dev, case):
-    """Ten joint updates (object, Zernikes, defocus, geometry) with torch Adam over the
-    library's gradients, against the same updates with the oracle's FP64 gradients."""
+OPTIMISERS = {
+    "Adam": lambda groups: torch.optim.Adam(groups),
+    "AdamW": lambda groups: torch.optim.AdamW(groups, weight_decay=1e-2),
+    "NAdam": lambda groups: torch.optim.NAdam(groups),
+    "RMSprop": lambda groups: torch.optim.RMSprop(groups),
+}
+
+
+@pytest.mark.parametrize("opt_name", list(OPTIMISERS))
+def test_torch_optimiser_solve_through_the_autograd_function_matches_oracle(dev, case, opt_name):
+    """Ten joint updates (object, Zernikes, defocus, geometry) with a torch optimiser
+    over the library's gradients, against the same optimiser fed the oracle's FP64
+    gradients (the optimiser variants of Sec. 2.2)."""
     from paper_2408_13782_amd.autograd import FPMLoss, LossContext
-    say("multi-parameter torch-Adam solve vs oracle")
+    say(f"multi-parameter torch {opt_name} solve vs oracle")
     w = case.w
     plan = case.plan()
     perms = inputs.led_permutations(w.n_led, 2, seed=5)
     sched = fo.batches_from_permutations(perms, w.batch)[:10]
-    lrs = dict(O=w.lr_object, c=w.lr_zernike, z=w.lr_z, geom=1e-3)
+    # RMSprop's first steps are 1/sqrt(1 - alpha) = 10 times lr: scaled to Adam's size
+    scale = 0.1 if opt_name == "RMSprop" else 1.0
+    lrs = dict(O=scale * w.lr_object, c=scale * w.lr_zernike, z=scale * w.lr_z, geom=scale * 1e-3)
     # GPU: torch tensors on the device
     O = T(case.O0, dev).requires_grad_(True)
     c = torch.zeros(15, dtype=torch.float32, device=dev, requires_grad=True)
     z = torch.zeros(1, dtype=torch.float32, device=dev, requires_grad=True)
     geom = torch.zeros(4, dtype=torch.float64, device=dev, requires_grad=True)
-    opt = torch.optim.Adam([dict(params=[O], lr=lrs["O"]), dict(params=[c], lr=lrs["c"]),
-                            dict(params=[z], lr=lrs["z"]), dict(params=[geom], lr=lrs["geom"])])
+    make = OPTIMISERS[opt_name]
+    opt = make([dict(params=[O], lr=lrs["O"]), dict(params=[c], lr=lrs["c"]),
+                dict(params=[z], lr=lrs["z"]), dict(params=[geom], lr=lrs["geom"])])
     A = T(case.A, dev)
     for leds in sched:
         opt.zero_grad()
@@ -251,8 +290,8 @@ def test_torch_adam_solve_through_the_autograd_function_matches_oracle(dev, case
     c_r = torch.zeros(15, dtype=torch.float64, requires_grad=True)
     z_r = torch.zeros(1, dtype=torch.float64, requires_grad=True)
     g_r = torch.zeros(4, dtype=torch.float64, requires_grad=True)
-    opt_r = torch.optim.Adam([dict(params=[O_r], lr=lrs["O"]), dict(params=[c_r], lr=lrs["c"]),
-                              dict(params=[z_r], lr=lrs["z"]), dict(params=[g_r], lr=lrs["geom"])])
+    opt_r = make([dict(params=[O_r], lr=lrs["O"]), dict(params=[c_r], lr=lrs["c"]),
+                  dict(params=[z_r], lr=lrs["z"]), dict(params=[g_r], lr=lrs["geom"])])
     for leds in sched:
         gr = case.oracle(O_r.detach().numpy(), c_r.detach().numpy(), float(z_r.detach()[0]),
                          g_r.detach().numpy(), None, leds)

@@ -193,6 +193,51 @@ def test_backward_with_aberrations_and_gamma(dev):
     assert abs(loss - ref.loss) <= 1e-5 * ref.loss
 
 
+@pytest.mark.parametrize("name,B", [("small", 8), ("paper", 16)])
+def test_intensity_loss_backward_and_step_match_oracle(dev, name, B):
+    """The intensity-L2 loss (Eq. 4) selected on the plan: gradients, loss and one
+    step against the oracle's intensity form."""
+    w = inputs.workload(name)
+    say(f"intensity loss {name} B={B}")
+    pr = oracle_problem(w, seed=3)
+    P = fo.pupil(pr.mask, pr.zern, np.zeros(15), 0.0, pr.kappa).astype(np.complex64)
+    leds = inputs.random_indices(w.n_led, B, seed=5)
+    gamma = inputs.random_real((w.n_led,), seed=6, lo=0.8, hi=1.2)
+    plan = make_plan(w, pr.shifts, B)
+    plan.set_loss("intensity")
+    gO = torch.zeros((w.m_hr, w.m_hr), dtype=torch.complex64, device=dev)
+    gP = torch.zeros((w.n_lr, w.n_lr), dtype=torch.complex64, device=dev)
+    loss = torch.zeros(1, dtype=torch.float64, device=dev)
+    plan.backward(T(pr.O0, dev), T(P, dev), leds, T(pr.A, dev), gO, gP, loss, T(gamma, dev))
+    torch.cuda.synchronize()
+    ref = fo.loss_and_grads(pr.O0.astype(np.complex128), P.astype(np.complex128), pr.shifts,
+                            leds, pr.A.astype(np.float64), gamma.astype(np.float64),
+                            loss="intensity")
+    m = pr.mask.astype(bool)
+    assert rel_l2(H(gO), ref.g_O) <= GRAD_TOL
+    assert rel_l2(H(gP)[m], ref.g_P[m]) <= GRAD_TOL
+    assert abs(float(H(loss)[0]) - ref.loss) <= 1e-5 * ref.loss
+    st = fpm.State(plan, T(pr.O0, dev))
+    plan.step(st, problem.hparams(w), leds, T(pr.A, dev))
+    torch.cuda.synchronize()
+    ost = fo.init_state(pr.O0)
+    cfg = fo.SolveConfig(lr_object=w.lr_object, learn_pupil=w.learn_zernike, loss="intensity")
+    oloss = fo.step(ost, cfg, pr.mask, pr.zern, pr.kappa, pr.shifts, leds,
+                    pr.A.astype(np.float64))
+    assert abs(float(H(st.loss)[0]) - oloss) <= 1e-5 * oloss
+    g = fo.loss_and_grads(pr.O0.astype(np.complex128), P.astype(np.complex128), pr.shifts, leds,
+                          pr.A.astype(np.float64), loss="intensity").g_O
+
+    def ri(z):
+        return np.stack([z.real, z.imag], -1).astype(np.float64)
+
+    O1, O1_ref, gg = ri(H(st.O)), ri(ost.O), ri(g)
+    decided = np.abs(gg) > 1e-4 * np.abs(gg).max()
+    diff = np.abs(O1 - O1_ref)
+    assert np.all(diff[decided] <= 1e-6 + 1e-5 * np.abs(O1_ref[decided]))
+    assert np.all(diff[~decided] <= 2 * w.lr_object * (1 + 1e-5))
+
+
 def test_pupil_grad_projection_matches_oracle(dev):
     w = inputs.workload("paper")
     say("pupil_grad paper")

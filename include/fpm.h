@@ -103,6 +103,16 @@ int fpm_plan_create(const fpm_desc* desc, const int32_t* shifts_host, fpm_plan**
 int fpm_plan_destroy(fpm_plan* plan);
 
 /*
+ * Replace the plan's LED table (same n_led; HOST int32 [n_led][2], copied),
+ * e.g. for another tile of the field of view, whose illumination angles
+ * differ (Sec. 2.1 k_m with the tile centre as the sample point). Windows are
+ * validated as in fpm_plan_create (FPM_EINVAL, nothing changed). Waits for
+ * `stream`, then enqueues the upload of the new Adam tile list on it; calls
+ * on the plan after this one (on that stream) use the new table.
+ */
+int fpm_plan_set_shifts(fpm_plan* plan, const int32_t* shifts_host, void* stream);
+
+/*
  * Loss of every later call on the plan (Eqs. 4-5; default amplitude):
  *   FPM_LOSS_AMPLITUDE: L = sum (sqrt(gamma)|psi| - A)^2, as stated below;
  *   FPM_LOSS_INTENSITY: L = sum (gamma |psi|^2 - A^2)^2 (Eq. 4 with I = A^2),

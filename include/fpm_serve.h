@@ -17,8 +17,10 @@
  *    admission is first-in first-out.
  *  - Per-request device state (spectrum, pupil, pupil parameters, Adam
  *    moments) and plan scratch live in slots kept in HBM between requests;
- *    slots are reused by later requests of the same shape (sizes, optics and
- *    LED table). fpm_server_reserve() creates them ahead of time, otherwise a
+ *    slots are reused by later requests of the same shape (sizes and optics).
+ *    A slot holding another LED table (another tile of the field of view) is
+ *    rebound to the request's table (fpm_plan_set_shifts) on the lane's
+ *    stream. fpm_server_reserve() creates slots ahead of time, otherwise a
  *    lane creates a slot when no free one of the request's shape exists.
  *  - A request's result depends only on the request: every reduction in the
  *    update is in a fixed order and a slot is used by one request at a time,

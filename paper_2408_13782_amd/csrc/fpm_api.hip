@@ -122,6 +122,8 @@ struct fpm_plan {
   float2* gP = nullptr;       // [N][N] pupil-gradient accumulator for fpm_step
   float* kappa_tab = nullptr;  // defocus phase per um at integer |u|^2 <= R^2
   int2* tiles = nullptr;      // [n_tiles] 32 x 32 HR tiles covered by some window
+  std::vector<int2> tiles_h;  // host copy, the source of fpm_plan_set_shifts' upload
+  std::vector<int2> rowext_h; // host copy of rowext
   double* part = nullptr;     // per-workgroup partial sums (loss | Zernike | pupil_grad)
   double* part_loss = nullptr;
   double* part_z = nullptr;
@@ -249,6 +251,51 @@ Batch batch_of(const fpm_plan* p, const int32_t* leds, int B) {
     bt.win[b] = make_int2(base + s.x, base + s.y);
   }
   return bt;
+}
+
+// Validate an LED table (every window inside the HR grid) and list the 32 x 32
+// HR tiles covered by the pupil disk of some window (Adam runs over these).
+int led_table(const fpm_plan* p, const int32_t* shifts_host, std::vector<int2>& shifts,
+              std::vector<int2>& tiles) {
+  const int base = p->M / 2 - p->N / 2;
+  shifts.assign(p->n_led, make_int2(0, 0));
+  for (int i = 0; i < p->n_led; ++i) {
+    const int sr = shifts_host[2 * i], sc = shifts_host[2 * i + 1];
+    if (base + sr < 0 || base + sr + p->N > p->M || base + sc < 0 || base + sc + p->N > p->M) {
+      char buf[160];
+      std::snprintf(buf, sizeof buf, "LED %d: window (%d, %d) leaves the %d x %d HR grid", i, sr,
+                    sc, p->M, p->M);
+      return fail(FPM_EINVAL, buf);
+    }
+    shifts[i] = make_int2(sr, sc);
+  }
+  const int nt = (p->M + 31) / 32;
+  std::vector<uint8_t> cover((size_t)nt * nt, 0);
+  for (int i = 0; i < p->n_led; ++i) {
+    const int2 s = shifts[i];
+    for (int ky = p->ky_lo; ky <= p->ky_hi; ++ky) {
+      const int row = base + s.x + ky;
+      const int c0 = base + s.y + p->rowext_h[ky].x, c1 = base + s.y + p->rowext_h[ky].y;
+      for (int tc = c0 / 32; tc <= c1 / 32; ++tc) cover[(size_t)(row / 32) * nt + tc] = 1;
+    }
+  }
+  tiles.clear();
+  for (int tr = 0; tr < nt; ++tr)
+    for (int tc = 0; tc < nt; ++tc)
+      if (cover[(size_t)tr * nt + tc]) tiles.push_back(make_int2(tr, tc));
+  return FPM_OK;
+}
+
+size_t tile_capacity(const fpm_plan* p) {
+  const size_t nt = (size_t)(p->M + 31) / 32;
+  return nt * nt;
+}
+
+// Synchronous upload of a tile list (plan creation).
+int copy_tiles(fpm_plan* p, const std::vector<int2>& tiles) {
+  if (!tiles.empty())
+    FPM_HIP(hipMemcpy(p->tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice));
+  return FPM_OK;
 }
 
 Disk disk_of(const fpm_plan* p) {
@@ -564,36 +611,15 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
       ++p->nrows;
     }
   }
-  // LED windows must lie inside the HR grid
-  p->shifts_h.resize(p->n_led);
-  const int base = p->M / 2 - p->N / 2;
-  for (int i = 0; i < p->n_led; ++i) {
-    const int sr = shifts_host[2 * i], sc = shifts_host[2 * i + 1];
-    if (base + sr < 0 || base + sr + p->N > p->M || base + sc < 0 || base + sc + p->N > p->M) {
-      delete p;
-      char buf[160];
-      std::snprintf(buf, sizeof buf, "LED %d: window (%d, %d) leaves the %d x %d HR grid", i, sr,
-                    sc, p->M, p->M);
-      return fail(FPM_EINVAL, buf);
-    }
-    p->shifts_h[i] = make_int2(sr, sc);
-  }
-  // HR tiles touched by some window (Adam runs over these only)
-  const int nt = (p->M + 31) / 32;
-  std::vector<uint8_t> cover((size_t)nt * nt, 0);
-  for (int i = 0; i < p->n_led; ++i) {
-    const int2 s = p->shifts_h[i];
-    for (int ky = p->ky_lo; ky <= p->ky_hi; ++ky) {
-      const int row = base + s.x + ky;
-      const int c0 = base + s.y + ext[ky].x, c1 = base + s.y + ext[ky].y;
-      for (int tc = c0 / 32; tc <= c1 / 32; ++tc) cover[(size_t)(row / 32) * nt + tc] = 1;
-    }
-  }
+  // LED table and the HR tiles its windows touch
   std::vector<int2> tiles;
-  for (int tr = 0; tr < nt; ++tr)
-    for (int tc = 0; tc < nt; ++tc)
-      if (cover[(size_t)tr * nt + tc]) tiles.push_back(make_int2(tr, tc));
+  p->rowext_h = ext;
+  if (int rc = led_table(p, shifts_host, p->shifts_h, tiles)) {
+    delete p;
+    return rc;
+  }
   p->n_tiles = (int)tiles.size();
+  p->tiles_h = tiles;
   p->hr_ok = hr_supported(p->M);
 
   // kappa(|u|^2) = 2 pi (sqrt(1/l^2 - k^2) - 1/l), k^2 = |u|^2 dk^2, cancellation-free form
@@ -609,7 +635,8 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
       (rc = upload<float2>(&p->device_bytes, &p->X, nullptr, (size_t)p->max_batch * p->N * p->N)) ||
       (rc = upload<float2>(&p->device_bytes, &p->gP, nullptr, (size_t)p->N * p->N)) ||
       (rc = upload(&p->device_bytes, &p->kappa_tab, kap.data(), kap.size())) ||
-      (rc = upload(&p->device_bytes, &p->tiles, tiles.data(), std::max<size_t>(tiles.size(), 1)))) {
+      (rc = upload<int2>(&p->device_bytes, &p->tiles, nullptr, tile_capacity(p))) ||
+      (rc = copy_tiles(p, tiles))) {
     plan_free(p);
     return rc;
   }
@@ -655,6 +682,23 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
 int fpm_plan_destroy(fpm_plan* p) {
   if (!p) return FPM_OK;
   plan_free(p);
+  return FPM_OK;
+}
+
+int fpm_plan_set_shifts(fpm_plan* p, const int32_t* shifts_host, void* stream) {
+  FPM_REQUIRE(p && shifts_host, "plan and shifts_host must not be NULL");
+  if (int rc = check_device(p)) return rc;
+  std::vector<int2> shifts, tiles;
+  if (int rc = led_table(p, shifts_host, shifts, tiles)) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  // the previous upload from tiles_h must have completed before it is replaced
+  FPM_HIP(hipStreamSynchronize(st));
+  p->shifts_h = std::move(shifts);
+  p->tiles_h = std::move(tiles);
+  p->n_tiles = (int)p->tiles_h.size();
+  if (p->n_tiles > 0)
+    FPM_HIP(hipMemcpyAsync(p->tiles, p->tiles_h.data(), p->tiles_h.size() * sizeof(int2),
+                           hipMemcpyHostToDevice, st));
   return FPM_OK;
 }
 

@@ -22,29 +22,34 @@ namespace {
 constexpr int kZernTerms = 15;
 constexpr int kMaxLanes = 64;
 
-// Shape of a request: everything a plan is built from.
+// Shape of a request: sizes and optics (what a plan's allocations depend on).
+// The LED table is not part of it: a slot is rebound to another table
+// (another tile of the field of view) with fpm_plan_set_shifts.
 struct ShapeKey {
   fpm_desc desc;
-  std::vector<int32_t> shifts;
   bool operator==(const ShapeKey& o) const {
     return desc.n_lr == o.desc.n_lr && desc.upsample == o.desc.upsample &&
            desc.n_led == o.desc.n_led && desc.max_batch == o.desc.max_batch &&
            desc.wavelength_um == o.desc.wavelength_um && desc.na == o.desc.na &&
-           desc.mag == o.desc.mag && desc.pixel_um == o.desc.pixel_um && shifts == o.shifts;
+           desc.mag == o.desc.mag && desc.pixel_um == o.desc.pixel_um;
   }
 };
 
-ShapeKey key_of(const fpm_desc* d, const int32_t* shifts_host) {
+ShapeKey key_of(const fpm_desc* d) {
   ShapeKey k;
   k.desc = *d;
-  k.shifts.assign(shifts_host, shifts_host + 2 * (size_t)d->n_led);
   return k;
+}
+
+std::vector<int32_t> table_of(const fpm_desc* d, const int32_t* shifts_host) {
+  return std::vector<int32_t>(shifts_host, shifts_host + 2 * (size_t)d->n_led);
 }
 
 // Device state of one reconstruction, laid out in one allocation:
 // O | m_O | v_O (complex [M][M] each) | P (complex [N][N]) | small block.
 struct Slot {
   ShapeKey key;
+  std::vector<int32_t> shifts;   // the LED table the plan holds now
   fpm_plan* plan = nullptr;
   void* block = nullptr;
   fpm_c32 *O = nullptr, *m_O = nullptr, *v_O = nullptr, *P = nullptr;
@@ -71,7 +76,7 @@ int64_t data_bytes(const fpm_desc& d) { return (int64_t)d.n_led * d.n_lr * d.n_l
 struct Job {
   fpm_request req{};
   ShapeKey key;
-  std::vector<int32_t> leds, sizes;
+  std::vector<int32_t> shifts, leds, sizes;
   int64_t footprint = 0;
   double t_submit = 0.0, t_admit = 0.0;
 };
@@ -127,10 +132,12 @@ void slot_free(Slot* s) {
 }
 
 // Build a slot of a shape on the current device (allocates).
-int slot_create(const ShapeKey& key, std::unique_ptr<Slot>& out) {
+int slot_create(const ShapeKey& key, const std::vector<int32_t>& shifts,
+                std::unique_ptr<Slot>& out) {
   auto s = std::make_unique<Slot>();
   s->key = key;
-  if (int rc = fpm_plan_create(&key.desc, key.shifts.data(), &s->plan))
+  s->shifts = shifts;
+  if (int rc = fpm_plan_create(&key.desc, shifts.data(), &s->plan))
     return serve_fail(rc, std::string("slot plan: ") + fpm_last_error());
   fpm_info info{};
   fpm_plan_info(s->plan, &info);
@@ -163,19 +170,31 @@ int slot_create(const ShapeKey& key, std::unique_ptr<Slot>& out) {
   return FPM_OK;
 }
 
-// Take a free slot of the job's shape (creating one if none is free).
-int slot_acquire(fpm_server* sv, const ShapeKey& key, Slot** out) {
+// Take a free slot of the job's shape, preferring one that holds the job's LED
+// table; another free slot of the shape is rebound to it on the lane's stream;
+// with none free, a new slot is created.
+int slot_acquire(fpm_server* sv, const Job& j, hipStream_t st, Slot** out) {
+  Slot* got = nullptr;
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     for (auto& s : sv->slots)
-      if (!s->busy && s->key == key) {
-        s->busy = true;
-        *out = s.get();
-        return FPM_OK;
+      if (!s->busy && s->key == j.key && (got == nullptr || s->shifts == j.shifts)) {
+        got = s.get();
+        if (s->shifts == j.shifts) break;
       }
+    if (got) got->busy = true;
+  }
+  if (got) {
+    *out = got;
+    if (got->shifts != j.shifts) {
+      if (int rc = fpm_plan_set_shifts(got->plan, j.shifts.data(), st))
+        return serve_fail(rc, fpm_last_error());
+      got->shifts = j.shifts;
+    }
+    return FPM_OK;
   }
   std::unique_ptr<Slot> s;
-  if (int rc = slot_create(key, s)) return rc;
+  if (int rc = slot_create(j.key, j.shifts, s)) return rc;
   s->busy = true;
   std::lock_guard<std::mutex> lk(sv->mu);
   *out = s.get();
@@ -267,7 +286,7 @@ void lane_main(fpm_server* sv, Lane* lane, int index) {
     }
     int rc = ok ? FPM_OK : serve_fail(FPM_EHIP, "lane stream or event creation failed");
     Slot* slot = nullptr;
-    if (rc == FPM_OK) rc = slot_acquire(sv, job->key, &slot);
+    if (rc == FPM_OK) rc = slot_acquire(sv, *job, st, &slot);
     if (rc == FPM_OK) rc = run_request(*job, slot, st, ev);
     if (rc != FPM_OK && st) (void)hipStreamSynchronize(st);
     const double t_done = sv->now_ms();
@@ -296,7 +315,8 @@ void lane_main(fpm_server* sv, Lane* lane, int index) {
 }
 
 // Footprint of a shape: from a slot or an earlier query, else from a temporary plan.
-int footprint_of(fpm_server* sv, const ShapeKey& key, int64_t* bytes) {
+int footprint_of(fpm_server* sv, const ShapeKey& key, const std::vector<int32_t>& shifts,
+                 int64_t* bytes) {
   {
     std::lock_guard<std::mutex> lk(sv->mu);
     for (auto& f : sv->footprints)
@@ -306,7 +326,7 @@ int footprint_of(fpm_server* sv, const ShapeKey& key, int64_t* bytes) {
       }
   }
   int64_t b = 0;
-  if (int rc = fpm_request_footprint(&key.desc, key.shifts.data(), &b)) return rc;
+  if (int rc = fpm_request_footprint(&key.desc, shifts.data(), &b)) return rc;
   std::lock_guard<std::mutex> lk(sv->mu);
   sv->footprints.emplace_back(key, b);
   *bytes = b;
@@ -374,10 +394,11 @@ int fpm_server_reserve(fpm_server* sv, const fpm_desc* d, const int32_t* shifts_
                        int32_t count) {
   if (!sv || !d || !shifts_host) return serve_fail(FPM_EINVAL, "arguments must not be NULL");
   if (count < 0) return serve_fail(FPM_EINVAL, "count must be >= 0");
-  const ShapeKey key = key_of(d, shifts_host);
+  const ShapeKey key = key_of(d);
+  const std::vector<int32_t> shifts = table_of(d, shifts_host);
   for (int i = 0; i < count; ++i) {
     std::unique_ptr<Slot> s;
-    if (int rc = slot_create(key, s)) return rc;
+    if (int rc = slot_create(key, shifts, s)) return rc;
     std::lock_guard<std::mutex> lk(sv->mu);
     bool known = false;
     for (auto& f : sv->footprints) known = known || f.first == key;
@@ -400,7 +421,8 @@ int fpm_server_submit(fpm_server* sv, const fpm_request* r) {
     return serve_fail(FPM_EINVAL, "leds and batch_sizes must not be NULL");
   auto job = std::make_unique<Job>();
   job->req = *r;
-  job->key = key_of(&d, r->shifts_host);
+  job->key = key_of(&d);
+  job->shifts = table_of(&d, r->shifts_host);
   size_t total = 0;
   for (int i = 0; i < r->n_steps; ++i) {
     const int b = r->batch_sizes[i];
@@ -419,7 +441,7 @@ int fpm_server_submit(fpm_server* sv, const fpm_request* r) {
   job->req.shifts_host = nullptr;
   job->req.leds = nullptr;
   job->req.batch_sizes = nullptr;
-  if (int rc = footprint_of(sv, job->key, &job->footprint)) return rc;
+  if (int rc = footprint_of(sv, job->key, job->shifts, &job->footprint)) return rc;
   if (job->footprint > sv->budget)
     return serve_fail(FPM_EINVAL, "the request's footprint exceeds the server's budget");
   std::lock_guard<std::mutex> lk(sv->mu);

@@ -93,6 +93,7 @@ EXPORTS = {
     "fpm_timing_enable": [C.c_void_p, C.c_int32],
     "fpm_timing_repeat": [C.c_void_p, C.c_int32, C.c_int32],
     "fpm_plan_set_loss": [C.c_void_p, C.c_int32],
+    "fpm_plan_set_shifts": [C.c_void_p, C.c_void_p, C.c_void_p],
     "fpm_timing_collect": [C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                            C.POINTER(C.c_int32)],
 }
@@ -267,6 +268,17 @@ class Plan:
         self.info = info
         self._lib = lib
         self._kinds = self._read_kernel_kinds()
+
+    def set_shifts(self, shifts):
+        """Replace the LED table (fpm_plan_set_shifts), e.g. for another tile's ROI centre."""
+        shifts = np.ascontiguousarray(np.asarray(shifts, np.int32).reshape(-1, 2))
+        if shifts.shape[0] != self.n_led:
+            raise FpmError(f"expected {self.n_led} LED offsets, got {shifts.shape[0]}")
+        _check(self._lib.fpm_plan_set_shifts(self._h, shifts.ctypes.data, _stream()))
+        self.shifts = shifts
+        info = _Info()
+        _check(self._lib.fpm_plan_info(self._h, C.byref(info)))
+        self.info = info
 
     LOSSES = {"amplitude": 0, "intensity": 1}
 

@@ -9,6 +9,7 @@
 #include "fpm_serve.h"
 
 extern std::atomic<int> peak;
+extern std::atomic<int> rebinds;
 
 #define CHECK(c)                                          \
   do {                                                    \
@@ -105,6 +106,36 @@ int main() {
   }
   CHECK(fpm_server_destroy(sv) == FPM_OK);
   for (int i = 0; i < 8; ++i) CHECK(loss[i] == 10.0);
+
+  // tiles of one shape with different LED tables share one slot, rebound per request
+  {
+    fpm_server_desc one{1, 8 * fp};
+    fpm_server* s1 = nullptr;
+    CHECK(fpm_server_create(&one, &s1) == FPM_OK);
+    std::vector<std::vector<int32_t>> tables(3, std::vector<int32_t>(18, 0));
+    for (int k = 0; k < 3; ++k) tables[k][0] = 7 * (k + 1);
+    const int order[6] = {0, 0, 1, 2, 2, 0};
+    for (int i = 0; i < 6; ++i) {
+      fpm_request r{};
+      r.desc = d;
+      r.shifts_host = tables[order[i]].data();
+      r.meas_amp = amp.data();
+      r.centre_led = 4;
+      r.leds = leds.data();
+      r.batch_sizes = sizes.data();
+      r.n_steps = 2;
+      r.O_out = outs[i].data();
+      r.tag = 100 + i;
+      CHECK(fpm_server_submit(s1, &r) == FPM_OK);
+    }
+    CHECK(fpm_server_drain(s1) == FPM_OK);
+    int32_t slots1 = 0;
+    CHECK(fpm_server_stats(s1, nullptr, nullptr, nullptr, nullptr, nullptr, &slots1) == FPM_OK);
+    CHECK(slots1 == 1);
+    for (int i = 0; i < 6; ++i) CHECK(outs[i][1].re == (float)(7 * (order[i] + 1)));
+    CHECK(rebinds.load() == 3);   // 0 -> 1 -> 2 -> 0
+    CHECK(fpm_server_destroy(s1) == FPM_OK);
+  }
   std::printf("OK\n");
   return 0;
 }

@@ -57,7 +57,10 @@ def test_error_strings():
 
 
 @pytest.mark.parametrize("name", ["small", "paper", "large"])
-@pytest.mark.parametrize("geometry", [(0.0, 0.0, 0.0, 0.0), (0.31, -0.27, 0.021, 1.3)])
+@pytest.mark.parametrize("geometry", [(0.0, 0.0, 0.0, 0.0, 0.0, 0.0),
+                                      (0.31, -0.27, 0.021, 1.3, 0.0, 0.0),
+                                      (0.0, 0.0, 0.0, 0.0, 1.7, -2.3),       # off-axis tile
+                                      (0.31, -0.27, 0.021, 1.3, -0.9, 0.45)])
 def test_led_shifts_match_oracle(name, geometry):
     w = inputs.workload(name)
     opt = fo.Optics(w.wavelength_um, w.na, w.mag, w.pixel_um, w.n_lr, w.upsample)

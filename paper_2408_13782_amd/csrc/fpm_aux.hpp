@@ -111,7 +111,10 @@ struct UpdateArgs {
   PupilGeom pg; const int2* rowext; float2* P;
 };
 
-constexpr int kPupilPerWg = 1024;   // pupil points rebuilt per workgroup
+#ifndef FPM_PUPIL_PER_WG
+#define FPM_PUPIL_PER_WG 512
+#endif
+constexpr int kPupilPerWg = FPM_PUPIL_PER_WG;   // pupil points rebuilt per workgroup
 
 // Gradient of the spectrum at 4 consecutive pixels (row r, columns c0..c0+3):
 // the sum, in batch order, of the patches of the LEDs whose disk covers them.

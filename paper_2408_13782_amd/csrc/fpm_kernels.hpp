@@ -62,7 +62,11 @@ template <> struct RowT<256> { static constexpr int value = FPM_ROW_T256; };
 template <> struct RowT<512> { static constexpr int value = FPM_ROW_T512; };
 template <int N> using RowPlan = PlanT<N, RowT<N>::value>;
 
+#ifndef FPM_COL_LINES256
+#define FPM_COL_LINES256 16
+#endif
 template <int N> struct ColLines { static constexpr int value = 16; };
+template <> struct ColLines<256> { static constexpr int value = FPM_COL_LINES256; };
 template <> struct ColLines<512> { static constexpr int value = 8; };
 
 // Threads per column transform in the column pass (more threads per column

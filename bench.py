@@ -37,14 +37,14 @@ FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, no packe
 # WRITE_SIZE; the factor 2 is what a plain device copy of known size reads on
 # the same counter), for the kernel build they were taken on.
 TRAFFIC = {
-    ("paper", "rows_forward"): (1938.0 * 2 + 4788.7) * 1024,
+    ("paper", "rows_forward"): (1938.1 * 2 + 4788.7) * 1024,
     ("paper", "cols"): (4456.7 * 2 + 4843.4) * 1024,
     ("paper", "rows_backward"): (4460.9 * 2 + 2450.0) * 1024,
-    ("paper", "update"): (7203.0 * 2 + 11804.1) * 1024,
-    ("large", "rows_forward"): (14122.5 * 2 + 39614.7) * 1024,
-    ("large", "cols"): (36179.4 * 2 + 39785.5) * 1024,
-    ("large", "rows_backward"): (33811.6 * 2 + 19586.9) * 1024,
-    ("large", "update"): (45635.2 * 2 + 58448.2) * 1024,
+    ("paper", "update"): (7203.0 * 2 + 11810.3) * 1024,
+    ("large", "rows_forward"): (14131.2 * 2 + 39614.7) * 1024,
+    ("large", "cols"): (36179.4 * 2 + 39784.9) * 1024,
+    ("large", "rows_backward"): (33817.8 * 2 + 19586.9) * 1024,
+    ("large", "update"): (45635.1 * 2 + 58430.6) * 1024,
 }
 
 

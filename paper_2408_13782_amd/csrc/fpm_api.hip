@@ -427,7 +427,10 @@ int cols_grid_of(const fpm_plan* p, int B) {
   return with_lr_size(p->N, [&](auto n) { return grids_of<decltype(n)::value>(p, B).cols(); });
 }
 
-int pupil_wgs(const fpm_plan* p) { return (p->N * p->N + kPupilPerWg - 1) / kPupilPerWg; }
+int pupil_wgs(const fpm_plan* p) {
+  const int per = pupil_per_wg(p->N);
+  return (p->N * p->N + per - 1) / per;
+}
 
 template <int N>
 int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr,

@@ -111,10 +111,10 @@ struct UpdateArgs {
   PupilGeom pg; const int2* rowext; float2* P;
 };
 
-#ifndef FPM_PUPIL_PER_WG
-#define FPM_PUPIL_PER_WG 512
-#endif
-constexpr int kPupilPerWg = FPM_PUPIL_PER_WG;   // pupil points rebuilt per workgroup
+// Pupil points rebuilt per workgroup of the update kernel. Every pupil
+// workgroup sums all row-pass moment partials first, so their number is kept
+// down where the row pass has many workgroups (N >= 384).
+constexpr int pupil_per_wg(int n) { return n <= 256 ? 512 : 1024; }
 
 // Gradient of the spectrum at 4 consecutive pixels (row r, columns c0..c0+3):
 // the sum, in batch order, of the patches of the LEDs whose disk covers them.
@@ -175,6 +175,7 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
 template <int N>
 __global__ void __launch_bounds__(256) update(UpdateArgs a) {
   FPM_PROBE(3, 0);
+  constexpr int kPupilPerWg = pupil_per_wg(N);
   const int n_pw = a.pupil ? (N * N + kPupilPerWg - 1) / kPupilPerWg : 1;
   if ((int)blockIdx.x >= n_pw) {
     const int2 tl = a.tiles[blockIdx.x - n_pw];

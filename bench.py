@@ -142,6 +142,49 @@ def ring_order(prob) -> "np.ndarray":
     return np.lexsort((np.arctan2(k[:, 0], k[:, 1]), np.round(np.hypot(k[:, 0], k[:, 1]), 9)))
 
 
+def multiparam_rate(w, prob, steps: int) -> dict:
+    """Throughput of the multi-parameter path on the same workload: fpm_loss_grad
+    through the autograd function (object, Zernikes, defocus, LED-array
+    geometry, sub-pixel crop) and torch Adam on every group, per random batch."""
+    import numpy as np
+    import torch
+    from paper_2408_13782_amd import fpm, inputs, problem
+    from paper_2408_13782_amd.autograd import FPMLoss, LossContext
+    plan = prob.plan
+    grid = fpm.LedGrid(w.n_side, w.pitch_mm, w.height_mm)
+    O = problem.initial_spectrum(prob).clone().requires_grad_(True)
+    c = torch.zeros(15, dtype=torch.float32, device="cuda", requires_grad=True)
+    z = torch.zeros(1, dtype=torch.float32, device="cuda", requires_grad=True)
+    geom = torch.zeros(4, dtype=torch.float64, device="cuda", requires_grad=True)
+    opt = torch.optim.Adam([dict(params=[O], lr=w.lr_object), dict(params=[c], lr=w.lr_zernike),
+                            dict(params=[z], lr=w.lr_z), dict(params=[geom], lr=1e-3)])
+    batches = problem.schedule(inputs.led_permutations(w.n_led, -(-(steps + 10) // w.steps_per_epoch()),
+                                                      seed=1), w.batch)
+    A = prob.meas_amp
+
+    def one(leds):
+        opt.zero_grad(set_to_none=False)
+        loss = FPMLoss.apply(O, c, z, geom, None, LossContext(plan, grid, leds, A))
+        loss.backward()
+        opt.step()
+
+    for leds in batches[:10]:
+        one(leds)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    n_img = 0
+    for leds in batches[10:10 + steps]:
+        one(leds)
+        n_img += len(leds)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    return {"led_images_per_s": n_img / (ms / 1e3), "ms_per_step": ms / steps,
+            "path": "fpm_loss_grad + torch.autograd + torch.optim.Adam (object, Zernike, "
+                    "defocus, LED-array geometry)"}
+
+
 def batch_sweep(w, batches, epochs: int, log) -> dict:
     """Random batches of several sizes (Eqs. 13-14) and the sequential fixed-order
     loop (Eq. 7) on the same synthetic data: quality of the object after each
@@ -324,6 +367,8 @@ def main():
         "per_kernel_mean_us": {k: v * 1e3 for k, v in timed.items()},
         "support_px": S, "union_px": U,
     }
+    detail["multiparam"] = multiparam_rate(w, prob, 100)
+    log(f"multi-parameter path: {detail['multiparam']['led_images_per_s']:.4g} LED-images/s")
     # digital refocusing of the reconstruction: 16 distances in [-40, 40] um
     z = torch.linspace(-40.0, 40.0, 16, dtype=torch.float32, device="cuda")
     foc = torch.empty((16, plan.M, plan.M), dtype=torch.complex64, device="cuda")

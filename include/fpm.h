@@ -285,6 +285,34 @@ int fpm_loss_grad(fpm_plan* plan, const fpm_led_grid* grid, const fpm_params* pa
                   const int32_t* leds, int32_t B, const float* meas_amp, fpm_grads* grads,
                   void* stream);
 
+/* Learned LED-array geometry of fpm_run_multi (device memory unless stated). */
+typedef struct {
+  double* geom;            /* [4] errors added to the grid's: shift_x_mm, shift_y_mm,
+                              rot_rad, dh_mm */
+  double* m_geom;          /* [4] Adam moments */
+  double* v_geom;          /* [4] */
+  double* g_geom;          /* [4] += each step's gradient, or NULL (diagnostics) */
+  double lr_shift_mm, lr_rot_rad, lr_height_mm;   /* host values */
+  int32_t learn;           /* update geom (else held; the offsets still follow it) */
+} fpm_geometry;
+
+/*
+ * n_steps fused multi-parameter updates (Sec. 2.2): per step the loss and the
+ * gradients of the spectrum, the Zernike coefficients, the defocus and the
+ * LED-array geometry (sub-pixel offsets and bilinear crop as in
+ * fpm_loss_grad), then Adam on all of them (torch semantics, FP64 for the
+ * scalars; the spectrum's Adam runs over the whole HR grid because the union
+ * of windows moves with the geometry). state: as fpm_run, with coeffs, z_um
+ * and their moments required (learned or not, per hp->learn_zernike,
+ * hp->learn_z); state->P must hold P(coeffs, z) on entry and is rebuilt each
+ * step. No LED intensities. Deterministic; one call is the same as n_steps
+ * calls of one step. Same batch layout as fpm_run.
+ */
+int fpm_run_multi(fpm_plan* plan, const fpm_led_grid* grid, fpm_state* state,
+                  fpm_geometry* geometry, const fpm_hparams* hp, const int32_t* leds,
+                  const int32_t* batch_sizes, int32_t n_steps, const float* meas_amp,
+                  void* stream);
+
 /*
  * HR object <-> spectrum (Sec. 2.1, Eq. 1) with the orthonormal scaling:
  *   direction +1: O = fftshift(fft2(o)) / M;   direction -1: o = ifft2(ifftshift(O)) * M.

@@ -130,9 +130,9 @@ struct fpm_plan {
   double* part_pg = nullptr;
   float* staging = nullptr;   // next pupil-parameter state, written by the update kernel
   double* part_lg = nullptr;  // partials of fpm_loss_grad (column pass | row pass)
-  SubSlot* sub = nullptr;     // [max_batch] sub-pixel offsets of fpm_loss_grad
   float2* P_ws = nullptr;     // [N][N] pupil built by fpm_loss_grad
   int* oob_ws = nullptr;      // window-clamp counter when the caller passes none
+  MultiParams* mpar = nullptr;  // [2] parameter blocks of fpm_run_multi
   unsigned* counters = nullptr;  // completion counter of pupil_grad's reduction
   int loss_kind = FPM_LOSS_AMPLITUDE;
   bool timing = false;
@@ -198,9 +198,9 @@ void plan_free(fpm_plan* p) {
   (void)hipFree(p->part);
   (void)hipFree(p->staging);
   (void)hipFree(p->part_lg);
-  (void)hipFree(p->sub);
   (void)hipFree(p->P_ws);
   (void)hipFree(p->oob_ws);
+  (void)hipFree(p->mpar);
   (void)hipFree(p->counters);
   delete p;
 }
@@ -432,19 +432,7 @@ int pupil_wgs(const fpm_plan* p) {
   return (p->N * p->N + per - 1) / per;
 }
 
-template <int N>
-int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr,
-                     const int32_t* leds, int B, const float* A, fpm_grads* gr, hipStream_t st) {
-  const Grids g = grids_of<N>(p, B);
-  const Batch bt = batch_of(p, leds, B);
-  const Disk dk = disk_of(p);
-  const PupilGeom pg = pupil_geom(p);
-  {
-    Timed tm(p, kPupilBuild, st);
-    pupil_build<<<(p->N * p->N + 255) / 256, 256, 0, st>>>(pg, p->rowext, pr->coeffs,
-                                                             pr->coeffs ? kZern : 0, pr->z_um,
-                                                             p->P_ws);
-  }
+GeomArgs geom_args(const fpm_plan* p, const fpm_led_grid* grid) {
   GeomArgs ga;
   ga.n_side = grid->n_side;
   ga.pitch_mm = grid->pitch_mm;
@@ -459,14 +447,30 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
   ga.lambda = p->lambda;
   ga.N = p->N;
   ga.M = p->M;
-  led_subpixel<<<1, kMaxSlots, 0, st>>>(ga, pr->geom, bt, p->sub, gr->oob ? gr->oob : p->oob_ws);
+  return ga;
+}
+
+template <int N>
+int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr,
+                     const int32_t* leds, int B, const float* A, fpm_grads* gr, hipStream_t st) {
+  const Grids g = grids_of<N>(p, B);
+  const Batch bt = batch_of(p, leds, B);
+  const Disk dk = disk_of(p);
+  const PupilGeom pg = pupil_geom(p);
+  {
+    Timed tm(p, kPupilBuild, st);
+    pupil_build<<<(p->N * p->N + 255) / 256, 256, 0, st>>>(pg, p->rowext, pr->coeffs,
+                                                             pr->coeffs ? kZern : 0, pr->z_um,
+                                                             p->P_ws);
+  }
+  const GeomArgs ga = geom_args(p, grid);
   const float2* O = reinterpret_cast<const float2*>(pr->O);
   double* col_part = p->part_lg;
   double* row_part = p->part_lg + (size_t)g.cols() * 2;
   {
     Timed tm(p, kRowsForward, st);
-    rows_forward_sub<N><<<g.rows(), kRowThreads, 0, st>>>(O, p->P_ws, bt, dk, p->sub,
-                                                          g.row_chunks, p->X, p->twN);
+    rows_forward_sub<N><<<g.rows(), kRowThreads, 0, st>>>(O, p->P_ws, bt, dk, ga, pr->geom,
+                                                          gr->oob, g.row_chunks, p->X, p->twN);
   }
   {
     Timed tm(p, kCols, st);
@@ -476,14 +480,14 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
   }
   {
     Timed tm(p, kRowsBackward, st);
-    rows_backward_sub<N><<<g.rows(), kRowThreads, 0, st>>>(p->X, O, p->P_ws, bt, dk, pg, p->sub,
-                                                           g.row_chunks, row_part, p->kappa_tab,
-                                                           p->twN);
+    rows_backward_sub<N><<<g.rows(), kRowThreads, 0, st>>>(p->X, O, p->P_ws, bt, dk, pg, ga,
+                                                           pr->geom, g.row_chunks, row_part,
+                                                           p->kappa_tab, p->twN);
   }
   if (gr->g_O) {
     Timed tm(p, kAdamObject, st);
-    gather_dense<N><<<(p->M / 32) * (p->M / 32), 256, 0, st>>>(p->X, bt, dk, p->sub,
-                                                               reinterpret_cast<float2*>(gr->g_O));
+    gather_dense<N><<<(p->M / 32) * (p->M / 32), 256, 0, st>>>(
+        p->X, bt, dk, ga, pr->geom, reinterpret_cast<float2*>(gr->g_O));
   }
   ReduceArgs ra;
   ra.col_part = col_part;
@@ -492,7 +496,8 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
   ra.row_part = row_part;
   ra.row_wgs = g.rows();
   ra.row_chunks = g.row_chunks;
-  ra.sub = p->sub;
+  ra.ga = ga;
+  ra.geom = pr->geom;
   ra.bt = bt;
   ra.gamma = pr->gamma;
   ra.loss = gr->loss;
@@ -501,6 +506,94 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
   ra.g_gamma = gr->g_gamma;
   loss_grad_reduce<<<1, 256, 0, st>>>(ra);
   FPM_HIP(hipGetLastError());
+  return FPM_OK;
+}
+
+// One fused multi-parameter step: parameters of this step in block `cur`,
+// the next ones written to `next`.
+template <int N>
+int launch_multi_step(fpm_plan* p, const GeomArgs& ga, fpm_state* s, const fpm_geometry* geo,
+                      const fpm_hparams* hp, const int32_t* leds, int B, const float* A,
+                      MultiParams* cur, MultiParams* next, hipStream_t st) {
+  const Grids g = grids_of<N>(p, B);
+  const Batch bt = batch_of(p, leds, B);
+  const Disk dk = disk_of(p);
+  const PupilGeom pg = pupil_geom(p);
+  const float2* O = reinterpret_cast<const float2*>(s->O);
+  float2* P = reinterpret_cast<float2*>(s->P);
+  double* col_part = p->part_lg;
+  double* row_part = p->part_lg + (size_t)g.cols() * 2;
+  const double* geom = cur->g;
+  {
+    Timed tm(p, kRowsForward, st);
+    for (int r = 0; r < tm.reps; ++r)
+      rows_forward_sub<N><<<g.rows(), kRowThreads, 0, st>>>(O, P, bt, dk, ga, geom, p->oob_ws,
+                                                            g.row_chunks, p->X, p->twN);
+  }
+  {
+    Timed tm(p, kCols, st);
+    for (int r = 0; r < tm.reps; ++r)
+      cols<N, false><<<g.cols(), ColLines<N>::value * ColPlan<N>::T, 0, st>>>(
+          p->X, A, nullptr, bt, dk, g.col_groups, col_part, nullptr, nullptr, p->twN,
+          1.0f / p->M);
+  }
+  {
+    Timed tm(p, kRowsBackward, st);
+    for (int r = 0; r < tm.reps; ++r)
+      rows_backward_sub<N><<<g.rows(), kRowThreads, 0, st>>>(p->X, O, P, bt, dk, pg, ga, geom,
+                                                             g.row_chunks, row_part,
+                                                             p->kappa_tab, p->twN);
+  }
+  const int t = s->t + 1;
+  const double b1 = hp->beta1, b2 = hp->beta2;
+  const double bc1 = 1.0 - std::pow(b1, t), bc2 = 1.0 - std::pow(b2, t);
+  MultiUpdateArgs a{};
+  a.M = p->M;
+  a.O = reinterpret_cast<float*>(s->O);
+  a.mO = reinterpret_cast<float*>(s->m_O);
+  a.vO = reinterpret_cast<float*>(s->v_O);
+  a.c.b1 = hp->beta1;
+  a.c.b2 = hp->beta2;
+  a.c.eps = hp->eps;
+  a.c.step_size = (float)(hp->lr_object / bc1);
+  a.c.sqrt_bc2 = (float)std::sqrt(bc2);
+  a.X = p->X;
+  a.bt = bt;
+  a.dk = dk;
+  a.ga = ga;
+  a.loss_part = col_part;
+  a.n_loss = g.cols();
+  a.loss = s->loss;
+  a.row_part = row_part;
+  a.n_rows = g.rows();
+  a.row_chunks = g.row_chunks;
+  a.cur = cur;
+  a.next = next;
+  a.sa.learn_c = hp->learn_zernike;
+  a.sa.learn_z = hp->learn_z;
+  a.sa.lr_c = hp->lr_zernike;
+  a.sa.lr_z = hp->lr_z;
+  a.sa.b1 = b1;
+  a.sa.b2 = b2;
+  a.sa.eps = hp->eps;
+  a.sa.bc1 = bc1;
+  a.sa.sqrt_bc2 = std::sqrt(bc2);
+  a.learn_geom = geo->learn;
+  a.lr_geom[0] = geo->lr_shift_mm;
+  a.lr_geom[1] = geo->lr_shift_mm;
+  a.lr_geom[2] = geo->lr_rot_rad;
+  a.lr_geom[3] = geo->lr_height_mm;
+  a.g_par = s->g_par;
+  a.g_geom = geo->g_geom;
+  a.pg = pg;
+  a.P = P;
+  const int grid = pupil_wgs(p) + (p->M / 32) * (p->M / 32);
+  {
+    Timed tm(p, kAdamObject, st);
+    for (int r = 0; r < tm.reps; ++r) update_multi<N><<<grid, 256, 0, st>>>(a);
+  }
+  FPM_HIP(hipGetLastError());
+  s->t = t;
   return FPM_OK;
 }
 
@@ -654,9 +747,9 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
     return rc;
   }
   if ((rc = upload<double>(&p->device_bytes, &p->part_lg, nullptr, (size_t)cols_grid * 2 + (size_t)rows_grid * kSubPar)) ||
-      (rc = upload<SubSlot>(&p->device_bytes, &p->sub, nullptr, (size_t)p->max_batch)) ||
       (rc = upload<float2>(&p->device_bytes, &p->P_ws, nullptr, (size_t)p->N * p->N)) ||
-      (rc = upload<int>(&p->device_bytes, &p->oob_ws, nullptr, 1))) {
+      (rc = upload<int>(&p->device_bytes, &p->oob_ws, nullptr, 1)) ||
+      (rc = upload<MultiParams>(&p->device_bytes, &p->mpar, nullptr, 2))) {
     plan_free(p);
     return rc;
   }
@@ -977,6 +1070,52 @@ int fpm_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr,
   return with_lr_size(p->N, [&](auto n) {
     return launch_loss_grad<decltype(n)::value>(p, grid, pr, leds, B, meas_amp, gr, st);
   });
+}
+
+int fpm_run_multi(fpm_plan* p, const fpm_led_grid* grid, fpm_state* s, fpm_geometry* geo,
+                  const fpm_hparams* hp, const int32_t* leds, const int32_t* batch_sizes,
+                  int32_t n_steps, const float* meas_amp, void* stream) {
+  FPM_REQUIRE(p && grid && s && geo && hp, "plan, grid, state, geometry and hparams must not be NULL");
+  FPM_REQUIRE(s->O && s->m_O && s->v_O && s->P && meas_amp,
+              "state O, m_O, v_O, P and meas_amp must not be NULL");
+  FPM_REQUIRE(s->coeffs && s->m_c && s->v_c && s->z_um && s->m_z && s->v_z,
+              "the Zernike and defocus state must not be NULL");
+  FPM_REQUIRE(geo->geom && geo->m_geom && geo->v_geom, "geometry state must not be NULL");
+  FPM_REQUIRE(grid->n_side >= 1 && grid->n_side * grid->n_side == p->n_led,
+              "grid->n_side^2 must equal the plan's n_led");
+  FPM_REQUIRE(s->t >= 0, "t must be >= 0");
+  FPM_REQUIRE(n_steps >= 0, "n_steps must be >= 0");
+  FPM_REQUIRE(n_steps == 0 || (leds && batch_sizes), "leds and batch_sizes must not be NULL");
+  if (int rc = check_device(p)) return rc;
+  size_t off = 0;
+  for (int i = 0; i < n_steps; ++i) {
+    FPM_REQUIRE(batch_sizes[i] >= 1 && batch_sizes[i] <= p->max_batch,
+                "every batch size must be in [1, max_batch]");
+    if (int rc = check_batch(p, leds + off, batch_sizes[i])) return rc;
+    off += (size_t)batch_sizes[i];
+  }
+  if (n_steps == 0) return FPM_OK;
+  hipStream_t st = (hipStream_t)stream;
+  MultiState ms{s->coeffs, s->m_c, s->v_c, s->z_um, s->m_z, s->v_z,
+                geo->geom, geo->m_geom, geo->v_geom};
+  multi_params_io<<<1, 64, 0, st>>>(ms, p->mpar, 1);
+  FPM_HIP(hipGetLastError());
+  const GeomArgs ga = geom_args(p, grid);
+  off = 0;
+  for (int i = 0; i < n_steps; ++i) {
+    MultiParams* cur = p->mpar + (i & 1);
+    MultiParams* next = p->mpar + ((i + 1) & 1);
+    const int B = batch_sizes[i];
+    const int rc = with_lr_size(p->N, [&](auto n) {
+      return launch_multi_step<decltype(n)::value>(p, ga, s, geo, hp, leds + off, B, meas_amp,
+                                                   cur, next, st);
+    });
+    if (rc) return rc;
+    off += (size_t)B;
+  }
+  multi_params_io<<<1, 64, 0, st>>>(ms, p->mpar + (n_steps & 1), 0);
+  FPM_HIP(hipGetLastError());
+  return FPM_OK;
 }
 
 int fpm_hr_transform(fpm_plan* p, const fpm_c32* in, fpm_c32* out, int32_t direction,

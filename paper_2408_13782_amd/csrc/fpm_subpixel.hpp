@@ -2,18 +2,24 @@
 // LED-array geometry, bilinear crop and its adjoint, gradients with respect to
 // the geometry and the LED intensities (paper Sec. 2.1 k_m and Eq. 3; Sec. 2.2).
 //
-// Launch order of one loss-and-gradient call:
-//   led_subpixel       offsets s_b = k_b(geometry) / dk, their Jacobian (FP64)
+// Every kernel derives the offsets of its batch slots itself, in FP64, from
+// the nominal grid and the current geometry errors (subslot_of), so no launch
+// is spent on them. Launch order of one loss-and-gradient call:
+//   pupil_build        P from the Zernike coefficients and defocus
 //   rows_forward_sub   bilinear crop C_b (4 taps) * P, inverse DFT of disk rows
 //   cols<.., kGamma>   as in the nearest path, plus sum e |psi| per workgroup
 //   rows_backward_sub  forward DFT of disk rows; patch conj(P) g_Phi; pupil
 //                      moments; dL/ds_b = sum Re(conj(g_C) dC/ds) partials
 //   gather_dense       g_O += sum_b sum_taps w_t patch_b (each pixel one thread)
 //   loss_grad_reduce   loss, Zernike/defocus, geometry (J_b^T dL/ds_b), gamma
+// and of one fused multi-parameter step: rows_forward_sub, cols,
+// rows_backward_sub, update_multi (Adam on the spectrum over the whole HR grid,
+// on the Zernike coefficients, defocus and geometry, and the pupil rebuild).
 #pragma once
 #include <hip/hip_runtime.h>
 
 #include "fft_line.hpp"
+#include "fpm_aux.hpp"
 #include "fpm_kernels.hpp"
 #include "fpm_optics.hpp"
 
@@ -36,14 +42,11 @@ struct GeomArgs {
   int N, M;
 };
 
-// Offsets of the batch's LEDs. With geom == NULL the plan's integer offsets
-// are used (zero fractional part, zero Jacobian). A window that would leave
-// the HR grid (with one pixel of bilinear margin) is clamped and counted in
-// *oob (the caller reports it).
-__global__ void led_subpixel(GeomArgs g, const double* __restrict__ geom, Batch bt,
-                             SubSlot* __restrict__ out, int* __restrict__ oob) {
-  const int b = threadIdx.x;
-  if (b >= bt.B) return;
+// Offsets of batch slot b. With geom == NULL the plan's integer offsets are
+// used (zero fractional part, zero Jacobian). A window that would leave the HR
+// grid (with one pixel of bilinear margin) is clamped; *clamped tells.
+__device__ inline SubSlot subslot_of(const GeomArgs& g, const double* __restrict__ geom,
+                                     const Batch& bt, int b, bool* clamped) {
   const int base = g.M / 2 - g.N / 2;
   SubSlot sl;
   for (int q = 0; q < 8; ++q) sl.J[q] = 0.0;
@@ -82,14 +85,20 @@ __global__ void led_subpixel(GeomArgs g, const double* __restrict__ geom, Batch 
   sl.ay = (float)(wr - fr);
   sl.ax = (float)(wc - fc);
   const int lo = 0, hi = g.M - g.N - 1;
-  if (fr < lo || fr > hi || fc < lo || fc > hi) {
-    atomicAdd(oob, 1);
-    fr = min(max(fr, lo), hi);
-    fc = min(max(fc, lo), hi);
+  *clamped = fr < lo || fr > hi || fc < lo || fc > hi;
+  sl.fr = min(max(fr, lo), hi);
+  sl.fc = min(max(fc, lo), hi);
+  return sl;
+}
+
+// The offsets of every slot of the batch into LDS (threads b < B compute slot b).
+__device__ __forceinline__ void subslots_to_lds(const GeomArgs& g, const double* geom,
+                                                const Batch& bt, SubSlot* sh) {
+  if ((int)threadIdx.x < bt.B) {
+    bool cl;
+    sh[threadIdx.x] = subslot_of(g, geom, bt, threadIdx.x, &cl);
   }
-  sl.fr = fr;
-  sl.fc = fc;
-  out[b] = sl;
+  __syncthreads();
 }
 
 // Bilinear sample of the spectrum at window (fr, fc) + (ky, kx) + (ay, ax).
@@ -113,8 +122,8 @@ __device__ __forceinline__ float2 blend(float2 t00, float2 t01, float2 t10, floa
 template <int N>
 __global__ void __launch_bounds__(kRowThreads)
 rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Batch bt, Disk dk,
-                 const SubSlot* __restrict__ sub, int chunks, float2* __restrict__ X,
-                 const float2* __restrict__ tw) {
+                 GeomArgs ga, const double* __restrict__ geom, int* __restrict__ oob,
+                 int chunks, float2* __restrict__ X, const float2* __restrict__ tw) {
   constexpr int T = RowPlan<N>::T;
   constexpr int E = N / T;
   constexpr int L = kRowThreads / T;
@@ -128,7 +137,9 @@ rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Bat
   const bool active = rr < dk.nrows;
   const int ky = dk.ky_lo + (active ? rr : 0);
   const int2 ext = disk_extent<N>(dk, ky);
-  const SubSlot sl = sub[b];
+  bool clamped;
+  const SubSlot sl = subslot_of(ga, geom, bt, b, &clamped);
+  if (clamped && c == 0 && threadIdx.x == 0 && oob) atomicAdd(oob, 1);
   const float2* prow = P + (size_t)ky * N;
   float2 v[E];
 #pragma unroll
@@ -155,8 +166,8 @@ constexpr int kSubPar = kPar + 2;   // pupil moments, then dL/ds (row, col)
 template <int N>
 __global__ void __launch_bounds__(kRowThreads)
 rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
-                  const float2* __restrict__ P, Batch bt, Disk dk, PupilGeom pg,
-                  const SubSlot* __restrict__ sub, int chunks, double* __restrict__ part,
+                  const float2* __restrict__ P, Batch bt, Disk dk, PupilGeom pg, GeomArgs ga,
+                  const double* __restrict__ geom, int chunks, double* __restrict__ part,
                   const float* __restrict__ kappa_tab, const float2* __restrict__ tw) {
   constexpr int T = RowPlan<N>::T;
   constexpr int E = N / T;
@@ -176,7 +187,8 @@ rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
   if (live) {
     float2* xr = X + ((size_t)b * N + ky) * N;
     const int2 ext = disk_extent<N>(dk, ky);
-    const SubSlot sl = sub[b];
+    bool clamped;
+    const SubSlot sl = subslot_of(ga, geom, bt, b, &clamped);
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = xr[t + m * T];
@@ -231,8 +243,10 @@ rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
 // 4 consecutive pixels, so every pixel is written by one thread (no atomics).
 template <int N>
 __global__ void __launch_bounds__(256)
-gather_dense(const float2* __restrict__ X, Batch bt, Disk dk, const SubSlot* __restrict__ sub,
-             float2* __restrict__ gO) {
+gather_dense(const float2* __restrict__ X, Batch bt, Disk dk, GeomArgs ga,
+             const double* __restrict__ geom, float2* __restrict__ gO) {
+  __shared__ SubSlot sub[kMaxSlots];
+  subslots_to_lds(ga, geom, bt, sub);
   const int tiles_per_row = bt.M / 32;
   const int tr0 = (blockIdx.x / tiles_per_row) * 32, tc0 = (blockIdx.x % tiles_per_row) * 32;
   const int r = tr0 + (threadIdx.x >> 3);
@@ -280,7 +294,8 @@ struct ReduceArgs {
   int col_wgs, col_chunks;
   const double* row_part;    // [row_wgs][kSubPar]
   int row_wgs, row_chunks;
-  const SubSlot* sub;
+  GeomArgs ga;
+  const double* geom;        // [4] or NULL (integer offsets)
   Batch bt;
   const float* gamma;        // [n_led] or NULL
   double* loss;              // += (nullable)
@@ -290,6 +305,8 @@ struct ReduceArgs {
 };
 
 __global__ void __launch_bounds__(256) loss_grad_reduce(ReduceArgs a) {
+  __shared__ SubSlot sub[kMaxSlots];
+  subslots_to_lds(a.ga, a.geom, a.bt, sub);
   __shared__ double red[256];
   __shared__ double mom[kPar];
   __shared__ double gs[kMaxSlots][2];
@@ -338,7 +355,7 @@ __global__ void __launch_bounds__(256) loss_grad_reduce(ReduceArgs a) {
       double gg[4] = {0.0, 0.0, 0.0, 0.0};
       for (int b = 0; b < a.bt.B; ++b)
         for (int p = 0; p < 4; ++p)
-          gg[p] += a.sub[b].J[p] * gs[b][0] + a.sub[b].J[4 + p] * gs[b][1];
+          gg[p] += sub[b].J[p] * gs[b][0] + sub[b].J[4 + p] * gs[b][1];
       for (int p = 0; p < 4; ++p) a.g_geom[p] += gg[p];
     }
     if (a.g_gamma) {
@@ -360,6 +377,255 @@ __global__ void __launch_bounds__(256) loss_grad_reduce(ReduceArgs a) {
       for (int k = 0; k < kMono; ++k) g += kZernMono[tid][k] * mom[k];
     }
     a.g_par[tid] += g;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Fused multi-parameter step: the learned scalars of step t live in a
+// parameter block (double-buffered by step parity), so that every kernel of a
+// step reads the geometry the step started with while its last kernel writes
+// the next one.
+
+struct MultiParams {
+  float c[kPar], m_c[kPar], v_c[kPar];   // Zernike 0..14, defocus at index 15
+  double g[4], m_g[4], v_g[4];           // LED-array geometry errors and their moments
+};
+
+// Copy the caller's scalar state into a parameter block, or back.
+struct MultiState {
+  float* coeffs; float* m_c; float* v_c;
+  float* z; float* m_z; float* v_z;
+  double* g; double* m_g; double* v_g;
+};
+
+__global__ void multi_params_io(MultiState s, MultiParams* __restrict__ blk, int to_block) {
+  const int i = threadIdx.x;
+  if (i < kPar) {
+    float* pc = i < kZern ? s.coeffs + i : s.z;
+    float* pm = i < kZern ? s.m_c + i : s.m_z;
+    float* pv = i < kZern ? s.v_c + i : s.v_z;
+    if (to_block) {
+      blk->c[i] = *pc;
+      blk->m_c[i] = *pm;
+      blk->v_c[i] = *pv;
+    } else {
+      *pc = blk->c[i];
+      *pm = blk->m_c[i];
+      *pv = blk->v_c[i];
+    }
+  } else if (i < kPar + 4) {
+    const int k = i - kPar;
+    if (to_block) {
+      blk->g[k] = s.g[k];
+      blk->m_g[k] = s.m_g[k];
+      blk->v_g[k] = s.v_g[k];
+    } else {
+      s.g[k] = blk->g[k];
+      s.m_g[k] = blk->m_g[k];
+      s.v_g[k] = blk->v_g[k];
+    }
+  }
+}
+
+struct MultiUpdateArgs {
+  int M;
+  float* O; float* mO; float* vO;
+  AdamCoef c;
+  const float2* X; Batch bt; Disk dk; GeomArgs ga;
+  const double* loss_part; int n_loss; double* loss;
+  const double* row_part; int n_rows, row_chunks;
+  const MultiParams* cur; MultiParams* next;
+  ScalarAdam sa;
+  int learn_geom; double lr_geom[4];
+  double* g_par; double* g_geom;      // diagnostics, += (nullable)
+  PupilGeom pg; float2* P;
+};
+
+// Last launch of a fused multi-parameter step:
+//  tile workgroups (after the pupil ones): Adam over every 32 x 32 tile of the
+//    HR grid (the union of windows moves with the geometry), the gradient
+//    gathered bilinearly from the batch's patches in batch order;
+//  pupil workgroups: sum the moment and offset-gradient partials in a fixed
+//    order, Adam on the Zernike coefficients, defocus and geometry (all of
+//    them compute the same numbers, workgroup 0 writes the next parameter
+//    block), rebuild their share of the pupil.
+template <int N>
+__global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
+  constexpr int kPer = pupil_per_wg(N);
+  const int n_pw = (N * N + kPer - 1) / kPer;
+  __shared__ SubSlot sub[kMaxSlots];
+  subslots_to_lds(a.ga, a.cur->g, a.bt, sub);
+  if ((int)blockIdx.x >= n_pw) {
+    const int ti = blockIdx.x - n_pw, tpr = a.M / 32;
+    const int tr0 = (ti / tpr) * 32, tc0 = (ti % tpr) * 32;
+    const int r = tr0 + (threadIdx.x >> 3);
+    const int c0 = tc0 + (threadIdx.x & 7) * 4;
+    const size_t f = ((size_t)r * a.M + c0) * 2;
+    float4* po = reinterpret_cast<float4*>(a.O + f);
+    float4* pm = reinterpret_cast<float4*>(a.mO + f);
+    float4* pv = reinterpret_cast<float4*>(a.vO + f);
+    float4 o[2], m[2], v[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      o[h] = po[h];
+      m[h] = pm[h];
+      v[h] = pv[h];
+    }
+    float2 g[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) g[q] = make_float2(0.f, 0.f);
+    for (int b = 0; b < a.bt.B; ++b) {
+      const SubSlot sl = sub[b];
+      if (tr0 + 31 < sl.fr + a.dk.ky_lo || tr0 > sl.fr + a.dk.ky_hi + 1 ||
+          tc0 + 31 < sl.fc + a.dk.ky_lo || tc0 > sl.fc + a.dk.ky_hi + 1)
+        continue;
+      const float wts[4] = {(1.f - sl.ay) * (1.f - sl.ax), (1.f - sl.ay) * sl.ax,
+                            sl.ay * (1.f - sl.ax), sl.ay * sl.ax};
+#pragma unroll
+      for (int tap = 0; tap < 4; ++tap) {
+        const int dy = tap >> 1, dxx = tap & 1;
+        const int ky = r - sl.fr - dy;
+        const int kyc = min(max(ky, a.dk.ky_lo), a.dk.ky_hi);
+        const int2 e = disk_extent<N>(a.dk, kyc);
+        const float2* xr = a.X + ((size_t)b * N + kyc) * N;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int kx = c0 + q - sl.fc - dxx;
+          const float2 val = xr[min(max(kx, e.x), e.y)];
+          if (ky == kyc && kx >= e.x && kx <= e.y) {
+            g[q].x += wts[tap] * val.x;
+            g[q].y += wts[tap] * val.y;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      adam1(o[h].x, m[h].x, v[h].x, g[2 * h].x, a.c);
+      adam1(o[h].y, m[h].y, v[h].y, g[2 * h].y, a.c);
+      adam1(o[h].z, m[h].z, v[h].z, g[2 * h + 1].x, a.c);
+      adam1(o[h].w, m[h].w, v[h].w, g[2 * h + 1].y, a.c);
+      store_next4<N>(po + h, o[h]);
+      store_next4<N>(pm + h, m[h]);
+      store_next4<N>(pv + h, v[h]);
+    }
+    return;
+  }
+  const int pw = blockIdx.x;
+  __shared__ double red[256];
+  __shared__ double gsum[kPar];
+  __shared__ double gs[kMaxSlots][2];
+  __shared__ double gg[4];
+  __shared__ float nextc[3][kPar];
+  __shared__ double nextg[3][4];
+  // pupil moments: thread (j, lane) sums partials lane, lane + 16, ...
+  {
+    const int j = threadIdx.x & (kPar - 1), lane = threadIdx.x / kPar;
+    double sj = 0.0;
+    for (int w = lane; w < a.n_rows; w += 256 / kPar) sj += a.row_part[(size_t)w * kSubPar + j];
+    red[threadIdx.x] = sj;
+  }
+  // offset gradients of each slot, from the workgroups that served it
+  if ((int)threadIdx.x < a.bt.B) {
+    double gy = 0.0, gx = 0.0;
+    for (int w = 0; w < a.n_rows; ++w) {
+      int b, c;
+      if (xcd_map(w, a.row_chunks, a.bt.B, b, c) && b == (int)threadIdx.x) {
+        gy += a.row_part[(size_t)w * kSubPar + kPar];
+        gx += a.row_part[(size_t)w * kSubPar + kPar + 1];
+      }
+    }
+    gs[threadIdx.x][0] = gy;
+    gs[threadIdx.x][1] = gx;
+  }
+  __syncthreads();
+  if (threadIdx.x < kPar) {
+    double mom = 0.0;
+    for (int k = 0; k < 256 / kPar; ++k) mom += red[k * kPar + threadIdx.x];
+    gsum[threadIdx.x] = mom;
+  }
+  if (threadIdx.x == 0) {
+    double t[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < a.bt.B; ++b)
+      for (int q = 0; q < 4; ++q) t[q] += sub[b].J[q] * gs[b][0] + sub[b].J[4 + q] * gs[b][1];
+    for (int q = 0; q < 4; ++q) gg[q] = t[q];
+  }
+  __syncthreads();
+  const int i = threadIdx.x;
+  if (i < kPar) {
+    double g = gsum[kZern];
+    if (i < kZern) {
+      g = 0.0;
+#pragma unroll
+      for (int k = 0; k < kMono; ++k) g += kZernMono[i][k] * gsum[k];
+    }
+    red[i] = g;
+    float p = a.cur->c[i], m = a.cur->m_c[i], v = a.cur->v_c[i];
+    const bool is_z = i == kZern;
+    const bool learn = is_z ? a.sa.learn_z : (a.sa.learn_c && i != 0);   // piston held
+    if (learn) {
+      const double lr = is_z ? a.sa.lr_z : a.sa.lr_c;
+      const double mm = a.sa.b1 * (double)m + (1.0 - a.sa.b1) * g;
+      const double vv = a.sa.b2 * (double)v + (1.0 - a.sa.b2) * g * g;
+      const double den = sqrt(vv) / a.sa.sqrt_bc2 + a.sa.eps;
+      p = (float)((double)p - lr / a.sa.bc1 * mm / den);
+      m = (float)mm;
+      v = (float)vv;
+    }
+    nextc[0][i] = p;
+    nextc[1][i] = m;
+    nextc[2][i] = v;
+  } else if (i < kPar + 4) {
+    const int k = i - kPar;
+    double p = a.cur->g[k], m = a.cur->m_g[k], v = a.cur->v_g[k];
+    if (a.learn_geom) {
+      const double g = gg[k];
+      m = a.sa.b1 * m + (1.0 - a.sa.b1) * g;
+      v = a.sa.b2 * v + (1.0 - a.sa.b2) * g * g;
+      p -= a.lr_geom[k] / a.sa.bc1 * m / (sqrt(v) / a.sa.sqrt_bc2 + a.sa.eps);
+    }
+    nextg[0][k] = p;
+    nextg[1][k] = m;
+    nextg[2][k] = v;
+  }
+  __syncthreads();
+  if (pw == 0) {
+    if (i < kPar) {
+      a.next->c[i] = nextc[0][i];
+      a.next->m_c[i] = nextc[1][i];
+      a.next->v_c[i] = nextc[2][i];
+      if (a.g_par) a.g_par[i] += red[i];
+    } else if (i < kPar + 4) {
+      const int k = i - kPar;
+      a.next->g[k] = nextg[0][k];
+      a.next->m_g[k] = nextg[1][k];
+      a.next->v_g[k] = nextg[2][k];
+      if (a.g_geom) a.g_geom[k] += gg[k];
+    }
+  }
+  // rebuild this workgroup's share of the pupil from the new parameters (FP64)
+  const int end = min((pw + 1) * kPer, N * N);
+  for (int idx = pw * kPer + threadIdx.x; idx < end; idx += 256) {
+    const int ky = idx / N, kx = idx - ky * N;
+    const int2 e = disk_extent<N>(a.dk, ky);
+    if (kx < e.x || kx > e.y) continue;   // off the disk P stays zero
+    const double ux = kx - N / 2, uy = ky - N / 2;
+    double z[kZern];
+    zernike15(ux * a.pg.inv_r, uy * a.pg.inv_r, z);
+    double th = 0.0;
+#pragma unroll
+    for (int q = 0; q < kZern; ++q) th += (double)nextc[0][q] * z[q];
+    th += (double)nextc[0][kZern] * defocus_kappa((ux * ux + uy * uy) * a.pg.dk2, a.pg.inv_l);
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    a.P[idx] = make_float2((float)cs, (float)sn);
+  }
+  if (pw == 0 && a.loss && threadIdx.x < 64) {
+    double s = 0.0;
+    for (int k = threadIdx.x; k < a.n_loss; k += 64) s += a.loss_part[k];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+    if (threadIdx.x == 0) *a.loss += s;
   }
 }
 

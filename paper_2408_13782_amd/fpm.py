@@ -68,6 +68,12 @@ class _Grads(C.Structure):
                 ("g_gamma", C.c_void_p), ("loss", C.c_void_p), ("oob", C.c_void_p)]
 
 
+class _Geometry(C.Structure):
+    _fields_ = [("geom", C.c_void_p), ("m_geom", C.c_void_p), ("v_geom", C.c_void_p),
+                ("g_geom", C.c_void_p), ("lr_shift_mm", C.c_double), ("lr_rot_rad", C.c_double),
+                ("lr_height_mm", C.c_double), ("learn", C.c_int32)]
+
+
 EXPORTS = {
     "fpm_plan_create": [C.POINTER(_Desc), C.c_void_p, C.POINTER(C.c_void_p)],
     "fpm_plan_destroy": [C.c_void_p],
@@ -87,6 +93,9 @@ EXPORTS = {
                 C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
     "fpm_loss_grad": [C.c_void_p, C.POINTER(_Grid), C.POINTER(_Params), C.c_void_p, C.c_int32,
                       C.c_void_p, C.POINTER(_Grads), C.c_void_p],
+    "fpm_run_multi": [C.c_void_p, C.POINTER(_Grid), C.POINTER(_State), C.POINTER(_Geometry),
+                      C.POINTER(_HParams), C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
+                      C.c_void_p],
     "fpm_hr_transform": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p],
     "fpm_init_spectrum": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "fpm_refocus": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p],
@@ -248,6 +257,30 @@ class State:
         return s
 
 
+class Geometry:
+    """Learned LED-array errors (shift_x_mm, shift_y_mm, rot_rad, dh_mm) with their Adam
+    moments, on the device (float64), for Plan.run_multi."""
+
+    def __init__(self, geom0=(0.0, 0.0, 0.0, 0.0), lr_shift_mm=5e-3, lr_rot_rad=5e-4,
+                 lr_height_mm=2e-2, learn=True, device="cuda"):
+        import torch
+        self.geom = torch.tensor(np.asarray(geom0, np.float64), device=device)
+        self.m = torch.zeros(4, dtype=torch.float64, device=device)
+        self.v = torch.zeros(4, dtype=torch.float64, device=device)
+        self.g = torch.zeros(4, dtype=torch.float64, device=device)
+        self.lr = (float(lr_shift_mm), float(lr_rot_rad), float(lr_height_mm))
+        self.learn = bool(learn)
+        self._c = _Geometry()
+
+    def c(self) -> _Geometry:
+        g = self._c
+        g.geom, g.m_geom, g.v_geom, g.g_geom = (self.geom.data_ptr(), self.m.data_ptr(),
+                                                self.v.data_ptr(), self.g.data_ptr())
+        g.lr_shift_mm, g.lr_rot_rad, g.lr_height_mm = self.lr
+        g.learn = int(self.learn)
+        return g
+
+
 class Plan:
     """One reconstruction problem's sizes, optics and LED table, with its scratch."""
 
@@ -394,6 +427,28 @@ class Plan:
         _check(self._lib.fpm_run(self._h, C.byref(cs), C.byref(hc), ids.ctypes.data,
                                  sizes.ctypes.data, int(sizes.size), _ptr(gamma), _ptr(meas_amp),
                                  _stream()))
+        state.t = cs.t
+
+    def run_multi(self, grid: LedGrid, state: State, geometry: Geometry, hp: HParams, leds_flat,
+                  batch_sizes, meas_amp):
+        """Fused multi-parameter updates (fpm_run_multi): spectrum, Zernikes, defocus and
+        LED-array geometry, batch i being the next batch_sizes[i] ids of leds_flat."""
+        import torch
+        sizes = np.ascontiguousarray(np.asarray(batch_sizes, np.int32))
+        ids, n = self._leds(leds_flat)
+        if int(sizes.sum()) > n:
+            raise FpmError("batch sizes exceed the number of LED ids")
+        self._images(meas_amp, None)
+        self._spectrum(state.O)
+        self._pupil(state.P)
+        for t in (geometry.geom, geometry.m, geometry.v, geometry.g):
+            _need(t, "geometry", torch.float64, (4,))
+        cs = state.c()
+        hc = hp.c()
+        gc = grid.c()
+        _check(self._lib.fpm_run_multi(self._h, C.byref(gc), C.byref(cs), C.byref(geometry.c()),
+                                       C.byref(hc), ids.ctypes.data, sizes.ctypes.data,
+                                       int(sizes.size), _ptr(meas_amp), _stream()))
         state.t = cs.t
 
     def loss_grad(self, grid: LedGrid, O, leds, meas_amp, coeffs=None, z_um=None, geom=None,

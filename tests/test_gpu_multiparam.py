@@ -324,3 +324,107 @@ def test_refocus_sweep_16_distances_over_1024(dev):
     want = fo.refocus(O.astype(np.complex128), z.astype(np.float64), opt)
     for i in range(len(z)):
         assert rel_l2(out[i], want[i]) <= GRAD_TOL, i
+
+
+# ---------------------------------------------------------------------------
+# fused multi-parameter updates (fpm_run_multi)
+
+
+def _multi_setup(case, dev, c0, z0, geom0, learn=True):
+    w = case.w
+    plan = case.plan()
+    st = fpm.State(plan, T(case.O0, dev), c0, z0)
+    geo = fpm.Geometry(geom0, lr_shift_mm=1e-3, lr_rot_rad=1e-3, lr_height_mm=1e-3, learn=learn)
+    hp = fpm.HParams(lr_object=w.lr_object, lr_zernike=w.lr_zernike, lr_z=w.lr_z,
+                     learn_zernike=True, learn_z=True)
+    return plan, st, geo, hp
+
+
+def test_fused_multi_step_gradients_and_update_match_oracle(dev, case):
+    say("fused multi-parameter step vs oracle")
+    w = case.w
+    c0 = inputs.random_real((15,), seed=41, lo=-0.2, hi=0.2)
+    c0[0] = 0.0
+    geom0 = 0.5 * case.geom_true
+    plan, st, geo, hp = _multi_setup(case, dev, c0, 1.2, geom0)
+    leds = inputs.random_indices(w.n_led, w.batch, seed=42)
+    plan.run_multi(case.grid, st, geo, hp, leds, [len(leds)], T(case.A, dev))
+    torch.cuda.synchronize()
+    O64 = case.O0.astype(np.complex128)
+    ref = case.oracle(O64, c0.astype(np.float64), float(np.float32(1.2)), geom0, None, leds)
+    assert abs(float(H(st.loss)[0]) - ref.loss) <= 1e-5 * ref.loss
+    # gradients accumulated for diagnostics
+    P = fo.pupil(case.mask, case.zern, c0.astype(np.float64), float(np.float32(1.2)), case.kappa)
+    s, J = fo.led_shifts_and_jacobian(case.opt, w.n_side, w.pitch_mm, w.height_mm, geom0)
+    sub = fo.loss_and_grads_subpixel(O64, P, s, leds, case.A.astype(np.float64))
+    _, _, g_theta = fo.pupil_param_grads(sub.g_P, P, case.zern, case.kappa)
+    g_par = H(st.g_par)
+    for j in range(15):
+        assert abs(g_par[j] - ref.g_coeffs[j]) <= GRAD_TOL * np.sum(np.abs(g_theta * case.zern[j]))
+    scale = np.zeros(4)
+    for b, led in enumerate(leds):
+        scale += np.abs(J[led].T) @ np.abs(sub.g_shift[b])
+    assert np.all(np.abs(H(geo.g) - ref.g_geom) <= 1e-4 * scale)
+    # Adam's first step is lr * sign(g) per real component
+    lr_g = np.array([1e-3] * 4)
+    want_g = geom0 - lr_g * np.sign(ref.g_geom)
+    np.testing.assert_allclose(H(geo.geom), want_g, rtol=0, atol=1e-9)
+    want_c = c0.astype(np.float64) - w.lr_zernike * np.sign(ref.g_coeffs)
+    want_c[0] = 0.0
+    np.testing.assert_allclose(H(st.coeffs), want_c, rtol=0, atol=1e-6)
+    np.testing.assert_allclose(float(H(st.z_um)[0]), 1.2 - w.lr_z * np.sign(ref.g_z), atol=1e-6)
+
+    def ri(z):
+        return np.stack([z.real, z.imag], -1).astype(np.float64)
+
+    O1, gg = ri(H(st.O)), ri(ref.g_O)
+    want_O = ri(O64) - w.lr_object * np.sign(gg)
+    decided = np.abs(gg) > 1e-4 * np.abs(gg).max()
+    diff = np.abs(O1 - want_O)
+    assert np.all(diff[decided] <= 1e-6 + 1e-6 * np.abs(want_O[decided]))
+    assert np.all(diff[~decided] <= 2 * w.lr_object * (1 + 1e-5))
+    # the pupil was rebuilt from the updated coefficients and defocus
+    P1 = fo.pupil(case.mask, case.zern, H(st.coeffs).astype(np.float64),
+                  float(H(st.z_um)[0]), case.kappa)
+    assert np.abs(H(st.P) - P1).max() <= 2e-6
+
+
+def test_fused_multi_run_matches_oracle_trajectory_and_is_deterministic(dev, case):
+    """Ten fused updates of every group against the same Adam updates (torch, FP64 on
+    the CPU) driven by the oracle's gradients; a second run is bitwise identical."""
+    say("fused multi-parameter run, 10 steps, vs oracle")
+    w = case.w
+    perms = inputs.led_permutations(w.n_led, 2, seed=7)
+    sched = fo.batches_from_permutations(perms, w.batch)[:10]
+    flat = np.concatenate(sched).astype(np.int32)
+    sizes = np.array([len(b) for b in sched], np.int32)
+    runs = []
+    for _ in range(2):
+        plan, st, geo, hp = _multi_setup(case, dev, np.zeros(15), 0.0, np.zeros(4))
+        plan.run_multi(case.grid, st, geo, hp, flat, sizes, T(case.A, dev))
+        torch.cuda.synchronize()
+        runs.append((H(st.O).copy(), H(st.coeffs).copy(), H(st.z_um).copy(), H(geo.geom).copy(),
+                     H(st.loss).copy()))
+        assert st.t == 10
+    for a, b in zip(runs[0], runs[1]):
+        np.testing.assert_array_equal(a, b)
+    O_r = torch.tensor(case.O0.astype(np.complex128), requires_grad=True)
+    c_r = torch.zeros(15, dtype=torch.float64, requires_grad=True)
+    z_r = torch.zeros(1, dtype=torch.float64, requires_grad=True)
+    g_r = torch.zeros(4, dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([dict(params=[O_r], lr=w.lr_object), dict(params=[c_r], lr=w.lr_zernike),
+                            dict(params=[z_r], lr=w.lr_z), dict(params=[g_r], lr=1e-3)])
+    for leds in sched:
+        gr = case.oracle(O_r.detach().numpy(), c_r.detach().numpy(), float(z_r.detach()[0]),
+                         g_r.detach().numpy(), None, leds)
+        O_r.grad = torch.tensor(gr.g_O)
+        c_r.grad = torch.tensor(gr.g_coeffs)
+        c_r.grad[0] = 0.0
+        z_r.grad = torch.tensor([gr.g_z], dtype=torch.float64)
+        g_r.grad = torch.tensor(gr.g_geom)
+        opt.step()
+    O, c, z, geom, _ = runs[0]
+    assert rel_l2(O, O_r.detach().numpy()) <= 1e-3
+    np.testing.assert_allclose(c, c_r.detach().numpy(), atol=0.2 * w.lr_zernike)
+    np.testing.assert_allclose(geom, g_r.detach().numpy(), atol=0.2 * 1e-3)
+    np.testing.assert_allclose(z, z_r.detach().numpy(), atol=0.2 * w.lr_z)

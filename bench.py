@@ -71,10 +71,11 @@ def union_support_px(plan) -> int:
     return int(cover.sum())
 
 
-def kernel_work(plan, B: int):
-    """Algorithmic (bytes, flops) per launch of each step kernel for a batch of B LEDs."""
+def kernel_work(plan, B: int, whole_grid: bool = False):
+    """Algorithmic (bytes, flops) per launch of each step kernel for a batch of B LEDs.
+    whole_grid: the fused multi-parameter step, whose Adam covers the whole HR grid."""
     N, S, rows = plan.N, plan.info.support_px, plan.info.support_rows
-    U = union_support_px(plan)
+    U = plan.M * plan.M if whole_grid else union_support_px(plan)
     return {
         # crop: read the spectrum on the pupil disk; 'rows' inverse DFTs of length N
         "rows_forward": (8.0 * S * B, rows * fft_flops(N) * B),
@@ -180,9 +181,23 @@ def multiparam_rate(w, prob, steps: int) -> dict:
     e1.record()
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1)
+    # the same groups through the fused multi-parameter step
+    st = fpm.State(plan, problem.initial_spectrum(prob))
+    geo = fpm.Geometry(lr_shift_mm=1e-3, lr_rot_rad=1e-3, lr_height_mm=1e-3)
+    hp = fpm.HParams(lr_object=w.lr_object, lr_zernike=w.lr_zernike, lr_z=w.lr_z,
+                     learn_zernike=True, learn_z=True)
+    ds = problem.flatten_schedule(batches[:10 + steps])
+    plan.run_multi(grid, st, geo, hp, *ds.span(0, 10), A)
+    torch.cuda.synchronize()
+    e0.record()
+    plan.run_multi(grid, st, geo, hp, *ds.span(10, 10 + steps), A)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_f = e0.elapsed_time(e1)
     return {"led_images_per_s": n_img / (ms / 1e3), "ms_per_step": ms / steps,
             "path": "fpm_loss_grad + torch.autograd + torch.optim.Adam (object, Zernike, "
-                    "defocus, LED-array geometry)"}
+                    "defocus, LED-array geometry)",
+            "fused_led_images_per_s": n_img / (ms_f / 1e3), "fused_ms_per_step": ms_f / steps}
 
 
 def batch_sweep(w, batches, epochs: int, log) -> dict:
@@ -272,12 +287,17 @@ def main():
         print(json.dumps(batch_sweep(w, args.batch_sweep, args.sweep_epochs, log)), flush=True)
         return
     log(f"workload {w.name}: {w.n_side}x{w.n_side} LEDs, N={w.n_lr}, M={w.m_hr}, B={w.batch}")
-    prob = problem.make_plan(w)
+    # workloads that learn the LED-array geometry: data from the true (seeded)
+    # geometry, solved from the nominal grid with the fused multi-parameter step
+    true_geom = inputs.true_geometry(w, 0) if w.learn_geometry else (0.0, 0.0, 0.0, 0.0)
+    prob = problem.make_plan(w, geometry=true_geom)
     problem.simulate(prob, seed=0)
     O0 = problem.initial_spectrum(prob)
     state = fpm.State(prob.plan, O0)
     hp = problem.hparams(w)
     plan = prob.plan
+    grid = fpm.LedGrid(w.n_side, w.pitch_mm, w.height_mm)
+    geometry = fpm.Geometry(lr_shift_mm=w.lr_shift, lr_rot_rad=w.lr_rot, lr_height_mm=w.lr_height)
     total = args.warmup + args.steps + args.profile_steps
     epochs = -(-total // w.steps_per_epoch())
     batches = problem.schedule(inputs.led_permutations(w.n_led, epochs, seed=0), w.batch)
@@ -288,7 +308,10 @@ def main():
 
     def run(start, stop):
         flat, sizes = ds.span(start, stop)
-        plan.run(state, hp, flat, sizes, A)
+        if w.learn_geometry:
+            plan.run_multi(grid, state, geometry, hp, flat, sizes, A)
+        else:
+            plan.run(state, hp, flat, sizes, A)
 
     run(0, args.warmup)
     torch.cuda.synchronize()
@@ -326,7 +349,7 @@ def main():
     # nothing after this pass reads it).
     REPS = 20
     per_pass = max(1, args.profile_steps // 4)
-    work, U = kernel_work(plan, w.batch)
+    work, U = kernel_work(plan, w.batch, whole_grid=w.learn_geometry)
     timed = {}
     start = args.warmup + args.steps
     for i, kind in enumerate(work):
@@ -367,8 +390,10 @@ def main():
         "per_kernel_mean_us": {k: v * 1e3 for k, v in timed.items()},
         "support_px": S, "union_px": U,
     }
-    detail["multiparam"] = multiparam_rate(w, prob, 100)
-    log(f"multi-parameter path: {detail['multiparam']['led_images_per_s']:.4g} LED-images/s")
+    if not w.learn_geometry:
+        detail["multiparam"] = multiparam_rate(w, prob, 100)
+        log(f"multi-parameter paths: fused {detail['multiparam']['fused_led_images_per_s']:.4g}, "
+            f"autograd {detail['multiparam']['led_images_per_s']:.4g} LED-images/s")
     # digital refocusing of the reconstruction: 16 distances in [-40, 40] um
     z = torch.linspace(-40.0, 40.0, 16, dtype=torch.float32, device="cuda")
     foc = torch.empty((16, plan.M, plan.M), dtype=torch.complex64, device="cuda")
@@ -391,7 +416,9 @@ def main():
         "config": {"workload": f"{w.name}: {w.n_side}x{w.n_side} LEDs, {w.n_lr}^2 LR -> "
                                f"{w.m_hr}^2 HR, batch {w.batch}, object"
                                + (" + Zernike pupil" if w.learn_zernike else "")
-                               + (" + defocus" if w.learn_z else ""),
+                               + (" + defocus" if w.learn_z else "")
+                               + (" + LED-array geometry (fused multi-parameter step)"
+                                  if w.learn_geometry else ""),
                    "n_led": w.n_led, "n_lr": w.n_lr, "m_hr": w.m_hr, "batch": w.batch},
         "roofline": roof,
         "detail": detail,

@@ -132,7 +132,9 @@ struct fpm_plan {
   double* part_lg = nullptr;  // partials of fpm_loss_grad (column pass | row pass)
   float2* P_ws = nullptr;     // [N][N] pupil built by fpm_loss_grad
   int* oob_ws = nullptr;      // window-clamp counter when the caller passes none
+  SubSlot* sub = nullptr;     // [max_batch] sub-pixel offsets of the current batch
   MultiParams* mpar = nullptr;  // [2] parameter blocks of fpm_run_multi
+  int* tile_flags = nullptr;  // [(M/32)^2] HR tiles with possibly non-zero Adam moments
   unsigned* counters = nullptr;  // completion counter of pupil_grad's reduction
   int loss_kind = FPM_LOSS_AMPLITUDE;
   bool timing = false;
@@ -201,6 +203,8 @@ void plan_free(fpm_plan* p) {
   (void)hipFree(p->P_ws);
   (void)hipFree(p->oob_ws);
   (void)hipFree(p->mpar);
+  (void)hipFree(p->sub);
+  (void)hipFree(p->tile_flags);
   (void)hipFree(p->counters);
   delete p;
 }
@@ -470,7 +474,8 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
   {
     Timed tm(p, kRowsForward, st);
     rows_forward_sub<N><<<g.rows(), kRowThreads, 0, st>>>(O, p->P_ws, bt, dk, ga, pr->geom,
-                                                          gr->oob, g.row_chunks, p->X, p->twN);
+                                                          gr->oob, p->sub, g.row_chunks, p->X,
+                                                          p->twN);
   }
   {
     Timed tm(p, kCols, st);
@@ -487,7 +492,7 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
   if (gr->g_O) {
     Timed tm(p, kAdamObject, st);
     gather_dense<N><<<(p->M / 32) * (p->M / 32), 256, 0, st>>>(
-        p->X, bt, dk, ga, pr->geom, reinterpret_cast<float2*>(gr->g_O));
+        p->X, bt, dk, p->sub, reinterpret_cast<float2*>(gr->g_O));
   }
   ReduceArgs ra;
   ra.col_part = col_part;
@@ -496,8 +501,7 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
   ra.row_part = row_part;
   ra.row_wgs = g.rows();
   ra.row_chunks = g.row_chunks;
-  ra.ga = ga;
-  ra.geom = pr->geom;
+  ra.sub = p->sub;
   ra.bt = bt;
   ra.gamma = pr->gamma;
   ra.loss = gr->loss;
@@ -528,7 +532,7 @@ int launch_multi_step(fpm_plan* p, const GeomArgs& ga, fpm_state* s, const fpm_g
     Timed tm(p, kRowsForward, st);
     for (int r = 0; r < tm.reps; ++r)
       rows_forward_sub<N><<<g.rows(), kRowThreads, 0, st>>>(O, P, bt, dk, ga, geom, p->oob_ws,
-                                                            g.row_chunks, p->X, p->twN);
+                                                            p->sub, g.row_chunks, p->X, p->twN);
   }
   {
     Timed tm(p, kCols, st);
@@ -549,6 +553,7 @@ int launch_multi_step(fpm_plan* p, const GeomArgs& ga, fpm_state* s, const fpm_g
   const double bc1 = 1.0 - std::pow(b1, t), bc2 = 1.0 - std::pow(b2, t);
   MultiUpdateArgs a{};
   a.M = p->M;
+  a.tile_flags = p->tile_flags;
   a.O = reinterpret_cast<float*>(s->O);
   a.mO = reinterpret_cast<float*>(s->m_O);
   a.vO = reinterpret_cast<float*>(s->v_O);
@@ -560,7 +565,7 @@ int launch_multi_step(fpm_plan* p, const GeomArgs& ga, fpm_state* s, const fpm_g
   a.X = p->X;
   a.bt = bt;
   a.dk = dk;
-  a.ga = ga;
+  a.sub = p->sub;
   a.loss_part = col_part;
   a.n_loss = g.cols();
   a.loss = s->loss;
@@ -749,7 +754,9 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
   if ((rc = upload<double>(&p->device_bytes, &p->part_lg, nullptr, (size_t)cols_grid * 2 + (size_t)rows_grid * kSubPar)) ||
       (rc = upload<float2>(&p->device_bytes, &p->P_ws, nullptr, (size_t)p->N * p->N)) ||
       (rc = upload<int>(&p->device_bytes, &p->oob_ws, nullptr, 1)) ||
-      (rc = upload<MultiParams>(&p->device_bytes, &p->mpar, nullptr, 2))) {
+      (rc = upload<MultiParams>(&p->device_bytes, &p->mpar, nullptr, 2)) ||
+      (rc = upload<SubSlot>(&p->device_bytes, &p->sub, nullptr, (size_t)p->max_batch)) ||
+      (rc = upload<int>(&p->device_bytes, &p->tile_flags, nullptr, tile_capacity(p)))) {
     plan_free(p);
     return rc;
   }
@@ -1099,6 +1106,9 @@ int fpm_run_multi(fpm_plan* p, const fpm_led_grid* grid, fpm_state* s, fpm_geome
   MultiState ms{s->coeffs, s->m_c, s->v_c, s->z_um, s->m_z, s->v_z,
                 geo->geom, geo->m_geom, geo->v_geom};
   multi_params_io<<<1, 64, 0, st>>>(ms, p->mpar, 1);
+  tiles_with_moments<<<(p->M / 32) * (p->M / 32), 256, 0, st>>>(
+      reinterpret_cast<const float*>(s->m_O), reinterpret_cast<const float*>(s->v_O), p->M,
+      p->tile_flags);
   FPM_HIP(hipGetLastError());
   const GeomArgs ga = geom_args(p, grid);
   off = 0;

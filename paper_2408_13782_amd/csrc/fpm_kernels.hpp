@@ -141,6 +141,26 @@ __device__ __forceinline__ void store_next4(float4* p, float4 v) {
   }
 }
 
+// sum_{i < n} src[i * stride] in increasing i, the loads issued kU at a time.
+template <int kU = 16>
+__device__ __forceinline__ double ordered_sum(const double* __restrict__ src, int n, int stride) {
+  double s = 0.0;
+  for (int i0 = 0; i0 < n; i0 += kU) {
+    double v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) v[u] = src[(size_t)min(i0 + u, n - 1) * stride];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (i0 + u < n) s += v[u];
+  }
+  return s;
+}
+
+// Inverse of xcd_map: the workgroup that serves chunk c of batch slot b.
+__device__ __forceinline__ int xcd_wg(int b, int c, int chunks) {
+  return (b % kXcds) + kXcds * ((b / kXcds) * chunks + c);
+}
+
 __device__ __forceinline__ void atomic_add_c(float2* p, float2 v) {
   float* f = reinterpret_cast<float*>(p);
   unsafeAtomicAdd(f, v.x);

@@ -91,13 +91,11 @@ __device__ inline SubSlot subslot_of(const GeomArgs& g, const double* __restrict
   return sl;
 }
 
-// The offsets of every slot of the batch into LDS (threads b < B compute slot b).
-__device__ __forceinline__ void subslots_to_lds(const GeomArgs& g, const double* geom,
+// The offsets of every slot of the batch into LDS, from the copies that
+// rows_forward_sub stored (threads b < B load slot b).
+__device__ __forceinline__ void subslots_to_lds(const SubSlot* __restrict__ stored,
                                                 const Batch& bt, SubSlot* sh) {
-  if ((int)threadIdx.x < bt.B) {
-    bool cl;
-    sh[threadIdx.x] = subslot_of(g, geom, bt, threadIdx.x, &cl);
-  }
+  if ((int)threadIdx.x < bt.B) sh[threadIdx.x] = stored[threadIdx.x];
   __syncthreads();
 }
 
@@ -123,7 +121,8 @@ template <int N>
 __global__ void __launch_bounds__(kRowThreads)
 rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Batch bt, Disk dk,
                  GeomArgs ga, const double* __restrict__ geom, int* __restrict__ oob,
-                 int chunks, float2* __restrict__ X, const float2* __restrict__ tw) {
+                 SubSlot* __restrict__ sub_out, int chunks, float2* __restrict__ X,
+                 const float2* __restrict__ tw) {
   constexpr int T = RowPlan<N>::T;
   constexpr int E = N / T;
   constexpr int L = kRowThreads / T;
@@ -139,7 +138,10 @@ rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Bat
   const int2 ext = disk_extent<N>(dk, ky);
   bool clamped;
   const SubSlot sl = subslot_of(ga, geom, bt, b, &clamped);
-  if (clamped && c == 0 && threadIdx.x == 0 && oob) atomicAdd(oob, 1);
+  if (c == 0 && threadIdx.x == 0) {
+    if (clamped && oob) atomicAdd(oob, 1);
+    sub_out[b] = sl;   // for the later kernels of the call
+  }
   const float2* prow = P + (size_t)ky * N;
   float2 v[E];
 #pragma unroll
@@ -239,29 +241,43 @@ rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
   block_partials<kSubPar>(acc, part);
 }
 
-// g_O += sum over slots and taps of w_t patch_b(p - f_b - t); one thread per
-// 4 consecutive pixels, so every pixel is written by one thread (no atomics).
+// Window corner and fractional offsets of every batch slot, compact, in LDS,
+// and the mask of the slots whose window (disk box, one pixel wider for the
+// taps) meets the 32 x 32 tile at (tr0, tc0). Uniform over the workgroup.
+struct Corner {
+  int fr, fc;
+  float ay, ax;
+};
+
+__device__ __forceinline__ unsigned long long tile_slots(const SubSlot* __restrict__ stored,
+                                                          const Batch& bt, const Disk& dk,
+                                                          int tr0, int tc0, Corner* cs) {
+  __shared__ unsigned long long mask;
+  if (threadIdx.x == 0) mask = 0ull;
+  __syncthreads();
+  if ((int)threadIdx.x < bt.B) {
+    const SubSlot sl = stored[threadIdx.x];
+    cs[threadIdx.x] = Corner{sl.fr, sl.fc, sl.ay, sl.ax};
+    const bool meets = !(tr0 + 31 < sl.fr + dk.ky_lo || tr0 > sl.fr + dk.ky_hi + 1 ||
+                         tc0 + 31 < sl.fc + dk.ky_lo || tc0 > sl.fc + dk.ky_hi + 1);
+    if (meets) atomicOr(&mask, 1ull << threadIdx.x);
+  }
+  __syncthreads();
+  return mask;
+}
+
+// Bilinear adjoint at 4 consecutive pixels (row r, columns c0..c0+3): the sum,
+// over the slots of `hit` in batch order and their 4 taps, of w_t patch_b(p - f_b - t).
 template <int N>
-__global__ void __launch_bounds__(256)
-gather_dense(const float2* __restrict__ X, Batch bt, Disk dk, GeomArgs ga,
-             const double* __restrict__ geom, float2* __restrict__ gO) {
-  __shared__ SubSlot sub[kMaxSlots];
-  subslots_to_lds(ga, geom, bt, sub);
-  const int tiles_per_row = bt.M / 32;
-  const int tr0 = (blockIdx.x / tiles_per_row) * 32, tc0 = (blockIdx.x % tiles_per_row) * 32;
-  const int r = tr0 + (threadIdx.x >> 3);
-  const int c0 = tc0 + (threadIdx.x & 7) * 4;
-  float2 g[4];
-  bool any = false;
+__device__ __forceinline__ void gather_bilinear(const float2* __restrict__ X, const Disk& dk,
+                                                const Corner* cs, unsigned long long hit,
+                                                int r, int c0, float2 (&g)[4]) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) g[q] = make_float2(0.f, 0.f);
-  for (int b = 0; b < bt.B; ++b) {
-    const SubSlot sl = sub[b];
-    // disk box of the window, one pixel wider for the taps
-    if (tr0 + 31 < sl.fr + dk.ky_lo || tr0 > sl.fr + dk.ky_hi + 1 ||
-        tc0 + 31 < sl.fc + dk.ky_lo || tc0 > sl.fc + dk.ky_hi + 1)
-      continue;
-    any = true;
+  while (hit) {
+    const int b = __ffsll((long long)hit) - 1;
+    hit &= hit - 1;
+    const Corner sl = cs[b];
     const float wts[4] = {(1.f - sl.ay) * (1.f - sl.ax), (1.f - sl.ay) * sl.ax,
                           sl.ay * (1.f - sl.ax), sl.ay * sl.ax};
 #pragma unroll
@@ -282,7 +298,23 @@ gather_dense(const float2* __restrict__ X, Batch bt, Disk dk, GeomArgs ga,
       }
     }
   }
-  if (!any) return;
+}
+
+// g_O += the batch's bilinear adjoint; one thread per 4 consecutive pixels of a
+// 32 x 32 tile, so every pixel is written by one thread (no atomics).
+template <int N>
+__global__ void __launch_bounds__(256)
+gather_dense(const float2* __restrict__ X, Batch bt, Disk dk,
+             const SubSlot* __restrict__ stored, float2* __restrict__ gO) {
+  __shared__ Corner cs[kMaxSlots];
+  const int tiles_per_row = bt.M / 32;
+  const int tr0 = (blockIdx.x / tiles_per_row) * 32, tc0 = (blockIdx.x % tiles_per_row) * 32;
+  const unsigned long long hit = tile_slots(stored, bt, dk, tr0, tc0, cs);
+  if (!hit) return;
+  const int r = tr0 + (threadIdx.x >> 3);
+  const int c0 = tc0 + (threadIdx.x & 7) * 4;
+  float2 g[4];
+  gather_bilinear<N>(X, dk, cs, hit, r, c0, g);
   float2* out = gO + (size_t)r * bt.M + c0;
 #pragma unroll
   for (int q = 0; q < 4; ++q) out[q] = make_float2(out[q].x + g[q].x, out[q].y + g[q].y);
@@ -294,8 +326,7 @@ struct ReduceArgs {
   int col_wgs, col_chunks;
   const double* row_part;    // [row_wgs][kSubPar]
   int row_wgs, row_chunks;
-  GeomArgs ga;
-  const double* geom;        // [4] or NULL (integer offsets)
+  const SubSlot* sub;        // [B] offsets stored by rows_forward_sub
   Batch bt;
   const float* gamma;        // [n_led] or NULL
   double* loss;              // += (nullable)
@@ -306,7 +337,7 @@ struct ReduceArgs {
 
 __global__ void __launch_bounds__(256) loss_grad_reduce(ReduceArgs a) {
   __shared__ SubSlot sub[kMaxSlots];
-  subslots_to_lds(a.ga, a.geom, a.bt, sub);
+  subslots_to_lds(a.sub, a.bt, sub);
   __shared__ double red[256];
   __shared__ double mom[kPar];
   __shared__ double gs[kMaxSlots][2];
@@ -315,9 +346,8 @@ __global__ void __launch_bounds__(256) loss_grad_reduce(ReduceArgs a) {
   // pupil moments: thread (j, lane) sums workgroups lane, lane + 16, ...
   {
     const int j = tid & (kPar - 1), lane = tid / kPar;
-    double s = 0.0;
-    for (int w = lane; w < a.row_wgs; w += 256 / kPar) s += a.row_part[(size_t)w * kSubPar + j];
-    red[tid] = s;
+    const int cnt = lane < a.row_wgs ? (a.row_wgs - lane + 256 / kPar - 1) / (256 / kPar) : 0;
+    red[tid] = ordered_sum(a.row_part + (size_t)lane * kSubPar + j, cnt, (256 / kPar) * kSubPar);
     __syncthreads();
     if (tid < kPar) {
       double m = 0.0;
@@ -328,18 +358,12 @@ __global__ void __launch_bounds__(256) loss_grad_reduce(ReduceArgs a) {
   }
   // per slot: dL/ds from the row pass, sum e |psi| from the column pass
   if (tid < a.bt.B) {
-    double gy = 0.0, gx = 0.0, e = 0.0;
-    for (int w = 0; w < a.row_wgs; ++w) {
-      int b, c;
-      if (xcd_map(w, a.row_chunks, a.bt.B, b, c) && b == tid) {
-        gy += a.row_part[(size_t)w * kSubPar + kPar];
-        gx += a.row_part[(size_t)w * kSubPar + kPar + 1];
-      }
-    }
-    for (int w = 0; w < a.col_wgs; ++w) {
-      int b, c;
-      if (xcd_map(w, a.col_chunks, a.bt.B, b, c) && b == tid) e += a.col_part[(size_t)w * 2 + 1];
-    }
+    // the workgroups of slot tid are xcd_wg(tid, c) = xcd_wg(tid, 0) + 8 c
+    const double* rp = a.row_part + (size_t)xcd_wg(tid, 0, a.row_chunks) * kSubPar;
+    const double gy = ordered_sum(rp + kPar, a.row_chunks, kXcds * kSubPar);
+    const double gx = ordered_sum(rp + kPar + 1, a.row_chunks, kXcds * kSubPar);
+    const double e = ordered_sum(a.col_part + (size_t)xcd_wg(tid, 0, a.col_chunks) * 2 + 1,
+                                 a.col_chunks, kXcds * 2);
     gs[tid][0] = gy;
     gs[tid][1] = gx;
     ea[tid] = e;
@@ -427,11 +451,36 @@ __global__ void multi_params_io(MultiState s, MultiParams* __restrict__ blk, int
   }
 }
 
+// Mark the 32 x 32 HR tiles whose Adam moments are not all zero (the tiles a
+// multi-parameter run must keep updating even when no window of the batch
+// covers them). One workgroup per tile.
+__global__ void __launch_bounds__(256) tiles_with_moments(const float* __restrict__ mO,
+                                                          const float* __restrict__ vO, int M,
+                                                          int* __restrict__ flags) {
+  const int tpr = M / 32;
+  const int r = (blockIdx.x / tpr) * 32 + (threadIdx.x >> 3);
+  const int c0 = (blockIdx.x % tpr) * 32 + (threadIdx.x & 7) * 4;
+  const size_t f = ((size_t)r * M + c0) * 2;
+  const float4* pm = reinterpret_cast<const float4*>(mO + f);
+  const float4* pv = reinterpret_cast<const float4*>(vO + f);
+  bool nz = false;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const float4 m = pm[h], v = pv[h];
+    nz = nz || m.x != 0.f || m.y != 0.f || m.z != 0.f || m.w != 0.f || v.x != 0.f ||
+         v.y != 0.f || v.z != 0.f || v.w != 0.f;
+  }
+  nz = __syncthreads_or(nz);
+  if (threadIdx.x == 0) flags[blockIdx.x] = nz ? 1 : 0;
+}
+
 struct MultiUpdateArgs {
   int M;
+  int* tile_flags;                    // [(M/32)^2] 1: moments may be non-zero
   float* O; float* mO; float* vO;
   AdamCoef c;
-  const float2* X; Batch bt; Disk dk; GeomArgs ga;
+  const float2* X; Batch bt; Disk dk;
+  const SubSlot* sub;                 // [B] offsets stored by rows_forward_sub
   const double* loss_part; int n_loss; double* loss;
   const double* row_part; int n_rows, row_chunks;
   const MultiParams* cur; MultiParams* next;
@@ -453,11 +502,16 @@ template <int N>
 __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
   constexpr int kPer = pupil_per_wg(N);
   const int n_pw = (N * N + kPer - 1) / kPer;
-  __shared__ SubSlot sub[kMaxSlots];
-  subslots_to_lds(a.ga, a.cur->g, a.bt, sub);
   if ((int)blockIdx.x >= n_pw) {
+    __shared__ Corner cs[kMaxSlots];
     const int ti = blockIdx.x - n_pw, tpr = a.M / 32;
     const int tr0 = (ti / tpr) * 32, tc0 = (ti % tpr) * 32;
+    // Adam moves a pixel only if its moments or its gradient are non-zero: a tile
+    // that no window of this batch covers and whose moments are all zero stays
+    // as it is (exactly), and is skipped
+    const unsigned long long hit = tile_slots(a.sub, a.bt, a.dk, tr0, tc0, cs);
+    if (!hit && !a.tile_flags[ti]) return;
+    if (hit && threadIdx.x == 0) a.tile_flags[ti] = 1;
     const int r = tr0 + (threadIdx.x >> 3);
     const int c0 = tc0 + (threadIdx.x & 7) * 4;
     const size_t f = ((size_t)r * a.M + c0) * 2;
@@ -466,39 +520,13 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
     float4* pv = reinterpret_cast<float4*>(a.vO + f);
     float4 o[2], m[2], v[2];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
+    for (int h = 0; h < 2; ++h) {   // in flight while the gradient is gathered
       o[h] = po[h];
       m[h] = pm[h];
       v[h] = pv[h];
     }
     float2 g[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) g[q] = make_float2(0.f, 0.f);
-    for (int b = 0; b < a.bt.B; ++b) {
-      const SubSlot sl = sub[b];
-      if (tr0 + 31 < sl.fr + a.dk.ky_lo || tr0 > sl.fr + a.dk.ky_hi + 1 ||
-          tc0 + 31 < sl.fc + a.dk.ky_lo || tc0 > sl.fc + a.dk.ky_hi + 1)
-        continue;
-      const float wts[4] = {(1.f - sl.ay) * (1.f - sl.ax), (1.f - sl.ay) * sl.ax,
-                            sl.ay * (1.f - sl.ax), sl.ay * sl.ax};
-#pragma unroll
-      for (int tap = 0; tap < 4; ++tap) {
-        const int dy = tap >> 1, dxx = tap & 1;
-        const int ky = r - sl.fr - dy;
-        const int kyc = min(max(ky, a.dk.ky_lo), a.dk.ky_hi);
-        const int2 e = disk_extent<N>(a.dk, kyc);
-        const float2* xr = a.X + ((size_t)b * N + kyc) * N;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int kx = c0 + q - sl.fc - dxx;
-          const float2 val = xr[min(max(kx, e.x), e.y)];
-          if (ky == kyc && kx >= e.x && kx <= e.y) {
-            g[q].x += wts[tap] * val.x;
-            g[q].y += wts[tap] * val.y;
-          }
-        }
-      }
-    }
+    gather_bilinear<N>(a.X, a.dk, cs, hit, r, c0, g);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       adam1(o[h].x, m[h].x, v[h].x, g[2 * h].x, a.c);
@@ -521,20 +549,15 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
   // pupil moments: thread (j, lane) sums partials lane, lane + 16, ...
   {
     const int j = threadIdx.x & (kPar - 1), lane = threadIdx.x / kPar;
-    double sj = 0.0;
-    for (int w = lane; w < a.n_rows; w += 256 / kPar) sj += a.row_part[(size_t)w * kSubPar + j];
-    red[threadIdx.x] = sj;
+    const int cnt = lane < a.n_rows ? (a.n_rows - lane + 256 / kPar - 1) / (256 / kPar) : 0;
+    red[threadIdx.x] = ordered_sum(a.row_part + (size_t)lane * kSubPar + j, cnt,
+                                   (256 / kPar) * kSubPar);
   }
   // offset gradients of each slot, from the workgroups that served it
   if ((int)threadIdx.x < a.bt.B) {
-    double gy = 0.0, gx = 0.0;
-    for (int w = 0; w < a.n_rows; ++w) {
-      int b, c;
-      if (xcd_map(w, a.row_chunks, a.bt.B, b, c) && b == (int)threadIdx.x) {
-        gy += a.row_part[(size_t)w * kSubPar + kPar];
-        gx += a.row_part[(size_t)w * kSubPar + kPar + 1];
-      }
-    }
+    const double* rp = a.row_part + (size_t)xcd_wg(threadIdx.x, 0, a.row_chunks) * kSubPar;
+    const double gy = ordered_sum(rp + kPar, a.row_chunks, kXcds * kSubPar);
+    const double gx = ordered_sum(rp + kPar + 1, a.row_chunks, kXcds * kSubPar);
     gs[threadIdx.x][0] = gy;
     gs[threadIdx.x][1] = gx;
   }
@@ -547,7 +570,8 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
   if (threadIdx.x == 0) {
     double t[4] = {0.0, 0.0, 0.0, 0.0};
     for (int b = 0; b < a.bt.B; ++b)
-      for (int q = 0; q < 4; ++q) t[q] += sub[b].J[q] * gs[b][0] + sub[b].J[4 + q] * gs[b][1];
+      for (int q = 0; q < 4; ++q)
+        t[q] += a.sub[b].J[q] * gs[b][0] + a.sub[b].J[4 + q] * gs[b][1];
     for (int q = 0; q < 4; ++q) gg[q] = t[q];
   }
   __syncthreads();

@@ -35,16 +35,17 @@ FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, no packe
 
 # HBM bytes per launch of a kernel from rocprofv3 counters (FETCH_SIZE x 2 +
 # WRITE_SIZE; the factor 2 is what a plain device copy of known size reads on
-# the same counter), for the kernel build they were taken on.
+# the same counter), for the kernel build they were taken on. The large
+# workload's kernels are those of the fused multi-parameter step.
 TRAFFIC = {
     ("paper", "rows_forward"): (1938.1 * 2 + 4788.7) * 1024,
     ("paper", "cols"): (4456.7 * 2 + 4843.4) * 1024,
     ("paper", "rows_backward"): (4460.9 * 2 + 2450.0) * 1024,
     ("paper", "update"): (7203.0 * 2 + 11810.3) * 1024,
-    ("large", "rows_forward"): (14131.2 * 2 + 39614.7) * 1024,
-    ("large", "cols"): (36179.4 * 2 + 39784.9) * 1024,
-    ("large", "rows_backward"): (33817.8 * 2 + 19586.9) * 1024,
-    ("large", "update"): (45635.1 * 2 + 58430.6) * 1024,
+    ("large", "rows_forward"): (14824.0 * 2 + 39716.4) * 1024,
+    ("large", "cols"): (36177.4 * 2 + 39785.5) * 1024,
+    ("large", "rows_backward"): (34244.7 * 2 + 19665.9) * 1024,
+    ("large", "update"): (45252.0 * 2 + 58248.7) * 1024,
 }
 
 
@@ -71,11 +72,12 @@ def union_support_px(plan) -> int:
     return int(cover.sum())
 
 
-def kernel_work(plan, B: int, whole_grid: bool = False):
+def kernel_work(plan, B: int):
     """Algorithmic (bytes, flops) per launch of each step kernel for a batch of B LEDs.
-    whole_grid: the fused multi-parameter step, whose Adam covers the whole HR grid."""
+    Adam's share is the union U of the LED windows (the pixels whose gradient can
+    be non-zero; with a learned geometry, U at the plan's table)."""
     N, S, rows = plan.N, plan.info.support_px, plan.info.support_rows
-    U = plan.M * plan.M if whole_grid else union_support_px(plan)
+    U = union_support_px(plan)
     return {
         # crop: read the spectrum on the pupil disk; 'rows' inverse DFTs of length N
         "rows_forward": (8.0 * S * B, rows * fft_flops(N) * B),
@@ -349,7 +351,7 @@ def main():
     # nothing after this pass reads it).
     REPS = 20
     per_pass = max(1, args.profile_steps // 4)
-    work, U = kernel_work(plan, w.batch, whole_grid=w.learn_geometry)
+    work, U = kernel_work(plan, w.batch)
     timed = {}
     start = args.warmup + args.steps
     for i, kind in enumerate(work):

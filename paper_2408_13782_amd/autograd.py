@@ -29,22 +29,33 @@ class LossContext:
 class FPMLoss(torch.autograd.Function):
     @staticmethod
     def forward(fctx, O, coeffs, z_um, geom, gamma, lctx: LossContext):
-        g = lctx.plan.loss_grad(lctx.grid, O.detach(), lctx.leds, lctx.meas_amp,
-                                coeffs=None if coeffs is None else coeffs.detach(),
-                                z_um=None if z_um is None else z_um.detach(),
-                                geom=None if geom is None else geom.detach(),
-                                gamma=None if gamma is None else gamma.detach())
-        fctx.grads = (g["g_O"],
-                      None if coeffs is None else g["g_par"][:fpm.N_ZERN].to(coeffs.dtype),
-                      None if z_um is None else g["g_par"][fpm.N_ZERN:].to(z_um.dtype),
-                      None if geom is None else g["g_geom"].to(geom.dtype),
-                      None if gamma is None else g["g_gamma"].to(gamma.dtype))
+        plan = lctx.plan
+        # the scalar accumulators in one buffer: loss | g_par (16) | g_geom (4) | g_gamma
+        n = plan.n_led
+        flat = torch.zeros(1 + fpm.N_PAR + 4 + n, dtype=torch.float64, device=O.device)
+        grads = {"loss": flat[:1], "g_par": flat[1:1 + fpm.N_PAR],
+                 "g_geom": flat[1 + fpm.N_PAR:5 + fpm.N_PAR], "g_gamma": flat[5 + fpm.N_PAR:],
+                 "g_O": torch.zeros_like(O, memory_format=torch.contiguous_format),
+                 "oob": torch.zeros(1, dtype=torch.int32, device=O.device)}
+        g = plan.loss_grad(lctx.grid, O.detach(), lctx.leds, lctx.meas_amp,
+                           coeffs=None if coeffs is None else coeffs.detach(),
+                           z_um=None if z_um is None else z_um.detach(),
+                           geom=None if geom is None else geom.detach(),
+                           gamma=None if gamma is None else gamma.detach(), grads=grads)
+        fctx.flat, fctx.g_O = flat, g["g_O"]
+        fctx.dtypes = tuple(None if t is None else t.dtype for t in (coeffs, z_um, geom, gamma))
         fctx.oob = g["oob"]
-        return g["loss"][0]
+        return flat[0].clone()
 
     @staticmethod
     def backward(fctx, grad_out):
-        out = []
-        for gr in fctx.grads:
-            out.append(None if gr is None else gr * grad_out.to(gr.real.dtype))
+        c_t, z_t, g_t, gm_t = fctx.dtypes
+        go = grad_out.to(torch.float64)
+        flat = fctx.flat * go                    # every scalar group in one kernel
+        par = flat[1:1 + fpm.N_PAR]
+        out = [fctx.g_O * go.to(torch.float32),
+               None if c_t is None else par[:fpm.N_ZERN].to(c_t),
+               None if z_t is None else par[fpm.N_ZERN:].to(z_t),
+               None if g_t is None else flat[1 + fpm.N_PAR:5 + fpm.N_PAR].to(g_t),
+               None if gm_t is None else flat[5 + fpm.N_PAR:].to(gm_t)]
         return (*out, None)

@@ -428,3 +428,54 @@ def test_fused_multi_run_matches_oracle_trajectory_and_is_deterministic(dev, cas
     np.testing.assert_allclose(c, c_r.detach().numpy(), atol=0.2 * w.lr_zernike)
     np.testing.assert_allclose(geom, g_r.detach().numpy(), atol=0.2 * 1e-3)
     np.testing.assert_allclose(z, z_r.detach().numpy(), atol=0.2 * w.lr_z)
+
+
+def test_fused_multi_step_at_the_large_size_matches_oracle(dev):
+    """One fused multi-parameter step at 512^2 -> 2048^2, B = 32 (the launch shape the
+    large benchmark times): loss and every parameter group's gradient."""
+    w = inputs.workload("large")
+    say("fused multi-parameter step, large size")
+    opt = optics_of(w)
+    geom_true = np.array(inputs.true_geometry(w, 0))
+    k = fo.led_wavevectors(opt, w.n_side, w.pitch_mm, w.height_mm, *geom_true)
+    shifts_true = fo.nearest_shifts(fo.led_shifts(opt, k))
+    amp, ph = inputs.truth_object(w.m_hr, seed=0)
+    O_true = fo.spectrum(fo.transmission(amp, ph))
+    mask, zern, kappa = fo.pupil_mask(opt), fo.zernike_basis(opt), fo.defocus_phase_per_um(opt)
+    P_true = fo.pupil(mask, zern, np.zeros(15), inputs.true_defocus(w, 0), kappa)
+    leds = inputs.random_indices(w.n_led, w.batch, seed=8)
+    # measurements only for the batch's LEDs (the others are never read)
+    A = np.zeros((w.n_led, w.n_lr, w.n_lr), np.float32)
+    A[leds] = inputs.poisson_amplitudes(fo.forward_intensities(O_true, P_true, shifts_true, leds),
+                                        np.full(len(leds), w.q_bright), seed=0)
+    O0 = (O_true * 0.9).astype(np.complex64)
+    c0 = inputs.random_real((15,), seed=9, lo=-0.1, hi=0.1)
+    c0[0] = 0.0
+    geom0 = 0.5 * geom_true
+    k0 = fo.led_wavevectors(opt, w.n_side, w.pitch_mm, w.height_mm)
+    plan = fpm.Plan(w.n_lr, w.upsample, fo.nearest_shifts(fo.led_shifts(opt, k0)), w.batch,
+                    w.wavelength_um, w.na, w.mag, w.pixel_um)
+    st = fpm.State(plan, T(O0, dev), c0, 0.7)
+    geo = fpm.Geometry(geom0, lr_shift_mm=1e-3, lr_rot_rad=1e-3, lr_height_mm=1e-3)
+    hp = fpm.HParams(lr_object=w.lr_object, lr_zernike=w.lr_zernike, lr_z=w.lr_z,
+                     learn_zernike=True, learn_z=True)
+    plan.run_multi(fpm.LedGrid(w.n_side, w.pitch_mm, w.height_mm), st, geo, hp, leds,
+                   [len(leds)], T(A, dev))
+    torch.cuda.synchronize()
+    z0 = float(np.float32(0.7))
+    ref = fo.multiparam_loss_and_grads(O0.astype(np.complex128), c0.astype(np.float64), z0, geom0,
+                                       None, leds, A.astype(np.float64), opt, w.n_side,
+                                       w.pitch_mm, w.height_mm, mask, zern, kappa)
+    assert abs(float(H(st.loss)[0]) - ref.loss) <= 1e-5 * ref.loss
+    P = fo.pupil(mask, zern, c0.astype(np.float64), z0, kappa)
+    s, J = fo.led_shifts_and_jacobian(opt, w.n_side, w.pitch_mm, w.height_mm, geom0)
+    sub = fo.loss_and_grads_subpixel(O0.astype(np.complex128), P, s, leds, A.astype(np.float64))
+    _, _, g_theta = fo.pupil_param_grads(sub.g_P, P, zern, kappa)
+    g_par = H(st.g_par)
+    for j in range(15):
+        assert abs(g_par[j] - ref.g_coeffs[j]) <= GRAD_TOL * np.sum(np.abs(g_theta * zern[j])), j
+    assert abs(g_par[15] - ref.g_z) <= GRAD_TOL * np.sum(np.abs(g_theta * kappa))
+    scale = np.zeros(4)
+    for b, led in enumerate(leds):
+        scale += np.abs(J[led].T) @ np.abs(sub.g_shift[b])
+    assert np.all(np.abs(H(geo.g) - ref.g_geom) <= 1e-4 * scale)

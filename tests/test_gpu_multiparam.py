@@ -102,7 +102,7 @@ def test_loss_grad_matches_oracle(dev, case):
     assert int(H(g["oob"])[0]) == 0
     assert abs(float(H(g["loss"])[0]) - ref.loss) <= 1e-5 * ref.loss
     assert rel_l2(H(g["g_O"]), ref.g_O) <= GRAD_TOL
-    # scalar groups are sums that cancel: judge them against the sum of their terms
+    # scalar groups are sums that cancel: measured against the sum of their terms
     P = fo.pupil(case.mask, case.zern, c.astype(np.float64), float(z[0]), case.kappa)
     sub = fo.loss_and_grads_subpixel(O64, P, s, leds, case.A.astype(np.float64),
                                      gamma.astype(np.float64))

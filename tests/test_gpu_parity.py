@@ -2,7 +2,7 @@
 
 Same seeded inputs on both sides (float32 / complex64 on the GPU, upcast for
 the oracle). Tolerances: gradients and fields within a relative L2 of 2e-5
-(the per-step gradient bar of this build; an N x N complex64 FFT pair has a
+(the per-step gradient bar; an N x N complex64 FFT pair has a
 relative error near 1e-6); pupil-parameter gradients within 2e-5 of the sum
 of their summands' magnitudes (the sums cancel); reconstructions after a full
 solve within 1e-3 relative error; integer decisions bit-exact.

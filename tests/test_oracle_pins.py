@@ -231,7 +231,7 @@ def test_zernike_and_defocus_gradients_match_central_differences():
     for j in [0, 1, 4, 7, 12, 14]:
         e = np.zeros(15); e[j] = h
         fd = (L(c + e, z) - L(c - e, z)) / (2 * h)
-        scale = np.sum(np.abs(g_theta * zern[j]))     # the sum cancels; judge on its terms
+        scale = np.sum(np.abs(g_theta * zern[j]))     # the sum cancels; measured on its terms
         assert abs(fd - g_c[j]) <= 1e-6 * scale
     fd = (L(c, z + h) - L(c, z - h)) / (2 * h)
     assert abs(fd - g_z) <= 1e-6 * np.sum(np.abs(g_theta * kappa))

@@ -205,20 +205,22 @@ def multiparam_rate(w, prob, steps: int) -> dict:
 def batch_sweep(w, batches, epochs: int, log) -> dict:
     """Random batches of several sizes (Eqs. 13-14) and the sequential fixed-order
     loop (Eq. 7) on the same synthetic data: quality of the object after each
-    epoch against wall-clock time on the GPU (evaluation not timed)."""
+    epoch against wall-clock time on the GPU (evaluation not timed). A batch
+    size of 0 stands for all LEDs: one full-gradient step per epoch (Eq. 6)."""
     import numpy as np
     import torch
     from paper_2408_13782_amd import fpm, inputs, problem
+    batches = [w.n_led if b <= 0 else min(b, w.n_led) for b in batches]
     prob = problem.make_plan(w, max_batch=max(batches))
     problem.simulate(prob, seed=0)
     plan = prob.plan
     o_true = plan.hr_transform(prob.O_true, -1).cpu().numpy()
     O0 = problem.initial_spectrum(prob)
     hp = problem.hparams(w)
-    runs = [("random", b) for b in batches] + [("sequential", 1)]
+    runs = [("full" if b == w.n_led else "random", b) for b in batches] + [("sequential", 1)]
     out = []
     for mode, B in runs:
-        if mode == "random":
+        if mode != "sequential":
             perms = inputs.led_permutations(w.n_led, epochs, seed=0)
         else:
             perms = np.tile(ring_order(prob), (epochs, 1)).astype(np.int32)
@@ -265,7 +267,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-sweep", type=int, nargs="*", default=None,
                     help="instead of the throughput line: quality vs time for these batch "
-                         "sizes and the sequential loop (e.g. --batch-sweep 1 4 8 16 32 64)")
+                         "sizes and the sequential loop (e.g. --batch-sweep 1 8 16 40 0; "
+                         "0 = all LEDs, the full gradient)")
     ap.add_argument("--sweep-epochs", type=int, default=30)
     ap.add_argument("--serving-requests", type=int, default=150,
                     help="requests of the tile-serving latency measurement at rho = 0.9 "

@@ -76,7 +76,8 @@ typedef struct {
   int32_t n_lr;          /* N */
   int32_t upsample;      /* s, M = s N (M <= 4096) */
   int32_t n_led;         /* rows of the LED table */
-  int32_t max_batch;     /* largest B any call on this plan will pass (<= 64) */
+  int32_t max_batch;     /* largest B any call on this plan will pass (<= 1024;
+                            the multi-parameter calls take at most 64 per batch) */
   double wavelength_um;  /* lambda */
   double na;             /* objective numerical aperture */
   double mag;            /* objective magnification */
@@ -243,6 +244,12 @@ int fpm_step(fpm_plan* plan, fpm_state* state, const fpm_hparams* hp, const int3
  * `leds` (HOST, int32, concatenated); batch_sizes is HOST memory [n_steps],
  * each in [1, max_batch]. Same effect as n_steps fpm_step calls; all ids
  * are validated before anything is enqueued.
+ *
+ * Batches of more than 64 LEDs (up to the full set, the full-gradient
+ * descent of Eq. 6) run in groups of 64: the passes of each group store its
+ * LEDs' patches, the update of every group but the last adds them into a
+ * gradient accumulator of the plan, the last one applies Adam. The additions
+ * keep the batch order, so the step equals a single pass over the batch.
  */
 int fpm_run(fpm_plan* plan, fpm_state* state, const fpm_hparams* hp, const int32_t* leds,
             const int32_t* batch_sizes, int32_t n_steps, const float* gamma,
@@ -279,7 +286,7 @@ typedef struct {
  * the offset gradient is the one-sided derivative where s_b crosses an
  * integer). A window that would leave the HR grid is clamped and counted in
  * grads->oob. All sums are in a fixed order (deterministic). Requires
- * grid->n_side^2 == n_led.
+ * grid->n_side^2 == n_led and B <= 64.
  */
 int fpm_loss_grad(fpm_plan* plan, const fpm_led_grid* grid, const fpm_params* params,
                   const int32_t* leds, int32_t B, const float* meas_amp, fpm_grads* grads,
@@ -306,7 +313,7 @@ typedef struct {
  * and their moments required (learned or not, per hp->learn_zernike,
  * hp->learn_z); state->P must hold P(coeffs, z) on entry and is rebuilt each
  * step. No LED intensities. Deterministic; one call is the same as n_steps
- * calls of one step. Same batch layout as fpm_run.
+ * calls of one step. Same batch layout as fpm_run, at most 64 LEDs per batch.
  */
 int fpm_run_multi(fpm_plan* plan, const fpm_led_grid* grid, fpm_state* state,
                   fpm_geometry* geometry, const fpm_hparams* hp, const int32_t* leds,

@@ -53,6 +53,11 @@ bool hr_supported(int m) {
 
 const char* const kHrSizes = "HR transforms support M in {256, 512, 768, 1024, 1536, 2048}";
 
+// A launch serves at most kMaxSlots LEDs (their windows travel in the kernel
+// arguments); larger batches of the nearest-pixel path run as consecutive
+// groups of kMaxSlots, up to kMaxBatch LEDs per batch.
+constexpr int kMaxBatch = 1024;
+
 template <int V> using Size = std::integral_constant<int, V>;
 
 // f(Size<N>{}) for the supported LR image sizes N (the kernels are templates on N).
@@ -118,7 +123,8 @@ struct fpm_plan {
   int2* rowext = nullptr;     // [N] (first, last) disk column of each pupil row
   float2* twN = nullptr;      // [N]
   float2* twM = nullptr;      // [M] when the HR transforms are available
-  float2* X = nullptr;        // [max_batch][N][N] row/column scratch
+  float2* X = nullptr;        // [min(max_batch, kMaxSlots)][N][N] row/column scratch
+  float2* gacc = nullptr;     // [M][M] gradient sums of a batch's earlier groups (max_batch > kMaxSlots)
   float2* gP = nullptr;       // [N][N] pupil-gradient accumulator for fpm_step
   float* kappa_tab = nullptr;  // defocus phase per um at integer |u|^2 <= R^2
   int2* tiles = nullptr;      // [n_tiles] 32 x 32 HR tiles covered by some window
@@ -194,6 +200,7 @@ void plan_free(fpm_plan* p) {
   (void)hipFree(p->twN);
   (void)hipFree(p->twM);
   (void)hipFree(p->X);
+  (void)hipFree(p->gacc);
   (void)hipFree(p->gP);
   (void)hipFree(p->kappa_tab);
   (void)hipFree(p->tiles);
@@ -336,6 +343,8 @@ struct BackwardOut {
   bool loss = false;          // column pass stores loss partials in part_loss
   int commit = 0;             // rows_forward commits the staged pupil-parameter state
   ScalarState scal{};
+  double* loss_part = nullptr;  // where the column pass stores its loss partials (with loss)
+  double* zpart = nullptr;      // where the row pass stores its moment partials (kPatchZern)
 };
 
 template <int N>
@@ -355,7 +364,7 @@ int launch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t
     Timed tm(p, kCols, st);
     for (int r = 0; r < tm.reps; ++r)
       cols<N, false><<<gr.cols(), ColLines<N>::value * ColPlan<N>::T, 0, st>>>(
-          p->X, A, gamma, bt, dk, gr.col_groups, o.loss ? p->part_loss : nullptr, nullptr,
+          p->X, A, gamma, bt, dk, gr.col_groups, o.loss ? o.loss_part : nullptr, nullptr,
           nullptr, p->twN, 1.0f / p->M);
   }
   {
@@ -376,7 +385,7 @@ int launch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t
         break;
       default:
         rows_backward<N, kPatchZern><<<gr.rows(), kRowThreads, 0, st>>>(
-            p->X, O, P, bt, dk, pg, gr.row_chunks, nullptr, nullptr, p->part_z, p->kappa_tab,
+            p->X, O, P, bt, dk, pg, gr.row_chunks, nullptr, nullptr, o.zpart, p->kappa_tab,
             p->twN);
         break;
     }
@@ -429,6 +438,25 @@ int rows_grid_of(const fpm_plan* p, int B) {
 
 int cols_grid_of(const fpm_plan* p, int B) {
   return with_lr_size(p->N, [&](auto n) { return grids_of<decltype(n)::value>(p, B).cols(); });
+}
+
+// Group g of a batch of B LEDs: kMaxSlots LEDs from position b0 (the last
+// group takes the rest). The groups' partial sums are stored one after the
+// other, so the partials of the whole batch form one list of
+// rows_grid_of(p, B) (cols_grid_of(p, B)) entries, as for a single launch.
+struct Group {
+  int b0, B, rows_off, cols_off;
+};
+
+int n_groups(int B) { return (B + kMaxSlots - 1) / kMaxSlots; }
+
+Group group_of(const fpm_plan* p, int B, int g) {
+  Group r;
+  r.b0 = g * kMaxSlots;
+  r.B = std::min(kMaxSlots, B - r.b0);
+  r.rows_off = g * rows_grid_of(p, kMaxSlots);
+  r.cols_off = g * cols_grid_of(p, kMaxSlots);
+  return r;
 }
 
 int pupil_wgs(const fpm_plan* p) {
@@ -670,7 +698,7 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
   if (!lr_supported(d->n_lr)) return fail(FPM_EUNSUPPORTED, "n_lr must be 64, 128, 192, 256, 384 or 512");
   FPM_REQUIRE(d->upsample >= 1 && (int64_t)d->upsample * d->n_lr <= 4096, "upsample out of range");
   FPM_REQUIRE(d->n_led >= 1 && d->max_batch >= 1, "n_led and max_batch must be >= 1");
-  FPM_REQUIRE(d->max_batch <= kMaxSlots, "max_batch must be <= 64");
+  FPM_REQUIRE(d->max_batch <= kMaxBatch, "max_batch must be <= 1024");
   FPM_REQUIRE(d->wavelength_um > 0 && d->na > 0 && d->mag > 0 && d->pixel_um > 0,
               "optics must be positive");
   fpm_plan* p = new fpm_plan();
@@ -733,7 +761,10 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
   const auto twn = twiddles(p->N);
   if ((rc = upload(&p->device_bytes, &p->rowext, ext.data(), ext.size())) ||
       (rc = upload(&p->device_bytes, &p->twN, twn.data(), twn.size())) ||
-      (rc = upload<float2>(&p->device_bytes, &p->X, nullptr, (size_t)p->max_batch * p->N * p->N)) ||
+      (rc = upload<float2>(&p->device_bytes, &p->X, nullptr,
+                           (size_t)std::min(p->max_batch, kMaxSlots) * p->N * p->N)) ||
+      (p->max_batch > kMaxSlots &&
+       (rc = upload<float2>(&p->device_bytes, &p->gacc, nullptr, (size_t)p->M * p->M))) ||
       (rc = upload<float2>(&p->device_bytes, &p->gP, nullptr, (size_t)p->N * p->N)) ||
       (rc = upload(&p->device_bytes, &p->kappa_tab, kap.data(), kap.size())) ||
       (rc = upload<int2>(&p->device_bytes, &p->tiles, nullptr, tile_capacity(p))) ||
@@ -879,9 +910,17 @@ int fpm_forward(fpm_plan* p, const fpm_c32* O, const fpm_c32* P, const int32_t* 
   const auto* pp = reinterpret_cast<const float2*>(P);
   auto* f = reinterpret_cast<float2*>(field_out);
   hipStream_t st = (hipStream_t)stream;
-  return with_lr_size(p->N, [&](auto n) {
-    return launch_forward<decltype(n)::value>(p, o, pp, leds, B, gamma, amp_out, f, st);
-  });
+  const size_t nn = (size_t)p->N * p->N;
+  for (int g = 0; g < n_groups(B); ++g) {
+    const Group gr = group_of(p, B, g);
+    if (int rc = with_lr_size(p->N, [&](auto n) {
+          return launch_forward<decltype(n)::value>(p, o, pp, leds + gr.b0, gr.B, gamma,
+                                                    amp_out + gr.b0 * nn,
+                                                    f ? f + gr.b0 * nn : nullptr, st);
+        }))
+      return rc;
+  }
+  return FPM_OK;
 }
 
 int fpm_backward(fpm_plan* p, const fpm_c32* O, const fpm_c32* P, const int32_t* leds, int32_t B,
@@ -896,10 +935,14 @@ int fpm_backward(fpm_plan* p, const fpm_c32* O, const fpm_c32* P, const int32_t*
   o.gP = reinterpret_cast<float2*>(gP);
   o.loss = loss != nullptr;
   hipStream_t st = (hipStream_t)stream;
-  if (int rc = dispatch_backward(p, reinterpret_cast<const float2*>(O),
-                                 reinterpret_cast<const float2*>(P), leds, B, gamma, meas_amp,
-                                 reinterpret_cast<float2*>(gO), o, st))
-    return rc;
+  for (int g = 0; g < n_groups(B); ++g) {
+    const Group gr = group_of(p, B, g);
+    o.loss_part = p->part_loss + gr.cols_off;
+    if (int rc = dispatch_backward(p, reinterpret_cast<const float2*>(O),
+                                   reinterpret_cast<const float2*>(P), leds + gr.b0, gr.B, gamma,
+                                   meas_amp, reinterpret_cast<float2*>(gO), o, st))
+      return rc;
+  }
   if (loss) {   // add the column pass's partials (fixed order)
     UpdateArgs a{};
     a.n = p->N;
@@ -950,6 +993,9 @@ ScalarState scalar_state_of(const fpm_state* s) {
 // One update: loss and gradients of the batch (projected onto the pupil
 // parameters when they are learned), then the update kernel (Adam on the
 // spectrum; Adam on the pupil parameters and the pupil rebuilt from them).
+// A batch of more than kMaxSlots LEDs runs its passes group by group; every
+// group but the last ends with an accumulating launch of the update kernel
+// (gradient sums into gacc), the last one with the full update.
 // `commit`: the previous step of this call staged a pupil-parameter state.
 int step_launches(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_t* leds, int B,
                   const float* gamma, const float* meas_amp, int commit, hipStream_t st) {
@@ -959,56 +1005,68 @@ int step_launches(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_
   const double b1 = hp->beta1, b2 = hp->beta2;
   const double bc1 = 1.0 - std::pow(b1, t), bc2 = 1.0 - std::pow(b2, t);
   float2* P = reinterpret_cast<float2*>(s->P);
-  BackwardOut o;
-  o.mode = learn_p ? kPatchZern : kPatch;
-  o.loss = s->loss != nullptr;
-  o.commit = commit;
-  o.scal = scalar_state_of(s);
-  if (int rc = dispatch_backward(p, reinterpret_cast<const float2*>(s->O), P, leds, B, gamma,
-                                 meas_amp, nullptr, o, st))
-    return rc;
-  UpdateArgs a{};
-  a.X = p->X;
-  a.bt = batch_of(p, leds, B);
-  a.dk = disk_of(p);
-  a.n = p->N;
-  a.tiles = p->tiles;
-  a.n_tiles = p->n_tiles;
-  a.M = p->M;
-  a.O = reinterpret_cast<float*>(s->O);
-  a.mO = reinterpret_cast<float*>(s->m_O);
-  a.vO = reinterpret_cast<float*>(s->v_O);
-  a.c.b1 = hp->beta1;
-  a.c.b2 = hp->beta2;
-  a.c.eps = hp->eps;
-  a.c.step_size = (float)(hp->lr_object / bc1);
-  a.c.sqrt_bc2 = (float)std::sqrt(bc2);
-  a.loss_part = p->part_loss;
-  a.n_loss = cols_grid_of(p, B);
-  a.loss = s->loss;
-  a.pupil = learn_p;
-  a.zpart = p->part_z;
-  a.n_zpart = rows_grid_of(p, B);
-  a.cur = o.scal;
-  a.sa.learn_c = learn_c;
-  a.sa.learn_z = learn_z;
-  a.sa.lr_c = hp->lr_zernike;
-  a.sa.lr_z = hp->lr_z;
-  a.sa.b1 = b1;
-  a.sa.b2 = b2;
-  a.sa.eps = hp->eps;
-  a.sa.bc1 = bc1;
-  a.sa.sqrt_bc2 = std::sqrt(bc2);
-  a.g_par = s->g_par;
-  a.staging = p->staging;
-  a.pg = pupil_geom(p);
-  a.rowext = p->rowext;
-  a.P = P;
-  const int extra = learn_p ? pupil_wgs(p) : 1;   // must match the kernel's n_pw
-  {
-    Timed tm(p, kAdamObject, st);
-    for (int r = 0; r < tm.reps; ++r)
-      if (int rc = launch_update(p, a, p->n_tiles + extra, st)) return rc;
+  const int G = n_groups(B);
+  for (int g = 0; g < G; ++g) {
+    const Group gr = group_of(p, B, g);
+    const bool last = g == G - 1;
+    BackwardOut o;
+    o.mode = learn_p ? kPatchZern : kPatch;
+    o.loss = s->loss != nullptr;
+    o.commit = commit && g == 0;
+    o.scal = scalar_state_of(s);
+    o.loss_part = p->part_loss + gr.cols_off;
+    o.zpart = p->part_z + (size_t)gr.rows_off * kPar;
+    if (int rc = dispatch_backward(p, reinterpret_cast<const float2*>(s->O), P, leds + gr.b0,
+                                   gr.B, gamma, meas_amp, nullptr, o, st))
+      return rc;
+    UpdateArgs a{};
+    a.X = p->X;
+    a.bt = batch_of(p, leds + gr.b0, gr.B);
+    a.dk = disk_of(p);
+    a.n = p->N;
+    a.tiles = p->tiles;
+    a.n_tiles = p->n_tiles;
+    a.M = p->M;
+    a.gacc = reinterpret_cast<float*>(p->gacc);
+    a.acc_in = g > 0;
+    a.acc_out = !last;
+    if (last) {
+      a.O = reinterpret_cast<float*>(s->O);
+      a.mO = reinterpret_cast<float*>(s->m_O);
+      a.vO = reinterpret_cast<float*>(s->v_O);
+      a.c.b1 = hp->beta1;
+      a.c.b2 = hp->beta2;
+      a.c.eps = hp->eps;
+      a.c.step_size = (float)(hp->lr_object / bc1);
+      a.c.sqrt_bc2 = (float)std::sqrt(bc2);
+      a.loss_part = p->part_loss;
+      a.n_loss = cols_grid_of(p, B);
+      a.loss = s->loss;
+      a.pupil = learn_p;
+      a.zpart = p->part_z;
+      a.n_zpart = rows_grid_of(p, B);
+      a.cur = o.scal;
+      a.sa.learn_c = learn_c;
+      a.sa.learn_z = learn_z;
+      a.sa.lr_c = hp->lr_zernike;
+      a.sa.lr_z = hp->lr_z;
+      a.sa.b1 = b1;
+      a.sa.b2 = b2;
+      a.sa.eps = hp->eps;
+      a.sa.bc1 = bc1;
+      a.sa.sqrt_bc2 = std::sqrt(bc2);
+      a.g_par = s->g_par;
+      a.staging = p->staging;
+      a.pg = pupil_geom(p);
+      a.rowext = p->rowext;
+      a.P = P;
+    }
+    const int extra = a.pupil ? pupil_wgs(p) : 1;   // must match the kernel's n_pw
+    {
+      Timed tm(p, kAdamObject, st);
+      for (int r = 0; r < tm.reps; ++r)
+        if (int rc = launch_update(p, a, p->n_tiles + extra, st)) return rc;
+    }
   }
   FPM_HIP(hipGetLastError());
   s->t = t;
@@ -1071,6 +1129,7 @@ int fpm_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr,
   FPM_REQUIRE(grid->n_side >= 1 && grid->n_side * grid->n_side == p->n_led,
               "grid->n_side^2 must equal the plan's n_led");
   if (int rc = check_batch(p, leds, B)) return rc;
+  FPM_REQUIRE(B <= kMaxSlots, "the multi-parameter path takes at most 64 LEDs per batch");
   if (int rc = check_device(p)) return rc;
   if (B == 0) return FPM_OK;
   hipStream_t st = (hipStream_t)stream;
@@ -1098,6 +1157,8 @@ int fpm_run_multi(fpm_plan* p, const fpm_led_grid* grid, fpm_state* s, fpm_geome
   for (int i = 0; i < n_steps; ++i) {
     FPM_REQUIRE(batch_sizes[i] >= 1 && batch_sizes[i] <= p->max_batch,
                 "every batch size must be in [1, max_batch]");
+    FPM_REQUIRE(batch_sizes[i] <= kMaxSlots,
+                "the multi-parameter path takes at most 64 LEDs per batch");
     if (int rc = check_batch(p, leds + off, batch_sizes[i])) return rc;
     off += (size_t)batch_sizes[i];
   }

@@ -98,9 +98,15 @@ struct ScalarAdam {
 //    rebuilds its share of the pupil from the new parameters; workgroup 0 of
 //    them stages the new parameter state, adds the gradients to g_par, and
 //    adds the batch loss (summed from the column pass's partials) to *loss.
+//  Batches of more than kMaxSlots LEDs are processed in groups: for every
+//  group but the last the kernel only accumulates (acc_out: g_acc = the
+//  group's gathered sum, started from g_acc when acc_in, no Adam); the last
+//  group's launch starts its sums from g_acc (acc_in) and applies Adam. The
+//  additions then happen in batch order, as in a single pass.
 struct UpdateArgs {
   const int2* tiles; int n_tiles; int M;
   float* O; float* mO; float* vO;
+  float* gacc; int acc_in, acc_out;
   AdamCoef c;
   // the batch's conj(P) g_Phi patches, stored in X by the row pass
   const float2* X; Batch bt; Disk dk; int n;
@@ -118,11 +124,10 @@ constexpr int pupil_per_wg(int n) { return n <= 256 ? 512 : 1024; }
 
 // Gradient of the spectrum at 4 consecutive pixels (row r, columns c0..c0+3):
 // the sum, in batch order, of the patches of the LEDs whose disk covers them.
+// g holds the running sums on entry (zero, or the earlier groups' sums).
 template <int N>
 __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int c0, int tile_r0,
                                                 int tile_c0, float2 (&g)[4]) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) g[q] = make_float2(0.f, 0.f);
   // slots whose disk bounding box meets this 32 x 32 tile (uniform over the workgroup)
   unsigned long long hit = 0ull;
   for (int b = 0; b < a.bt.B; ++b) {
@@ -185,16 +190,31 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     float4* po = reinterpret_cast<float4*>(a.O + f);
     float4* pm = reinterpret_cast<float4*>(a.mO + f);
     float4* pv = reinterpret_cast<float4*>(a.vO + f);
-    float4 o[2], m[2], v[2];
+    float4 o[2], m[2], v[2], gi[2];
+    float4* pg = a.gacc ? reinterpret_cast<float4*>(a.gacc + f) : nullptr;
 #pragma unroll
     for (int h = 0; h < 2; ++h) {   // in flight while the gradient is gathered
-      o[h] = po[h];
-      m[h] = pm[h];
-      v[h] = pv[h];
+      if (!a.acc_out) {
+        o[h] = po[h];
+        m[h] = pm[h];
+        v[h] = pv[h];
+      }
+      gi[h] = a.acc_in ? pg[h] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     float2 g[4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      g[2 * h] = make_float2(gi[h].x, gi[h].y);
+      g[2 * h + 1] = make_float2(gi[h].z, gi[h].w);
+    }
     gather_gradient<N>(a, r, col, tl.x * 32, tl.y * 32, g);
     FPM_PROBE(3, 1);
+    if (a.acc_out) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+        store_next4<N>(pg + h, make_float4(g[2 * h].x, g[2 * h].y, g[2 * h + 1].x, g[2 * h + 1].y));
+      return;
+    }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       adam1(o[h].x, m[h].x, v[h].x, g[2 * h].x, a.c);

@@ -394,6 +394,62 @@ def test_step_with_zernike_learning_matches_oracle(dev):
     np.testing.assert_allclose(H(st.coeffs), ost.coeffs, atol=2e-5 * w.lr_zernike * 2 + 1e-7)
 
 
+def test_batches_above_64_run_in_groups_and_match_oracle(dev):
+    """Batches of more than 64 LEDs (the full gradient of Eq. 6 over an 11x11 grid,
+    121 LEDs, and ragged batches of 100 + 21) run as groups of 64 whose gradient sums
+    are carried between launches: forward, loss and gradients, and a schedule of
+    object + Zernike steps against the oracle; the steps are deterministic."""
+    w = inputs.workload("small", n_side=11, learn_zernike=True)
+    say("batches above 64 LEDs: 121 (full gradient) and 100 + 21")
+    pr = oracle_problem(w, seed=4)
+    plan = make_plan(w, pr.shifts, w.n_led)
+    assert plan.info.max_batch == 121
+    A = T(pr.A, dev)
+    P = plan.pupil()
+    P64 = H(P).astype(np.complex128)
+    all_leds = inputs.led_permutations(w.n_led, 1, seed=5)[0]
+    amp = plan.forward(T(pr.O0, dev), P, all_leds)
+    torch.cuda.synchronize()
+    ref_amp = fo.forward_amplitudes(pr.O0.astype(np.complex128), P64, pr.shifts, all_leds)
+    assert rel_l2(H(amp), ref_amp) <= GRAD_TOL
+    leds100 = all_leds[:100]
+    _, gO, gP, loss, ref = _backward_case(dev, w, pr.O0, H(P), leds100, pr.A, None)
+    m = pr.mask.astype(bool)
+    assert rel_l2(gO, ref.g_O) <= GRAD_TOL
+    assert rel_l2(gP[m], ref.g_P[m]) <= GRAD_TOL
+    assert abs(loss - ref.loss) <= 1e-5 * ref.loss
+    # two epochs of full-gradient steps, then two epochs cut into batches of 100 + 21
+    perms = inputs.led_permutations(w.n_led, 4, seed=6)
+    batches = problem.schedule(perms[:2], w.n_led) + problem.schedule(perms[2:], 100)
+    assert [len(b) for b in batches] == [121, 121, 100, 21, 100, 21]
+    sched = problem.flatten_schedule(batches)
+    hp = problem.hparams(w)
+    outs = []
+    for _ in range(2):
+        st = _gpu_state(plan, pr.O0, dev)
+        plan.run(st, hp, sched.flat, sched.sizes, A)
+        torch.cuda.synchronize()
+        outs.append((H(st.O).copy(), H(st.coeffs).copy(), H(st.loss).copy(), H(st.P).copy()))
+    for a, b in zip(outs[0], outs[1]):
+        np.testing.assert_array_equal(a, b)
+    ost = fo.init_state(pr.O0)
+    cfg = fo.SolveConfig(lr_object=w.lr_object, lr_zernike=w.lr_zernike, learn_pupil=True)
+    A64 = pr.A.astype(np.float64)
+    oloss = sum(fo.step(ost, cfg, pr.mask, pr.zern, pr.kappa, pr.shifts, b, A64) for b in batches)
+    O_gpu, c_gpu, loss_gpu, _ = outs[0]
+    assert abs(float(loss_gpu[0]) - oloss) <= 1e-5 * oloss
+    dO_gpu, dO_ora = O_gpu.astype(np.complex128) - pr.O0, ost.O - pr.O0
+    assert rel_l2(dO_gpu, dO_ora) <= 5e-3
+    assert rel_l2(O_gpu, ost.O) <= 1e-4
+    np.testing.assert_allclose(c_gpu, ost.coeffs, atol=2e-3 * w.lr_zernike)
+    # the full-gradient loss and object gradient at the GPU's state
+    st = _gpu_state(plan, O_gpu, dev)
+    assert _gradient_at_gpu_state(dev, plan, pr, st, all_leds, P) <= GRAD_TOL
+    # the multi-parameter path keeps 64 LEDs per batch
+    with pytest.raises(fpm.FpmError):
+        plan.loss_grad(fpm.LedGrid(w.n_side, w.pitch_mm, w.height_mm), st.O, all_leds, A)
+
+
 def _gradient_at_gpu_state(dev, plan, pr, st, leds, P):
     gO = torch.zeros_like(st.O)
     plan.backward(st.O, P, np.asarray(leds, np.int32), T(pr.A, dev), gO)
@@ -501,7 +557,7 @@ def test_edge_cases(dev):
     with pytest.raises(fpm.FpmError):
         plan.backward(O, P, np.zeros(9, np.int32), A, gO)
     with pytest.raises(fpm.FpmError):
-        fpm.Plan(w.n_lr, w.upsample, pr.shifts, 65, w.wavelength_um, w.na, w.mag, w.pixel_um)
+        fpm.Plan(w.n_lr, w.upsample, pr.shifts, 1025, w.wavelength_um, w.na, w.mag, w.pixel_um)
     # a window leaving the HR grid is refused at plan creation
     bad = pr.shifts.copy()
     bad[0] = (w.m_hr, 0)

@@ -137,7 +137,7 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
     if (meets) hit |= 1ull << b;
   }
 #ifndef FPM_GATHER_ROUND
-#define FPM_GATHER_ROUND 4
+#define FPM_GATHER_ROUND 2
 #endif
   constexpr int kRound = FPM_GATHER_ROUND;
   while (hit) {
@@ -238,7 +238,10 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     // (independent loads in flight, then a fixed summation order)
     const int j = threadIdx.x & (kPar - 1);
     double sj = 0.0;
-    constexpr int kStride = 256 / kPar, kUnroll = 24;
+#ifndef FPM_ZPART_UNROLL
+#define FPM_ZPART_UNROLL 24
+#endif
+    constexpr int kStride = 256 / kPar, kUnroll = FPM_ZPART_UNROLL;
     for (int i0 = threadIdx.x / kPar; i0 < a.n_zpart; i0 += kStride * kUnroll) {
       double vals[kUnroll];
 #pragma unroll

@@ -27,6 +27,7 @@
 // XCD's L2 by the next.
 #pragma once
 #include <hip/hip_runtime.h>
+#include <cfloat>
 #include <stdint.h>
 
 #include "fft_line.hpp"
@@ -491,33 +492,41 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
         if (field_out) field_out[o] = psi;
       }
     } else {
+      // v = M psi here. Both 1/M scalings (of psi and of the residual's forward
+      // transform, which is linear) are folded into one factor k on v.
+      const float inv_m2 = inv_m * inv_m, m_side = 1.f / inv_m;
 #pragma unroll
       for (int m = 0; m < E; ++m) {
-        const float2 psi = cscale(v[m], inv_m);
-        const float q = psi.x * psi.x + psi.y * psi.y;
-        float f;
+        const float qv = v[m].x * v[m].x + v[m].y * v[m].y;   // M^2 |psi|^2
+        float k;
         if (bt.intensity) {
           // e = gamma |psi|^2 - A^2, g_psi = 4 gamma e psi; dL/dgamma = 2 sum e |psi|^2
+          const float q = qv * inv_m2;
           const float e = sg * sg * q - a_meas[m] * a_meas[m];
           acc += e * e;
           if constexpr (kGamma) acc_ea += e * q;
-          f = 4.f * sg * sg * e;
+          k = 4.f * sg * sg * e * inv_m2;
         } else {
-          // e = sqrt(gamma) |psi| - A, g_psi = 2 sqrt(gamma) e psi/|psi|
-          const float a = sqrtf(q);
+          // e = sqrt(gamma) |psi| - A and g_psi = 2 sqrt(gamma) e psi/|psi|
+          //   = 2 sqrt(gamma) (sqrt(gamma) - A/|psi|) psi, with 1/|psi| from one
+          // reciprocal square root (1 ulp) instead of a square root and a division;
+          // where |psi|^2 is below the normal range, 1/|psi| is taken as 0 (then
+          // e = -A and g_psi vanishes with psi)
+          const float rv = qv >= FLT_MIN ? __builtin_amdgcn_rsqf(qv) : 0.f;   // 1/(M |psi|)
+          const float a = qv * rv * inv_m;
           const float e = sg * a - a_meas[m];
           acc += e * e;
           if constexpr (kGamma) acc_ea += e * a;
-          f = a > 0.f ? 2.f * sg * e / a : 0.f;
+          k = 2.f * sg * (sg - a_meas[m] * rv * m_side) * inv_m2;
         }
-        v[m] = cscale(psi, f);
+        v[m] = cscale(v[m], k);
       }
       ColPlan<N>::template run<-1>(v, t, lds, lay, lds_tw);
       FPM_PROBE(1, 2);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int ky = half_shift<N>(t + m * T);
-        if (ky >= dk.ky_lo && ky <= dk.ky_hi) store_next<N>(xb + (size_t)ky * N + x, cscale(v[m], inv_m));
+        if (ky >= dk.ky_lo && ky <= dk.ky_hi) store_next<N>(xb + (size_t)ky * N + x, v[m]);
       }
     }
   }

@@ -122,8 +122,9 @@ struct UpdateArgs {
 // down where the row pass has many workgroups (N >= 384).
 constexpr int pupil_per_wg(int n) { return n <= 256 ? 512 : 1024; }
 
-// Gradient of the spectrum at 4 consecutive pixels (row r, columns c0..c0+3):
-// the sum, in batch order, of the patches of the LEDs whose disk covers them.
+// Gradient of the spectrum at the 4 pixels of a tile thread (row r, columns
+// c0 + tile_col(q)): the sum, in batch order, of the patches of the LEDs whose
+// disk covers them.
 // g holds the running sums on entry (zero, or the earlier groups' sums).
 template <int N>
 __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int c0, int tile_r0,
@@ -161,7 +162,7 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
       const float2* xr = a.X + ((size_t)b * N + kyc) * N;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int kx = c0 + q - wc;
+        const int kx = c0 + tile_col(q) - wc;
         ok[u][q] = bs[u] >= 0 && ky == kyc && kx >= e.x && kx <= e.y;
         val[u][q] = xr[min(max(kx, e.x), e.y)];
       }
@@ -185,7 +186,7 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
   if ((int)blockIdx.x >= n_pw) {
     const int2 tl = a.tiles[blockIdx.x - n_pw];
     const int r = tl.x * 32 + (threadIdx.x >> 3);
-    const int col = tl.y * 32 + (threadIdx.x & 7) * 4;         // complex column
+    const int col = tl.y * 32 + (threadIdx.x & 7) * 2;         // complex column
     const size_t f = ((size_t)r * a.M + col) * 2;                // float offset
     float4* po = reinterpret_cast<float4*>(a.O + f);
     float4* pm = reinterpret_cast<float4*>(a.mO + f);
@@ -195,11 +196,11 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {   // in flight while the gradient is gathered
       if (!a.acc_out) {
-        o[h] = po[h];
-        m[h] = pm[h];
-        v[h] = pv[h];
+        o[h] = po[8 * h];
+        m[h] = pm[8 * h];
+        v[h] = pv[8 * h];
       }
-      gi[h] = a.acc_in ? pg[h] : make_float4(0.f, 0.f, 0.f, 0.f);
+      gi[h] = a.acc_in ? pg[8 * h] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
     float2 g[4];
 #pragma unroll
@@ -212,7 +213,7 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     if (a.acc_out) {
 #pragma unroll
       for (int h = 0; h < 2; ++h)
-        store_next4<N>(pg + h, make_float4(g[2 * h].x, g[2 * h].y, g[2 * h + 1].x, g[2 * h + 1].y));
+        store_next4<N>(pg + 8 * h, make_float4(g[2 * h].x, g[2 * h].y, g[2 * h + 1].x, g[2 * h + 1].y));
       return;
     }
 #pragma unroll
@@ -221,9 +222,9 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
       adam1(o[h].y, m[h].y, v[h].y, g[2 * h].y, a.c);
       adam1(o[h].z, m[h].z, v[h].z, g[2 * h + 1].x, a.c);
       adam1(o[h].w, m[h].w, v[h].w, g[2 * h + 1].y, a.c);
-      store_next4<N>(po + h, o[h]);
-      store_next4<N>(pm + h, m[h]);
-      store_next4<N>(pv + h, v[h]);
+      store_next4<N>(po + 8 * h, o[h]);
+      store_next4<N>(pm + 8 * h, m[h]);
+      store_next4<N>(pv + 8 * h, v[h]);
     }
     FPM_PROBE(3, 2);
     FPM_PROBE(3, 3);

@@ -130,6 +130,12 @@ __device__ __forceinline__ void store_next(float2* p, float2 v) {
   }
 }
 
+// Tile kernels (32 x 32 HR tiles, 256 threads): thread t covers row t / 8 of
+// the tile and the complex columns 2 (t % 8) + tile_col(q), q = 0..3, i.e. the
+// float4 t % 8 and t % 8 + 8 of the row, so that each 16-byte access of 8
+// neighbouring lanes fills one whole 128-byte line.
+__device__ __forceinline__ constexpr int tile_col(int q) { return (q & 1) + (q >> 1) * 16; }
+
 template <int N>
 __device__ __forceinline__ void store_next4(float4* p, float4 v) {
   if constexpr (NtStores<N>::value) {

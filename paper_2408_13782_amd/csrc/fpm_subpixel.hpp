@@ -266,8 +266,9 @@ __device__ __forceinline__ unsigned long long tile_slots(const SubSlot* __restri
   return mask;
 }
 
-// Bilinear adjoint at 4 consecutive pixels (row r, columns c0..c0+3): the sum,
-// over the slots of `hit` in batch order and their 4 taps, of w_t patch_b(p - f_b - t).
+// Bilinear adjoint at the 4 pixels of a tile thread (row r, columns
+// c0 + tile_col(q)): the sum, over the slots of `hit` in batch order and their
+// 4 taps, of w_t patch_b(p - f_b - t).
 template <int N>
 __device__ __forceinline__ void gather_bilinear(const float2* __restrict__ X, const Disk& dk,
                                                 const Corner* cs, unsigned long long hit,
@@ -289,7 +290,7 @@ __device__ __forceinline__ void gather_bilinear(const float2* __restrict__ X, co
       const float2* xr = X + ((size_t)b * N + kyc) * N;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int kx = c0 + q - sl.fc - dxx;
+        const int kx = c0 + tile_col(q) - sl.fc - dxx;
         const float2 val = xr[min(max(kx, e.x), e.y)];
         if (ky == kyc && kx >= e.x && kx <= e.y) {
           g[q].x += wts[tap] * val.x;
@@ -300,8 +301,8 @@ __device__ __forceinline__ void gather_bilinear(const float2* __restrict__ X, co
   }
 }
 
-// g_O += the batch's bilinear adjoint; one thread per 4 consecutive pixels of a
-// 32 x 32 tile, so every pixel is written by one thread (no atomics).
+// g_O += the batch's bilinear adjoint; one thread per 4 pixels of a 32 x 32
+// tile, so every pixel is written by one thread (no atomics).
 template <int N>
 __global__ void __launch_bounds__(256)
 gather_dense(const float2* __restrict__ X, Batch bt, Disk dk,
@@ -312,12 +313,15 @@ gather_dense(const float2* __restrict__ X, Batch bt, Disk dk,
   const unsigned long long hit = tile_slots(stored, bt, dk, tr0, tc0, cs);
   if (!hit) return;
   const int r = tr0 + (threadIdx.x >> 3);
-  const int c0 = tc0 + (threadIdx.x & 7) * 4;
+  const int c0 = tc0 + (threadIdx.x & 7) * 2;
   float2 g[4];
   gather_bilinear<N>(X, dk, cs, hit, r, c0, g);
   float2* out = gO + (size_t)r * bt.M + c0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) out[q] = make_float2(out[q].x + g[q].x, out[q].y + g[q].y);
+  for (int q = 0; q < 4; ++q) {
+    float2& o = out[tile_col(q)];
+    o = make_float2(o.x + g[q].x, o.y + g[q].y);
+  }
 }
 
 // Final sums of a loss-and-gradient call, in fixed order (one workgroup).
@@ -513,7 +517,7 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
     if (!hit && !a.tile_flags[ti]) return;
     if (hit && threadIdx.x == 0) a.tile_flags[ti] = 1;
     const int r = tr0 + (threadIdx.x >> 3);
-    const int c0 = tc0 + (threadIdx.x & 7) * 4;
+    const int c0 = tc0 + (threadIdx.x & 7) * 2;
     const size_t f = ((size_t)r * a.M + c0) * 2;
     float4* po = reinterpret_cast<float4*>(a.O + f);
     float4* pm = reinterpret_cast<float4*>(a.mO + f);
@@ -521,9 +525,9 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
     float4 o[2], m[2], v[2];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {   // in flight while the gradient is gathered
-      o[h] = po[h];
-      m[h] = pm[h];
-      v[h] = pv[h];
+      o[h] = po[8 * h];
+      m[h] = pm[8 * h];
+      v[h] = pv[8 * h];
     }
     float2 g[4];
     gather_bilinear<N>(a.X, a.dk, cs, hit, r, c0, g);
@@ -533,9 +537,9 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
       adam1(o[h].y, m[h].y, v[h].y, g[2 * h].y, a.c);
       adam1(o[h].z, m[h].z, v[h].z, g[2 * h + 1].x, a.c);
       adam1(o[h].w, m[h].w, v[h].w, g[2 * h + 1].y, a.c);
-      store_next4<N>(po + h, o[h]);
-      store_next4<N>(pm + h, m[h]);
-      store_next4<N>(pv + h, v[h]);
+      store_next4<N>(po + 8 * h, o[h]);
+      store_next4<N>(pm + 8 * h, m[h]);
+      store_next4<N>(pv + 8 * h, v[h]);
     }
     return;
   }

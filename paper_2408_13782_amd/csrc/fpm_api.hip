@@ -459,10 +459,9 @@ Group group_of(const fpm_plan* p, int B, int g) {
   return r;
 }
 
-int pupil_wgs(const fpm_plan* p) {
-  const int per = pupil_per_wg(p->N);
-  return (p->N * p->N + per - 1) / per;
-}
+// Workgroup slots of the pupil part of the update kernels (the kernels derive
+// the same count).
+int pupil_wgs(const fpm_plan* p) { return pupil_wg_slots(p->N, p->nrows); }
 
 GeomArgs geom_args(const fpm_plan* p, const fpm_led_grid* grid) {
   GeomArgs ga;

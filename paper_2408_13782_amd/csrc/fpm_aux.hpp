@@ -117,10 +117,59 @@ struct UpdateArgs {
   PupilGeom pg; const int2* rowext; float2* P;
 };
 
-// Pupil points rebuilt per workgroup of the update kernel. Every pupil
-// workgroup sums all row-pass moment partials first, so their number is kept
-// down where the row pass has many workgroups (N >= 384).
-constexpr int pupil_per_wg(int n) { return n <= 256 ? 512 : 1024; }
+// Pupil rows rebuilt per workgroup of the update kernels (about 512 points or
+// fewer each). Every pupil workgroup first sums all of the row pass's moment
+// partials, so only rows that hold disk points get a workgroup.
+__host__ __device__ constexpr int pupil_rows_per_wg(int n) { return n <= 64 ? 8 : n <= 128 ? 4 : 2; }
+__host__ __device__ constexpr int pupil_wg_count(int n, int disk_rows) {
+  return (disk_rows + pupil_rows_per_wg(n) - 1) / pupil_rows_per_wg(n);
+}
+// Workgroup slots given to them: a multiple of the 8 XCDs, so that HR tile t
+// (workgroup pupil_wg_slots + t) runs on XCD t mod 8 whatever the pupil size;
+// the padding workgroups return at once.
+__host__ __device__ constexpr int pupil_wg_slots(int n, int disk_rows) {
+  return (pupil_wg_count(n, disk_rows) + 7) / 8 * 8;
+}
+
+// Pupil workgroup pw rebuilds P on the disk points of disk rows pw R .. pw R + R - 1
+// (R = pupil_rows_per_wg(N)) from the phase coefficients coef[0..14] (Zernike)
+// and, with `defocus`, coef[15] (z); the workgroup's 256 threads are spread
+// over those rows' points. FP64 phase, FP32 store; off the disk P stays zero.
+// kReload: re-read the coefficients for every point instead of keeping them
+// live across the loop (for a host kernel that is short of registers).
+template <int N, bool kReload>
+__device__ __forceinline__ void rebuild_pupil_rows(int pw, const Disk& dk, const PupilGeom& pg,
+                                                   const float* coef, bool defocus, float2* P) {
+  constexpr int R = pupil_rows_per_wg(N);
+  const int r0 = pw * R;
+  int start[R], first[R];
+  int total = 0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int2 e = r0 + r < dk.nrows ? disk_extent<N>(dk, dk.ky_lo + r0 + r) : make_int2(0, -1);
+    start[r] = total;
+    first[r] = e.x;
+    total += max(e.y - e.x + 1, 0);
+  }
+  for (int i = threadIdx.x; i < total; i += 256) {
+    if constexpr (kReload) asm volatile("" ::: "memory");
+    int r = 0, s0 = 0, x0 = first[0];
+#pragma unroll
+    for (int q = 1; q < R; ++q)
+      if (i >= start[q]) { r = q; s0 = start[q]; x0 = first[q]; }
+    const int ky = dk.ky_lo + r0 + r, kx = x0 + (i - s0);
+    const double ux = kx - N / 2, uy = ky - N / 2;
+    double z[kZern];
+    zernike15(ux * pg.inv_r, uy * pg.inv_r, z);
+    double th = 0.0;
+#pragma unroll
+    for (int q = 0; q < kZern; ++q) th += (double)coef[q] * z[q];
+    if (defocus) th += (double)coef[kZern] * defocus_kappa((ux * ux + uy * uy) * pg.dk2, pg.inv_l);
+    double sn, cs;
+    sincos(th, &sn, &cs);
+    P[(size_t)ky * N + kx] = make_float2((float)cs, (float)sn);
+  }
+}
 
 // Gradient of the spectrum at the 4 pixels of a tile thread (row r, columns
 // c0 + tile_col(q)): the sum, in batch order, of the patches of the LEDs whose
@@ -181,8 +230,7 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
 template <int N>
 __global__ void __launch_bounds__(256) update(UpdateArgs a) {
   FPM_PROBE(3, 0);
-  constexpr int kPupilPerWg = pupil_per_wg(N);
-  const int n_pw = a.pupil ? (N * N + kPupilPerWg - 1) / kPupilPerWg : 1;
+  const int n_pw = a.pupil ? pupil_wg_slots(N, a.dk.nrows) : 1;
   if ((int)blockIdx.x >= n_pw) {
     const int2 tl = a.tiles[blockIdx.x - n_pw];
     const int r = tl.x * 32 + (threadIdx.x >> 3);
@@ -231,6 +279,7 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     return;
   }
   const int pw = blockIdx.x;
+  if (a.pupil && pw >= pupil_wg_count(N, a.dk.nrows)) return;   // padding
   __shared__ double red[256];
   __shared__ double gsum[kPar];
   __shared__ float next[kScal];
@@ -273,9 +322,11 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
       red[threadIdx.x] = g;
       // current value, moments; unchanged unless learned
       const bool is_z = threadIdx.x == kZern;
-      const float* pc = is_z ? a.cur.z : a.cur.coeffs + threadIdx.x;
-      const float* pm = is_z ? a.cur.m_z : a.cur.m_c + threadIdx.x;
-      const float* pv = is_z ? a.cur.v_z : a.cur.v_c + threadIdx.x;
+      // (a NULL array stands for zeros: the Zernike state may be absent when
+      // only the defocus is learned, and the reverse)
+      const float* pc = is_z ? a.cur.z : a.cur.coeffs ? a.cur.coeffs + threadIdx.x : nullptr;
+      const float* pm = is_z ? a.cur.m_z : a.cur.m_c ? a.cur.m_c + threadIdx.x : nullptr;
+      const float* pv = is_z ? a.cur.v_z : a.cur.v_c ? a.cur.v_c + threadIdx.x : nullptr;
       float p = pc ? *pc : 0.f, m = pm ? *pm : 0.f, v = pv ? *pv : 0.f;
       // piston (j = 0): a global phase with an identically zero gradient, held fixed
       const bool learn = is_z ? a.sa.learn_z : (a.sa.learn_c && threadIdx.x != 0);
@@ -296,23 +347,8 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     if (pw == 0 && threadIdx.x < kScal) a.staging[threadIdx.x] = next[threadIdx.x];
     if (pw == 0 && threadIdx.x < kPar && a.g_par) a.g_par[threadIdx.x] += red[threadIdx.x];
     FPM_PROBE(3, 1);
-    // rebuild this workgroup's share of the pupil from the new parameters (FP64)
-    const int end = min((pw + 1) * kPupilPerWg, N * N);
-    for (int idx = pw * kPupilPerWg + threadIdx.x; idx < end; idx += 256) {
-      const int ky = idx / N, kx = idx - ky * N;
-      const int2 e = disk_extent<N>(a.dk, ky);
-      if (kx < e.x || kx > e.y) continue;   // off the disk P stays zero
-      const double ux = kx - N / 2, uy = ky - N / 2;
-      double z[kZern];
-      zernike15(ux * a.pg.inv_r, uy * a.pg.inv_r, z);
-      double th = 0.0;
-#pragma unroll
-      for (int q = 0; q < kZern; ++q) th += (double)next[q] * z[q];
-      if (a.cur.z) th += (double)next[kZern] * defocus_kappa((ux * ux + uy * uy) * a.pg.dk2, a.pg.inv_l);
-      double sn, cs;
-      sincos(th, &sn, &cs);
-      a.P[idx] = make_float2((float)cs, (float)sn);
-    }
+    // rebuild this workgroup's rows of the pupil from the new parameters
+    rebuild_pupil_rows<N, false>(pw, a.dk, a.pg, next, a.cur.z != nullptr, a.P);
   }
   FPM_PROBE(3, 2);
   if (pw == 0 && a.loss && threadIdx.x < 64) {

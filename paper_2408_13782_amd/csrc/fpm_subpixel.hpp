@@ -130,6 +130,7 @@ rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Bat
   __shared__ float2 lds_tw[N];
   int b, c;
   if (!xcd_map(blockIdx.x, chunks, bt.B, b, c)) return;
+  FPM_PROBE(0, 0);
   stage_twiddles<N>(lds_tw, tw);
   const int line = threadIdx.x / T, t = threadIdx.x % T;
   const int rr = c * L + line;
@@ -161,6 +162,7 @@ rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Bat
 #pragma unroll
     for (int m = 0; m < E; ++m) xr[t + m * T] = v[m];
   }
+  FPM_PROBE(0, 3);
 }
 
 constexpr int kSubPar = kPar + 2;   // pupil moments, then dL/ds (row, col)
@@ -178,6 +180,7 @@ rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
   __shared__ float2 lds_tw[N];
   int b, c;
   const bool live = xcd_map(blockIdx.x, chunks, bt.B, b, c);
+  FPM_PROBE(2, 0);
   if (live) stage_twiddles<N>(lds_tw, tw);
   const int line = threadIdx.x / T, t = threadIdx.x % T;
   const int rr = c * L + line;
@@ -239,6 +242,7 @@ rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
     }
   }
   block_partials<kSubPar>(acc, part);
+  FPM_PROBE(2, 3);
 }
 
 // Window corner and fractional offsets of every batch slot, compact, in LDS,
@@ -252,15 +256,18 @@ struct Corner {
 __device__ __forceinline__ unsigned long long tile_slots(const SubSlot* __restrict__ stored,
                                                           const Batch& bt, const Disk& dk,
                                                           int tr0, int tc0, Corner* cs) {
+  // the B <= 64 slots are served by the first wave; its ballot is the mask
   __shared__ unsigned long long mask;
-  if (threadIdx.x == 0) mask = 0ull;
-  __syncthreads();
-  if ((int)threadIdx.x < bt.B) {
-    const SubSlot sl = stored[threadIdx.x];
-    cs[threadIdx.x] = Corner{sl.fr, sl.fc, sl.ay, sl.ax};
-    const bool meets = !(tr0 + 31 < sl.fr + dk.ky_lo || tr0 > sl.fr + dk.ky_hi + 1 ||
-                         tc0 + 31 < sl.fc + dk.ky_lo || tc0 > sl.fc + dk.ky_hi + 1);
-    if (meets) atomicOr(&mask, 1ull << threadIdx.x);
+  if (threadIdx.x < 64) {
+    bool meets = false;
+    if ((int)threadIdx.x < bt.B) {
+      const SubSlot sl = stored[threadIdx.x];
+      cs[threadIdx.x] = Corner{sl.fr, sl.fc, sl.ay, sl.ax};
+      meets = !(tr0 + 31 < sl.fr + dk.ky_lo || tr0 > sl.fr + dk.ky_hi + 1 ||
+                tc0 + 31 < sl.fc + dk.ky_lo || tc0 > sl.fc + dk.ky_hi + 1);
+    }
+    const unsigned long long m = __ballot(meets);
+    if (threadIdx.x == 0) mask = m;
   }
   __syncthreads();
   return mask;
@@ -364,8 +371,8 @@ __global__ void __launch_bounds__(256) loss_grad_reduce(ReduceArgs a) {
   if (tid < a.bt.B) {
     // the workgroups of slot tid are xcd_wg(tid, c) = xcd_wg(tid, 0) + 8 c
     const double* rp = a.row_part + (size_t)xcd_wg(tid, 0, a.row_chunks) * kSubPar;
-    const double gy = ordered_sum(rp + kPar, a.row_chunks, kXcds * kSubPar);
-    const double gx = ordered_sum(rp + kPar + 1, a.row_chunks, kXcds * kSubPar);
+    const double gy = ordered_sum<32>(rp + kPar, a.row_chunks, kXcds * kSubPar);
+    const double gx = ordered_sum<32>(rp + kPar + 1, a.row_chunks, kXcds * kSubPar);
     const double e = ordered_sum(a.col_part + (size_t)xcd_wg(tid, 0, a.col_chunks) * 2 + 1,
                                  a.col_chunks, kXcds * 2);
     gs[tid][0] = gy;
@@ -504,18 +511,20 @@ struct MultiUpdateArgs {
 //    block), rebuild their share of the pupil.
 template <int N>
 __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
-  constexpr int kPer = pupil_per_wg(N);
-  const int n_pw = (N * N + kPer - 1) / kPer;
+  const int n_pw = pupil_wg_slots(N, a.dk.nrows);
   if ((int)blockIdx.x >= n_pw) {
     __shared__ Corner cs[kMaxSlots];
     const int ti = blockIdx.x - n_pw, tpr = a.M / 32;
     const int tr0 = (ti / tpr) * 32, tc0 = (ti % tpr) * 32;
     // Adam moves a pixel only if its moments or its gradient are non-zero: a tile
     // that no window of this batch covers and whose moments are all zero stays
-    // as it is (exactly), and is skipped
+    // as it is (exactly), and is skipped (the flag is fetched together with the
+    // batch's slot data)
+    const int flagged = a.tile_flags[ti];
     const unsigned long long hit = tile_slots(a.sub, a.bt, a.dk, tr0, tc0, cs);
-    if (!hit && !a.tile_flags[ti]) return;
-    if (hit && threadIdx.x == 0) a.tile_flags[ti] = 1;
+    if (!hit && !flagged) return;
+    FPM_PROBE(3, 0);
+    if (hit && !flagged && threadIdx.x == 0) a.tile_flags[ti] = 1;
     const int r = tr0 + (threadIdx.x >> 3);
     const int c0 = tc0 + (threadIdx.x & 7) * 2;
     const size_t f = ((size_t)r * a.M + c0) * 2;
@@ -531,6 +540,7 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
     }
     float2 g[4];
     gather_bilinear<N>(a.X, a.dk, cs, hit, r, c0, g);
+    FPM_PROBE(3, 1);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       adam1(o[h].x, m[h].x, v[h].x, g[2 * h].x, a.c);
@@ -541,9 +551,12 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
       store_next4<N>(pm + 8 * h, m[h]);
       store_next4<N>(pv + 8 * h, v[h]);
     }
+    FPM_PROBE(3, 2);
     return;
   }
   const int pw = blockIdx.x;
+  if (pw >= pupil_wg_count(N, a.dk.nrows)) return;   // padding
+  FPM_PROBE(3, 0);
   __shared__ double red[256];
   __shared__ double gsum[kPar];
   __shared__ double gs[kMaxSlots][2];
@@ -554,18 +567,19 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
   {
     const int j = threadIdx.x & (kPar - 1), lane = threadIdx.x / kPar;
     const int cnt = lane < a.n_rows ? (a.n_rows - lane + 256 / kPar - 1) / (256 / kPar) : 0;
-    red[threadIdx.x] = ordered_sum(a.row_part + (size_t)lane * kSubPar + j, cnt,
+    red[threadIdx.x] = ordered_sum<32>(a.row_part + (size_t)lane * kSubPar + j, cnt,
                                    (256 / kPar) * kSubPar);
   }
   // offset gradients of each slot, from the workgroups that served it
   if ((int)threadIdx.x < a.bt.B) {
     const double* rp = a.row_part + (size_t)xcd_wg(threadIdx.x, 0, a.row_chunks) * kSubPar;
-    const double gy = ordered_sum(rp + kPar, a.row_chunks, kXcds * kSubPar);
-    const double gx = ordered_sum(rp + kPar + 1, a.row_chunks, kXcds * kSubPar);
+    const double gy = ordered_sum<32>(rp + kPar, a.row_chunks, kXcds * kSubPar);
+    const double gx = ordered_sum<32>(rp + kPar + 1, a.row_chunks, kXcds * kSubPar);
     gs[threadIdx.x][0] = gy;
     gs[threadIdx.x][1] = gx;
   }
   __syncthreads();
+  FPM_PROBE(3, 1);
   if (threadIdx.x < kPar) {
     double mom = 0.0;
     for (int k = 0; k < 256 / kPar; ++k) mom += red[k * kPar + threadIdx.x];
@@ -631,23 +645,9 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
       if (a.g_geom) a.g_geom[k] += gg[k];
     }
   }
-  // rebuild this workgroup's share of the pupil from the new parameters (FP64)
-  const int end = min((pw + 1) * kPer, N * N);
-  for (int idx = pw * kPer + threadIdx.x; idx < end; idx += 256) {
-    const int ky = idx / N, kx = idx - ky * N;
-    const int2 e = disk_extent<N>(a.dk, ky);
-    if (kx < e.x || kx > e.y) continue;   // off the disk P stays zero
-    const double ux = kx - N / 2, uy = ky - N / 2;
-    double z[kZern];
-    zernike15(ux * a.pg.inv_r, uy * a.pg.inv_r, z);
-    double th = 0.0;
-#pragma unroll
-    for (int q = 0; q < kZern; ++q) th += (double)nextc[0][q] * z[q];
-    th += (double)nextc[0][kZern] * defocus_kappa((ux * ux + uy * uy) * a.pg.dk2, a.pg.inv_l);
-    double sn, cs;
-    sincos(th, &sn, &cs);
-    a.P[idx] = make_float2((float)cs, (float)sn);
-  }
+  // rebuild this workgroup's rows of the pupil from the new parameters
+  rebuild_pupil_rows<N, true>(pw, a.dk, a.pg, nextc[0], true, a.P);
+  FPM_PROBE(3, 2);
   if (pw == 0 && a.loss && threadIdx.x < 64) {
     double s = 0.0;
     for (int k = threadIdx.x; k < a.n_loss; k += 64) s += a.loss_part[k];
@@ -655,6 +655,7 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
     for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
     if (threadIdx.x == 0) *a.loss += s;
   }
+  FPM_PROBE(3, 3);
 }
 
 }  // namespace fpm

@@ -370,6 +370,40 @@ def test_step_is_deterministic(dev):
         np.testing.assert_array_equal(a, b)
 
 
+def test_defocus_only_step_accepts_null_zernike_arrays(dev):
+    """With only the defocus learned, the Zernike arrays of the state may be NULL
+    (they stand for zeros): two steps give bitwise what zero arrays give."""
+    import ctypes as C
+    w = inputs.workload("small", learn_z=True)
+    say("defocus-only steps with NULL Zernike state")
+    pr = oracle_problem(w, seed=0)
+    plan = make_plan(w, pr.shifts, w.batch)
+    hp = problem.hparams(w)
+    assert hp.learn_z and not hp.learn_zernike
+    A = T(pr.A, dev)
+    outs = []
+    for null in (False, True):
+        st = fpm.State(plan, T(pr.O0, dev), None, 2.0)
+        for i in range(2):
+            leds = inputs.random_indices(w.n_led, w.batch, seed=50 + i)
+            if not null:
+                plan.step(st, hp, leds, A)
+                continue
+            cs = st.c()
+            cs.coeffs = cs.m_c = cs.v_c = None
+            ids = np.ascontiguousarray(leds, np.int32)
+            rc = plan._lib.fpm_step(plan._h, C.byref(cs), C.byref(hp.c()), ids.ctypes.data,
+                                    len(ids), None, A.data_ptr(),
+                                    C.c_void_p(torch.cuda.current_stream().cuda_stream))
+            fpm._check(rc)
+            st.t = cs.t
+        torch.cuda.synchronize()
+        outs.append([H(t).copy() for t in (st.O, st.P, st.z_um, st.m_z, st.v_z, st.loss)])
+    assert float(outs[0][2][0]) != 2.0
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_step_with_zernike_learning_matches_oracle(dev):
     w = inputs.workload("paper")
     say("two steps paper (object + Zernike)")

@@ -47,7 +47,8 @@
  * Errors.  Every call returns FPM_OK (0) or a negative code; arguments are
  *   validated on the host before any launch, so a failed call has enqueued
  *   nothing. fpm_strerror() names the code; fpm_last_error() gives a
- *   human-readable message for the last failure on the calling thread.
+ *   human-readable message for the last failure on the calling thread. No
+ *   C++ exception leaves a call (a failed host allocation is FPM_ENOMEM).
  */
 #ifndef FPM_H
 #define FPM_H

@@ -22,6 +22,9 @@
  *    rebound to the request's table (fpm_plan_set_shifts) on the lane's
  *    stream. fpm_server_reserve() creates slots ahead of time, otherwise a
  *    lane creates a slot when no free one of the request's shape exists.
+ *    Idle slots are not counted in the budget; when a new slot does not fit
+ *    in device memory, the lane frees every idle slot and tries once more
+ *    (the request fails with FPM_ENOMEM only if it still does not fit).
  *  - A request's result depends only on the request: every reduction in the
  *    update is in a fixed order and a slot is used by one request at a time,
  *    so the same request gives bitwise the same result alone or in a mix.
@@ -32,7 +35,8 @@
  *
  * Threads.  fpm_server_* calls may come from any host thread; the server's
  * lanes are host threads of its own. All calls return FPM_OK or a negative
- * code from fpm.h (fpm_last_error() has the message on the calling thread).
+ * code from fpm.h (fpm_last_error() has the message on the calling thread);
+ * no C++ exception leaves them (a failed host allocation is FPM_ENOMEM).
  * The server uses the HIP device that is current when it is created.
  */
 #ifndef FPM_SERVE_H

@@ -5,6 +5,8 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -31,6 +33,19 @@ int set_error(int code, const std::string& msg) {
 namespace {
 
 int fail(int code, const std::string& msg) { return fpm::set_error(code, msg); }
+
+// Runs the body of an entry point; a C++ exception (a failed host allocation,
+// a thread that cannot start) becomes an error code: none crosses the C ABI.
+template <class F>
+int guarded(F&& body) {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return fail(FPM_ENOMEM, "host memory allocation failed");
+  } catch (const std::exception& e) {
+    return fail(FPM_EHIP, std::string("host runtime error: ") + e.what());
+  }
+}
 
 #define FPM_HIP(call)                                                              \
   do {                                                                             \
@@ -692,124 +707,126 @@ const char* fpm_strerror(int code) {
 const char* fpm_last_error(void) { return g_last_error.c_str(); }
 
 int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** out) {
-  FPM_REQUIRE(d && shifts_host && out, "desc, shifts_host and plan must not be NULL");
-  *out = nullptr;
-  if (!lr_supported(d->n_lr)) return fail(FPM_EUNSUPPORTED, "n_lr must be 64, 128, 192, 256, 384 or 512");
-  FPM_REQUIRE(d->upsample >= 1 && (int64_t)d->upsample * d->n_lr <= 4096, "upsample out of range");
-  FPM_REQUIRE(d->n_led >= 1 && d->max_batch >= 1, "n_led and max_batch must be >= 1");
-  FPM_REQUIRE(d->max_batch <= kMaxBatch, "max_batch must be <= 1024");
-  FPM_REQUIRE(d->wavelength_um > 0 && d->na > 0 && d->mag > 0 && d->pixel_um > 0,
-              "optics must be positive");
-  fpm_plan* p = new fpm_plan();
-  FPM_HIP(hipGetDevice(&p->device));
-  p->N = d->n_lr;
-  p->s = d->upsample;
-  p->M = d->n_lr * d->upsample;
-  p->n_led = d->n_led;
-  p->max_batch = d->max_batch;
-  p->lambda = d->wavelength_um;
-  p->na = d->na;
-  p->mag = d->mag;
-  p->pixel = d->pixel_um;
-  const double dx = d->pixel_um / d->mag;
-  p->dk = 1.0 / (p->N * dx);
-  p->radius = d->na / d->wavelength_um / p->dk;
-  if (!(p->radius < p->N / 2 - 1)) {
-    delete p;
-    return fail(FPM_EINVAL, "pupil disk does not fit the N x N pupil grid");
-  }
-  // pupil disk: |u|^2 <= R^2, per-row column extents
-  std::vector<int2> ext(p->N);
-  const double r2 = p->radius * p->radius;
-  for (int ky = 0; ky < p->N; ++ky) {
-    const double uy = ky - p->N / 2;
-    int lo = p->N, hi = -1;
-    for (int kx = 0; kx < p->N; ++kx) {
-      const double ux = kx - p->N / 2;
-      if (uy * uy + ux * ux <= r2) {
-        lo = std::min(lo, kx);
-        hi = std::max(hi, kx);
-        ++p->support_px;
+  return guarded([&]() -> int {
+    FPM_REQUIRE(d && shifts_host && out, "desc, shifts_host and plan must not be NULL");
+    *out = nullptr;
+    if (!lr_supported(d->n_lr)) return fail(FPM_EUNSUPPORTED, "n_lr must be 64, 128, 192, 256, 384 or 512");
+    FPM_REQUIRE(d->upsample >= 1 && (int64_t)d->upsample * d->n_lr <= 4096, "upsample out of range");
+    FPM_REQUIRE(d->n_led >= 1 && d->max_batch >= 1, "n_led and max_batch must be >= 1");
+    FPM_REQUIRE(d->max_batch <= kMaxBatch, "max_batch must be <= 1024");
+    FPM_REQUIRE(d->wavelength_um > 0 && d->na > 0 && d->mag > 0 && d->pixel_um > 0,
+                "optics must be positive");
+    fpm_plan* p = new fpm_plan();
+    FPM_HIP(hipGetDevice(&p->device));
+    p->N = d->n_lr;
+    p->s = d->upsample;
+    p->M = d->n_lr * d->upsample;
+    p->n_led = d->n_led;
+    p->max_batch = d->max_batch;
+    p->lambda = d->wavelength_um;
+    p->na = d->na;
+    p->mag = d->mag;
+    p->pixel = d->pixel_um;
+    const double dx = d->pixel_um / d->mag;
+    p->dk = 1.0 / (p->N * dx);
+    p->radius = d->na / d->wavelength_um / p->dk;
+    if (!(p->radius < p->N / 2 - 1)) {
+      delete p;
+      return fail(FPM_EINVAL, "pupil disk does not fit the N x N pupil grid");
+    }
+    // pupil disk: |u|^2 <= R^2, per-row column extents
+    std::vector<int2> ext(p->N);
+    const double r2 = p->radius * p->radius;
+    for (int ky = 0; ky < p->N; ++ky) {
+      const double uy = ky - p->N / 2;
+      int lo = p->N, hi = -1;
+      for (int kx = 0; kx < p->N; ++kx) {
+        const double ux = kx - p->N / 2;
+        if (uy * uy + ux * ux <= r2) {
+          lo = std::min(lo, kx);
+          hi = std::max(hi, kx);
+          ++p->support_px;
+        }
+      }
+      ext[ky] = make_int2(lo, hi);
+      if (hi >= lo) {
+        if (p->nrows == 0) p->ky_lo = ky;
+        p->ky_hi = ky;
+        ++p->nrows;
       }
     }
-    ext[ky] = make_int2(lo, hi);
-    if (hi >= lo) {
-      if (p->nrows == 0) p->ky_lo = ky;
-      p->ky_hi = ky;
-      ++p->nrows;
+    // LED table and the HR tiles its windows touch
+    std::vector<int2> tiles;
+    p->rowext_h = ext;
+    if (int rc = led_table(p, shifts_host, p->shifts_h, tiles)) {
+      delete p;
+      return rc;
     }
-  }
-  // LED table and the HR tiles its windows touch
-  std::vector<int2> tiles;
-  p->rowext_h = ext;
-  if (int rc = led_table(p, shifts_host, p->shifts_h, tiles)) {
-    delete p;
-    return rc;
-  }
-  p->n_tiles = (int)tiles.size();
-  p->tiles_h = tiles;
-  p->hr_ok = hr_supported(p->M);
+    p->n_tiles = (int)tiles.size();
+    p->tiles_h = tiles;
+    p->hr_ok = hr_supported(p->M);
 
-  // kappa(|u|^2) = 2 pi (sqrt(1/l^2 - k^2) - 1/l), k^2 = |u|^2 dk^2, cancellation-free form
-  std::vector<float> kap((size_t)std::floor(r2) + 1);
-  for (size_t q = 0; q < kap.size(); ++q) {
-    const double k2 = (double)q * p->dk * p->dk, il = 1.0 / p->lambda;
-    kap[q] = (float)(-2.0 * M_PI * k2 / (std::sqrt(il * il - k2) + il));
-  }
-  int rc = FPM_OK;
-  const auto twn = twiddles(p->N);
-  if ((rc = upload(&p->device_bytes, &p->rowext, ext.data(), ext.size())) ||
-      (rc = upload(&p->device_bytes, &p->twN, twn.data(), twn.size())) ||
-      (rc = upload<float2>(&p->device_bytes, &p->X, nullptr,
-                           (size_t)std::min(p->max_batch, kMaxSlots) * p->N * p->N)) ||
-      (p->max_batch > kMaxSlots &&
-       (rc = upload<float2>(&p->device_bytes, &p->gacc, nullptr, (size_t)p->M * p->M))) ||
-      (rc = upload<float2>(&p->device_bytes, &p->gP, nullptr, (size_t)p->N * p->N)) ||
-      (rc = upload(&p->device_bytes, &p->kappa_tab, kap.data(), kap.size())) ||
-      (rc = upload<int2>(&p->device_bytes, &p->tiles, nullptr, tile_capacity(p))) ||
-      (rc = copy_tiles(p, tiles))) {
-    plan_free(p);
-    return rc;
-  }
-  int rows_grid = 0, cols_grid = 0;
-  reduce_grids(p, rows_grid, cols_grid);
-  const int pg_grid = (p->N * p->N + 255) / 256;
-  const size_t n_part = (size_t)cols_grid + (size_t)rows_grid * kPar + (size_t)pg_grid * kPar;
-  if ((rc = upload<double>(&p->device_bytes, &p->part, nullptr, n_part)) ||
-      (rc = upload<float>(&p->device_bytes, &p->staging, nullptr, kScal)) ||
-      (rc = upload<unsigned>(&p->device_bytes, &p->counters, nullptr, kCounters))) {
-    plan_free(p);
-    return rc;
-  }
-  if ((rc = upload<double>(&p->device_bytes, &p->part_lg, nullptr, (size_t)cols_grid * 2 + (size_t)rows_grid * kSubPar)) ||
-      (rc = upload<float2>(&p->device_bytes, &p->P_ws, nullptr, (size_t)p->N * p->N)) ||
-      (rc = upload<int>(&p->device_bytes, &p->oob_ws, nullptr, 1)) ||
-      (rc = upload<MultiParams>(&p->device_bytes, &p->mpar, nullptr, 2)) ||
-      (rc = upload<SubSlot>(&p->device_bytes, &p->sub, nullptr, (size_t)p->max_batch)) ||
-      (rc = upload<int>(&p->device_bytes, &p->tile_flags, nullptr, tile_capacity(p)))) {
-    plan_free(p);
-    return rc;
-  }
-  p->part_loss = p->part;
-  p->part_z = p->part + cols_grid;
-  p->part_pg = p->part_z + (size_t)rows_grid * kPar;
-  if (hipMemset(p->counters, 0, kCounters * sizeof(unsigned)) != hipSuccess) {
-    plan_free(p);
-    return fail(FPM_EHIP, "hipMemset failed");
-  }
-  if (p->hr_ok) {
-    const auto twm = twiddles(p->M);
-    if ((rc = upload(&p->device_bytes, &p->twM, twm.data(), twm.size()))) {
+    // kappa(|u|^2) = 2 pi (sqrt(1/l^2 - k^2) - 1/l), k^2 = |u|^2 dk^2, cancellation-free form
+    std::vector<float> kap((size_t)std::floor(r2) + 1);
+    for (size_t q = 0; q < kap.size(); ++q) {
+      const double k2 = (double)q * p->dk * p->dk, il = 1.0 / p->lambda;
+      kap[q] = (float)(-2.0 * M_PI * k2 / (std::sqrt(il * il - k2) + il));
+    }
+    int rc = FPM_OK;
+    const auto twn = twiddles(p->N);
+    if ((rc = upload(&p->device_bytes, &p->rowext, ext.data(), ext.size())) ||
+        (rc = upload(&p->device_bytes, &p->twN, twn.data(), twn.size())) ||
+        (rc = upload<float2>(&p->device_bytes, &p->X, nullptr,
+                             (size_t)std::min(p->max_batch, kMaxSlots) * p->N * p->N)) ||
+        (p->max_batch > kMaxSlots &&
+         (rc = upload<float2>(&p->device_bytes, &p->gacc, nullptr, (size_t)p->M * p->M))) ||
+        (rc = upload<float2>(&p->device_bytes, &p->gP, nullptr, (size_t)p->N * p->N)) ||
+        (rc = upload(&p->device_bytes, &p->kappa_tab, kap.data(), kap.size())) ||
+        (rc = upload<int2>(&p->device_bytes, &p->tiles, nullptr, tile_capacity(p))) ||
+        (rc = copy_tiles(p, tiles))) {
       plan_free(p);
       return rc;
     }
-  }
-  if (hipMemset(p->gP, 0, (size_t)p->N * p->N * sizeof(float2)) != hipSuccess) {
-    plan_free(p);
-    return fail(FPM_EHIP, "hipMemset failed");
-  }
-  *out = p;
-  return FPM_OK;
+    int rows_grid = 0, cols_grid = 0;
+    reduce_grids(p, rows_grid, cols_grid);
+    const int pg_grid = (p->N * p->N + 255) / 256;
+    const size_t n_part = (size_t)cols_grid + (size_t)rows_grid * kPar + (size_t)pg_grid * kPar;
+    if ((rc = upload<double>(&p->device_bytes, &p->part, nullptr, n_part)) ||
+        (rc = upload<float>(&p->device_bytes, &p->staging, nullptr, kScal)) ||
+        (rc = upload<unsigned>(&p->device_bytes, &p->counters, nullptr, kCounters))) {
+      plan_free(p);
+      return rc;
+    }
+    if ((rc = upload<double>(&p->device_bytes, &p->part_lg, nullptr, (size_t)cols_grid * 2 + (size_t)rows_grid * kSubPar)) ||
+        (rc = upload<float2>(&p->device_bytes, &p->P_ws, nullptr, (size_t)p->N * p->N)) ||
+        (rc = upload<int>(&p->device_bytes, &p->oob_ws, nullptr, 1)) ||
+        (rc = upload<MultiParams>(&p->device_bytes, &p->mpar, nullptr, 2)) ||
+        (rc = upload<SubSlot>(&p->device_bytes, &p->sub, nullptr, (size_t)p->max_batch)) ||
+        (rc = upload<int>(&p->device_bytes, &p->tile_flags, nullptr, tile_capacity(p)))) {
+      plan_free(p);
+      return rc;
+    }
+    p->part_loss = p->part;
+    p->part_z = p->part + cols_grid;
+    p->part_pg = p->part_z + (size_t)rows_grid * kPar;
+    if (hipMemset(p->counters, 0, kCounters * sizeof(unsigned)) != hipSuccess) {
+      plan_free(p);
+      return fail(FPM_EHIP, "hipMemset failed");
+    }
+    if (p->hr_ok) {
+      const auto twm = twiddles(p->M);
+      if ((rc = upload(&p->device_bytes, &p->twM, twm.data(), twm.size()))) {
+        plan_free(p);
+        return rc;
+      }
+    }
+    if (hipMemset(p->gP, 0, (size_t)p->N * p->N * sizeof(float2)) != hipSuccess) {
+      plan_free(p);
+      return fail(FPM_EHIP, "hipMemset failed");
+    }
+    *out = p;
+    return FPM_OK;
+  });
 }
 
 int fpm_plan_destroy(fpm_plan* p) {
@@ -819,20 +836,22 @@ int fpm_plan_destroy(fpm_plan* p) {
 }
 
 int fpm_plan_set_shifts(fpm_plan* p, const int32_t* shifts_host, void* stream) {
-  FPM_REQUIRE(p && shifts_host, "plan and shifts_host must not be NULL");
-  if (int rc = check_device(p)) return rc;
-  std::vector<int2> shifts, tiles;
-  if (int rc = led_table(p, shifts_host, shifts, tiles)) return rc;
-  hipStream_t st = (hipStream_t)stream;
-  // the previous upload from tiles_h must have completed before it is replaced
-  FPM_HIP(hipStreamSynchronize(st));
-  p->shifts_h = std::move(shifts);
-  p->tiles_h = std::move(tiles);
-  p->n_tiles = (int)p->tiles_h.size();
-  if (p->n_tiles > 0)
-    FPM_HIP(hipMemcpyAsync(p->tiles, p->tiles_h.data(), p->tiles_h.size() * sizeof(int2),
-                           hipMemcpyHostToDevice, st));
-  return FPM_OK;
+  return guarded([&]() -> int {
+    FPM_REQUIRE(p && shifts_host, "plan and shifts_host must not be NULL");
+    if (int rc = check_device(p)) return rc;
+    std::vector<int2> shifts, tiles;
+    if (int rc = led_table(p, shifts_host, shifts, tiles)) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    // the previous upload from tiles_h must have completed before it is replaced
+    FPM_HIP(hipStreamSynchronize(st));
+    p->shifts_h = std::move(shifts);
+    p->tiles_h = std::move(tiles);
+    p->n_tiles = (int)p->tiles_h.size();
+    if (p->n_tiles > 0)
+      FPM_HIP(hipMemcpyAsync(p->tiles, p->tiles_h.data(), p->tiles_h.size() * sizeof(int2),
+                             hipMemcpyHostToDevice, st));
+    return FPM_OK;
+  });
 }
 
 int fpm_plan_set_loss(fpm_plan* p, int32_t kind) {
@@ -1233,9 +1252,15 @@ int fpm_refocus(fpm_plan* p, const fpm_c32* O, const float* z_um, int32_t nz, fp
 }
 
 int fpm_timing_enable(fpm_plan* p, int32_t enable) {
-  FPM_REQUIRE(p, "plan must not be NULL");
-  p->timing = enable != 0;
-  return FPM_OK;
+  return guarded([&]() -> int {
+    FPM_REQUIRE(p, "plan must not be NULL");
+    if (enable) {   // no host allocation inside the launch brackets afterwards
+      p->timed.reserve(kMaxTimed);
+      p->event_pool.reserve(2 * kMaxTimed);
+    }
+    p->timing = enable != 0;
+    return FPM_OK;
+  });
 }
 
 int fpm_timing_repeat(fpm_plan* p, int32_t kind, int32_t reps) {

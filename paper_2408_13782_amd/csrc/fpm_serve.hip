@@ -7,6 +7,8 @@
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
+#include <exception>
+#include <new>
 #include <deque>
 #include <memory>
 #include <mutex>
@@ -98,6 +100,19 @@ namespace {
 
 int serve_fail(int code, const std::string& msg) { return fpm::set_error(code, msg); }
 
+// Runs the body of an entry point; a C++ exception (a failed host allocation,
+// a thread that cannot start) becomes an error code: none crosses the C ABI.
+template <class F>
+int guarded(F&& body) {
+  try {
+    return body();
+  } catch (const std::bad_alloc&) {
+    return serve_fail(FPM_ENOMEM, "host memory allocation failed");
+  } catch (const std::exception& e) {
+    return serve_fail(FPM_EHIP, std::string("host runtime error: ") + e.what());
+  }
+}
+
 }  // namespace
 
 struct fpm_server {
@@ -170,9 +185,30 @@ int slot_create(const ShapeKey& key, const std::vector<int32_t>& shifts,
   return FPM_OK;
 }
 
+// Free the slots no request is using (any shape) and return how many. Their
+// work has finished: a lane releases a slot only after waiting for its stream.
+int free_idle_slots(fpm_server* sv) {
+  std::vector<std::unique_ptr<Slot>> idle;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    for (auto it = sv->slots.begin(); it != sv->slots.end();) {
+      if (!(*it)->busy) {
+        idle.push_back(std::move(*it));
+        it = sv->slots.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  for (auto& x : idle) slot_free(x.get());
+  return (int)idle.size();
+}
+
 // Take a free slot of the job's shape, preferring one that holds the job's LED
 // table; another free slot of the shape is rebound to it on the lane's stream;
-// with none free, a new slot is created.
+// with none free, a new slot is created. Idle slots are not part of the
+// admission budget: when a new slot does not fit in device memory, the idle
+// slots are freed and the creation is tried once more.
 int slot_acquire(fpm_server* sv, const Job& j, hipStream_t st, Slot** out) {
   Slot* got = nullptr;
   {
@@ -194,7 +230,9 @@ int slot_acquire(fpm_server* sv, const Job& j, hipStream_t st, Slot** out) {
     return FPM_OK;
   }
   std::unique_ptr<Slot> s;
-  if (int rc = slot_create(j.key, j.shifts, s)) return rc;
+  int rc = slot_create(j.key, j.shifts, s);
+  if (rc == FPM_ENOMEM && free_idle_slots(sv) > 0) rc = slot_create(j.key, j.shifts, s);
+  if (rc) return rc;
   s->busy = true;
   std::lock_guard<std::mutex> lk(sv->mu);
   *out = s.get();
@@ -286,7 +324,7 @@ void lane_main(fpm_server* sv, Lane* lane, int index) {
     }
     int rc = ok ? FPM_OK : serve_fail(FPM_EHIP, "lane stream or event creation failed");
     Slot* slot = nullptr;
-    if (rc == FPM_OK) rc = slot_acquire(sv, *job, st, &slot);
+    if (rc == FPM_OK) rc = guarded([&] { return slot_acquire(sv, *job, st, &slot); });
     if (rc == FPM_OK) rc = run_request(*job, slot, st, ev);
     if (rc != FPM_OK && st) (void)hipStreamSynchronize(st);
     const double t_done = sv->now_ms();
@@ -338,22 +376,24 @@ int footprint_of(fpm_server* sv, const ShapeKey& key, const std::vector<int32_t>
 extern "C" {
 
 int fpm_server_create(const fpm_server_desc* d, fpm_server** out) {
-  if (!d || !out) return serve_fail(FPM_EINVAL, "desc and server must not be NULL");
-  if (d->n_lanes < 1 || d->n_lanes > kMaxLanes)
-    return serve_fail(FPM_EINVAL, "n_lanes must be in [1, 64]");
-  if (d->hbm_budget_bytes <= 0) return serve_fail(FPM_EINVAL, "hbm_budget_bytes must be > 0");
-  auto sv = new fpm_server();
-  if (hipGetDevice(&sv->device) != hipSuccess) {
-    delete sv;
-    return serve_fail(FPM_EHIP, "hipGetDevice failed");
-  }
-  sv->budget = d->hbm_budget_bytes;
-  sv->t0 = std::chrono::steady_clock::now();
-  for (int i = 0; i < d->n_lanes; ++i) sv->lanes.push_back(std::make_unique<Lane>());
-  for (int i = 0; i < d->n_lanes; ++i)
-    sv->lanes[i]->thread = std::thread(lane_main, sv, sv->lanes[i].get(), i);
-  *out = sv;
-  return FPM_OK;
+  return guarded([&]() -> int {
+    if (!d || !out) return serve_fail(FPM_EINVAL, "desc and server must not be NULL");
+    if (d->n_lanes < 1 || d->n_lanes > kMaxLanes)
+      return serve_fail(FPM_EINVAL, "n_lanes must be in [1, 64]");
+    if (d->hbm_budget_bytes <= 0) return serve_fail(FPM_EINVAL, "hbm_budget_bytes must be > 0");
+    auto sv = new fpm_server();
+    if (hipGetDevice(&sv->device) != hipSuccess) {
+      delete sv;
+      return serve_fail(FPM_EHIP, "hipGetDevice failed");
+    }
+    sv->budget = d->hbm_budget_bytes;
+    sv->t0 = std::chrono::steady_clock::now();
+    for (int i = 0; i < d->n_lanes; ++i) sv->lanes.push_back(std::make_unique<Lane>());
+    for (int i = 0; i < d->n_lanes; ++i)
+      sv->lanes[i]->thread = std::thread(lane_main, sv, sv->lanes[i].get(), i);
+    *out = sv;
+    return FPM_OK;
+  });
 }
 
 int fpm_server_drain(fpm_server* sv) {
@@ -379,76 +419,82 @@ int fpm_server_destroy(fpm_server* sv) {
 }
 
 int fpm_request_footprint(const fpm_desc* d, const int32_t* shifts_host, int64_t* bytes) {
-  if (!d || !shifts_host || !bytes)
-    return serve_fail(FPM_EINVAL, "desc, shifts_host and bytes must not be NULL");
-  fpm_plan* p = nullptr;
-  if (int rc = fpm_plan_create(d, shifts_host, &p)) return serve_fail(rc, fpm_last_error());
-  fpm_info info{};
-  fpm_plan_info(p, &info);
-  fpm_plan_destroy(p);
-  *bytes = state_bytes(*d) + info.device_bytes + data_bytes(*d);
-  return FPM_OK;
+  return guarded([&]() -> int {
+    if (!d || !shifts_host || !bytes)
+      return serve_fail(FPM_EINVAL, "desc, shifts_host and bytes must not be NULL");
+    fpm_plan* p = nullptr;
+    if (int rc = fpm_plan_create(d, shifts_host, &p)) return serve_fail(rc, fpm_last_error());
+    fpm_info info{};
+    fpm_plan_info(p, &info);
+    fpm_plan_destroy(p);
+    *bytes = state_bytes(*d) + info.device_bytes + data_bytes(*d);
+    return FPM_OK;
+  });
 }
 
 int fpm_server_reserve(fpm_server* sv, const fpm_desc* d, const int32_t* shifts_host,
                        int32_t count) {
-  if (!sv || !d || !shifts_host) return serve_fail(FPM_EINVAL, "arguments must not be NULL");
-  if (count < 0) return serve_fail(FPM_EINVAL, "count must be >= 0");
-  const ShapeKey key = key_of(d);
-  const std::vector<int32_t> shifts = table_of(d, shifts_host);
-  for (int i = 0; i < count; ++i) {
-    std::unique_ptr<Slot> s;
-    if (int rc = slot_create(key, shifts, s)) return rc;
-    std::lock_guard<std::mutex> lk(sv->mu);
-    bool known = false;
-    for (auto& f : sv->footprints) known = known || f.first == key;
-    if (!known) sv->footprints.emplace_back(key, s->footprint);
-    sv->slots.push_back(std::move(s));
-  }
-  return FPM_OK;
+  return guarded([&]() -> int {
+    if (!sv || !d || !shifts_host) return serve_fail(FPM_EINVAL, "arguments must not be NULL");
+    if (count < 0) return serve_fail(FPM_EINVAL, "count must be >= 0");
+    const ShapeKey key = key_of(d);
+    const std::vector<int32_t> shifts = table_of(d, shifts_host);
+    for (int i = 0; i < count; ++i) {
+      std::unique_ptr<Slot> s;
+      if (int rc = slot_create(key, shifts, s)) return rc;
+      std::lock_guard<std::mutex> lk(sv->mu);
+      bool known = false;
+      for (auto& f : sv->footprints) known = known || f.first == key;
+      if (!known) sv->footprints.emplace_back(key, s->footprint);
+      sv->slots.push_back(std::move(s));
+    }
+    return FPM_OK;
+  });
 }
 
 int fpm_server_submit(fpm_server* sv, const fpm_request* r) {
-  if (!sv || !r) return serve_fail(FPM_EINVAL, "server and request must not be NULL");
-  const fpm_desc& d = r->desc;
-  if (!r->shifts_host || !r->meas_amp || !r->O_out)
-    return serve_fail(FPM_EINVAL, "shifts_host, meas_amp and O_out must not be NULL");
-  if (d.n_led < 1 || d.max_batch < 1) return serve_fail(FPM_EINVAL, "empty LED table or batch");
-  if (r->centre_led < 0 || r->centre_led >= d.n_led)
-    return serve_fail(FPM_EINVAL, "centre_led outside [0, n_led)");
-  if (r->n_steps < 0) return serve_fail(FPM_EINVAL, "n_steps must be >= 0");
-  if (r->n_steps > 0 && (!r->leds || !r->batch_sizes))
-    return serve_fail(FPM_EINVAL, "leds and batch_sizes must not be NULL");
-  auto job = std::make_unique<Job>();
-  job->req = *r;
-  job->key = key_of(&d);
-  job->shifts = table_of(&d, r->shifts_host);
-  size_t total = 0;
-  for (int i = 0; i < r->n_steps; ++i) {
-    const int b = r->batch_sizes[i];
-    if (b < 1 || b > d.max_batch)
-      return serve_fail(FPM_EINVAL, "batch sizes must be in [1, max_batch]");
-    total += (size_t)b;
-  }
-  for (size_t i = 0; i < total; ++i)
-    if (r->leds[i] < 0 || r->leds[i] >= d.n_led)
-      return serve_fail(FPM_EINVAL, "LED id outside [0, n_led)");
-  if (r->n_steps > 0) {
-    job->leds.assign(r->leds, r->leds + total);
-    job->sizes.assign(r->batch_sizes, r->batch_sizes + r->n_steps);
-  }
-  // the copies own the host arrays from here on
-  job->req.shifts_host = nullptr;
-  job->req.leds = nullptr;
-  job->req.batch_sizes = nullptr;
-  if (int rc = footprint_of(sv, job->key, job->shifts, &job->footprint)) return rc;
-  if (job->footprint > sv->budget)
-    return serve_fail(FPM_EINVAL, "the request's footprint exceeds the server's budget");
-  std::lock_guard<std::mutex> lk(sv->mu);
-  job->t_submit = sv->now_ms();
-  sv->queue.push_back(std::move(job));
-  admit_locked(sv);
-  return FPM_OK;
+  return guarded([&]() -> int {
+    if (!sv || !r) return serve_fail(FPM_EINVAL, "server and request must not be NULL");
+    const fpm_desc& d = r->desc;
+    if (!r->shifts_host || !r->meas_amp || !r->O_out)
+      return serve_fail(FPM_EINVAL, "shifts_host, meas_amp and O_out must not be NULL");
+    if (d.n_led < 1 || d.max_batch < 1) return serve_fail(FPM_EINVAL, "empty LED table or batch");
+    if (r->centre_led < 0 || r->centre_led >= d.n_led)
+      return serve_fail(FPM_EINVAL, "centre_led outside [0, n_led)");
+    if (r->n_steps < 0) return serve_fail(FPM_EINVAL, "n_steps must be >= 0");
+    if (r->n_steps > 0 && (!r->leds || !r->batch_sizes))
+      return serve_fail(FPM_EINVAL, "leds and batch_sizes must not be NULL");
+    auto job = std::make_unique<Job>();
+    job->req = *r;
+    job->key = key_of(&d);
+    job->shifts = table_of(&d, r->shifts_host);
+    size_t total = 0;
+    for (int i = 0; i < r->n_steps; ++i) {
+      const int b = r->batch_sizes[i];
+      if (b < 1 || b > d.max_batch)
+        return serve_fail(FPM_EINVAL, "batch sizes must be in [1, max_batch]");
+      total += (size_t)b;
+    }
+    for (size_t i = 0; i < total; ++i)
+      if (r->leds[i] < 0 || r->leds[i] >= d.n_led)
+        return serve_fail(FPM_EINVAL, "LED id outside [0, n_led)");
+    if (r->n_steps > 0) {
+      job->leds.assign(r->leds, r->leds + total);
+      job->sizes.assign(r->batch_sizes, r->batch_sizes + r->n_steps);
+    }
+    // the copies own the host arrays from here on
+    job->req.shifts_host = nullptr;
+    job->req.leds = nullptr;
+    job->req.batch_sizes = nullptr;
+    if (int rc = footprint_of(sv, job->key, job->shifts, &job->footprint)) return rc;
+    if (job->footprint > sv->budget)
+      return serve_fail(FPM_EINVAL, "the request's footprint exceeds the server's budget");
+    std::lock_guard<std::mutex> lk(sv->mu);
+    job->t_submit = sv->now_ms();
+    sv->queue.push_back(std::move(job));
+    admit_locked(sv);
+    return FPM_OK;
+  });
 }
 
 int fpm_server_poll(fpm_server* sv, fpm_completion* out, int32_t max_out, int32_t* n_out,

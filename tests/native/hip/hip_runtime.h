@@ -2,6 +2,7 @@
 // scheduling logic (admission, FIFO order, completion records) can be tested
 // on a machine without a GPU. Memory is host memory; streams complete at once.
 #pragma once
+#include <atomic>
 #include <cstdlib>
 #include <cstring>
 #include <cstddef>
@@ -18,7 +19,21 @@ inline hipError_t hipEventSynchronize(hipEvent_t) { return 0; }
 inline hipError_t hipEventDestroy(hipEvent_t e) { free(e); return 0; }
 inline hipError_t hipStreamDestroy(hipStream_t s) { free(s); return 0; }
 inline hipError_t hipStreamSynchronize(hipStream_t) { return 0; }
-inline hipError_t hipMalloc(void** p, size_t n) { *p = malloc(n); return *p ? 0 : 2; }
-inline hipError_t hipFree(void* p) { free(p); return 0; }
+// Device memory: host memory, with an optional cap on the number of live
+// allocations (0: none) so that out-of-memory paths can be exercised.
+inline std::atomic<int>& hip_stub_alloc_cap() { static std::atomic<int> cap{0}; return cap; }
+inline std::atomic<int>& hip_stub_live() { static std::atomic<int> live{0}; return live; }
+inline hipError_t hipMalloc(void** p, size_t n) {
+  const int cap = hip_stub_alloc_cap().load();
+  if (cap > 0 && hip_stub_live().load() >= cap) { *p = nullptr; return 2; }
+  *p = malloc(n);
+  if (!*p) return 2;
+  ++hip_stub_live();
+  return 0;
+}
+inline hipError_t hipFree(void* p) {
+  if (p) { --hip_stub_live(); free(p); }
+  return 0;
+}
 inline hipError_t hipMemsetAsync(void* p, int v, size_t n, hipStream_t) { memset(p, v, n); return 0; }
 inline hipError_t hipMemcpyAsync(void* d, const void* s, size_t n, int, hipStream_t) { memcpy(d, s, n); return 0; }

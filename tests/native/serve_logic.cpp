@@ -1,12 +1,14 @@
 // Scheduling checks of the tile server against the stand-ins in fake_fpm.cpp:
 // every request completes with its own result, admission is first-in
 // first-out, the footprint budget caps the requests in flight, invalid
-// requests are refused, destroy waits for queued work.
+// requests are refused, destroy waits for queued work, idle slots of other
+// shapes are freed when device memory runs out.
 #include <atomic>
 #include <cstdio>
 #include <vector>
 
 #include "fpm_serve.h"
+#include "hip/hip_runtime.h"
 
 extern std::atomic<int> peak;
 extern std::atomic<int> rebinds;
@@ -135,6 +137,43 @@ int main() {
     for (int i = 0; i < 6; ++i) CHECK(outs[i][1].re == (float)(7 * (order[i] + 1)));
     CHECK(rebinds.load() == 3);   // 0 -> 1 -> 2 -> 0
     CHECK(fpm_server_destroy(s1) == FPM_OK);
+  }
+  // device memory for two slots only: a third shape frees the idle slots
+  {
+    hip_stub_alloc_cap() = 2;
+    fpm_server_desc one{1, 8 * fp};
+    fpm_server* s2 = nullptr;
+    CHECK(fpm_server_create(&one, &s2) == FPM_OK);
+    std::vector<fpm_desc> shapes(3, d);
+    shapes[1].wavelength_um = 0.6;
+    shapes[2].wavelength_um = 0.7;
+    const int order[5] = {0, 1, 2, 0, 1};
+    for (int i = 0; i < 5; ++i) {
+      fpm_request r{};
+      r.desc = shapes[order[i]];
+      r.shifts_host = shifts.data();
+      r.meas_amp = amp.data();
+      r.centre_led = 4;
+      r.leds = leds.data();
+      r.batch_sizes = sizes.data();
+      r.n_steps = 2;
+      r.O_out = outs[i].data();
+      r.loss_out = &loss[i];
+      loss[i] = 0.0;
+      r.tag = 200 + i;
+      CHECK(fpm_server_submit(s2, &r) == FPM_OK);
+    }
+    CHECK(fpm_server_drain(s2) == FPM_OK);
+    std::vector<fpm_completion> cc(8);
+    int32_t nc = 0, slots2 = 0;
+    CHECK(fpm_server_poll(s2, cc.data(), 8, &nc, 0) == FPM_OK && nc == 5);
+    for (int i = 0; i < nc; ++i) CHECK(cc[i].status == FPM_OK);
+    for (int i = 0; i < 5; ++i) CHECK(loss[i] == 2.0);
+    CHECK(fpm_server_stats(s2, nullptr, nullptr, nullptr, nullptr, nullptr, &slots2) == FPM_OK);
+    CHECK(slots2 <= 2);
+    CHECK(fpm_server_destroy(s2) == FPM_OK);
+    CHECK(hip_stub_live().load() == 0);
+    hip_stub_alloc_cap() = 0;
   }
   std::printf("OK\n");
   return 0;

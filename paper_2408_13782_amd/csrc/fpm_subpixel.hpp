@@ -381,11 +381,7 @@ __global__ void __launch_bounds__(256) loss_grad_reduce(ReduceArgs a) {
   }
   __syncthreads();
   if (tid == 0) {
-    if (a.loss) {
-      double l = 0.0;
-      for (int w = 0; w < a.col_wgs; ++w) l += a.col_part[(size_t)w * 2];
-      *a.loss += l;
-    }
+    if (a.loss) *a.loss += ordered_sum<32>(a.col_part, a.col_wgs, 2);   // workgroup order
     if (a.g_geom) {
       double gg[4] = {0.0, 0.0, 0.0, 0.0};
       for (int b = 0; b < a.bt.B; ++b)

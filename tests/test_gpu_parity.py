@@ -484,6 +484,41 @@ def test_batches_above_64_run_in_groups_and_match_oracle(dev):
         plan.loss_grad(fpm.LedGrid(w.n_side, w.pitch_mm, w.height_mm), st.O, all_leds, A)
 
 
+def test_full_gradient_step_at_paper_size_matches_oracle(dev):
+    """All 225 LEDs of the paper workload in one batch (Eq. 6; four groups of up
+    to 64): loss and object gradient of fpm_backward, then one object + Zernike
+    step, against the oracle."""
+    w = inputs.workload("paper")
+    say("full-gradient batch of 225 LEDs at 256^2 -> 1024^2")
+    pr = oracle_problem(w, seed=0)
+    leds = inputs.led_permutations(w.n_led, 1, seed=8)[0]
+    P = fo.pupil(pr.mask, pr.zern, np.zeros(15), 0.0, pr.kappa).astype(np.complex64)
+    plan, gO, gP, loss, ref = _backward_case(dev, w, pr.O0, P, leds, pr.A, None)
+    assert plan.info.max_batch == 225
+    m = pr.mask.astype(bool)
+    assert rel_l2(gO, ref.g_O) <= GRAD_TOL
+    assert rel_l2(gP[m], ref.g_P[m]) <= GRAD_TOL
+    assert abs(loss - ref.loss) <= 1e-5 * ref.loss
+    st = _gpu_state(plan, pr.O0, dev)
+    hp = problem.hparams(w)
+    plan.step(st, hp, leds, T(pr.A, dev))
+    torch.cuda.synchronize()
+    ost = fo.init_state(pr.O0)
+    cfg = fo.SolveConfig(lr_object=w.lr_object, lr_zernike=w.lr_zernike, learn_pupil=True)
+    oloss = fo.step(ost, cfg, pr.mask, pr.zern, pr.kappa, pr.shifts, leds, pr.A.astype(np.float64))
+    assert abs(float(H(st.loss)[0]) - oloss) <= 1e-5 * oloss
+    # Adam's first step is lr sign(g): compare where the sign is decided
+    def ri(z):
+        return np.stack([z.real, z.imag], -1).astype(np.float64)
+
+    O1, O1_ref, g = ri(H(st.O)), ri(ost.O), ri(ref.g_O)
+    decided = np.abs(g) > 1e-4 * np.abs(g).max()
+    diff = np.abs(O1 - O1_ref)
+    assert np.all(diff[decided] <= 1e-6 + 1e-5 * np.abs(O1_ref[decided]))
+    assert np.count_nonzero(diff[~decided] > 1e-6) <= 1e-3 * diff.size
+    np.testing.assert_allclose(H(st.coeffs)[1:], ost.coeffs[1:], atol=1e-3 * w.lr_zernike)
+
+
 def _gradient_at_gpu_state(dev, plan, pr, st, leds, P):
     gO = torch.zeros_like(st.O)
     plan.backward(st.O, P, np.asarray(leds, np.int32), T(pr.A, dev), gO)

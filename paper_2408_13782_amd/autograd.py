@@ -13,9 +13,12 @@ from __future__ import annotations
 
 from dataclasses import dataclass
 
+import numpy as np
 import torch
 
 from . import fpm
+
+MAX_GROUP = 64   # LEDs per fpm_loss_grad call
 
 
 @dataclass
@@ -37,11 +40,15 @@ class FPMLoss(torch.autograd.Function):
                  "g_geom": flat[1 + fpm.N_PAR:5 + fpm.N_PAR], "g_gamma": flat[5 + fpm.N_PAR:],
                  "g_O": torch.zeros_like(O, memory_format=torch.contiguous_format),
                  "oob": torch.zeros(1, dtype=torch.int32, device=O.device)}
-        g = plan.loss_grad(lctx.grid, O.detach(), lctx.leds, lctx.meas_amp,
-                           coeffs=None if coeffs is None else coeffs.detach(),
-                           z_um=None if z_um is None else z_um.detach(),
-                           geom=None if geom is None else geom.detach(),
-                           gamma=None if gamma is None else gamma.detach(), grads=grads)
+        # fpm_loss_grad takes up to 64 LEDs and adds into the accumulators: a
+        # larger batch (up to the full gradient of Eq. 6) is summed in groups
+        leds = np.ascontiguousarray(np.asarray(lctx.leds, np.int32).reshape(-1))
+        for b0 in range(0, max(leds.size, 1), MAX_GROUP):
+            g = plan.loss_grad(lctx.grid, O.detach(), leds[b0:b0 + MAX_GROUP], lctx.meas_amp,
+                               coeffs=None if coeffs is None else coeffs.detach(),
+                               z_um=None if z_um is None else z_um.detach(),
+                               geom=None if geom is None else geom.detach(),
+                               gamma=None if gamma is None else gamma.detach(), grads=grads)
         fctx.flat, fctx.g_O = flat, g["g_O"]
         fctx.dtypes = tuple(None if t is None else t.dtype for t in (coeffs, z_um, geom, gamma))
         fctx.oob = g["oob"]

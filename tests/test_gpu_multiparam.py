@@ -118,6 +118,50 @@ def test_loss_grad_matches_oracle(dev, case):
     np.testing.assert_allclose(H(g["g_gamma"]), ref.g_gamma, rtol=1e-5, atol=1e-6 * np.abs(ref.g_gamma).max())
 
 
+def test_autograd_function_takes_batches_above_64_in_groups(dev):
+    """All 81 LEDs of a 9x9 grid through the autograd function (two calls of
+    fpm_loss_grad adding into the same accumulators): loss and every gradient
+    against the oracle."""
+    from paper_2408_13782_amd.autograd import FPMLoss, LossContext
+    say("autograd function with a batch of 81 LEDs")
+    cs = Case(n_side=9, seed=1)
+    w = cs.w
+    plan = cs.plan(max_batch=w.n_led)
+    c0 = inputs.random_real((15,), seed=22, lo=-0.2, hi=0.2).astype(np.float32)
+    geom0 = 0.5 * cs.geom_true
+    gamma0 = inputs.random_real((w.n_led,), seed=23, lo=0.8, hi=1.2)
+    leds = inputs.led_permutations(w.n_led, 1, seed=24)[0]
+    s, J = fo.led_shifts_and_jacobian(cs.opt, w.n_side, w.pitch_mm, w.height_mm, geom0)
+    frac = np.abs((s + (w.m_hr // 2 - w.n_lr // 2)) - np.round(s + (w.m_hr // 2 - w.n_lr // 2)))
+    assert frac.min() > 1e-4
+    O = T(cs.O0, dev).requires_grad_()
+    c = T(c0, dev).requires_grad_()
+    z = torch.tensor([0.7], dtype=torch.float32, device=dev, requires_grad=True)
+    geom = T(geom0, dev).requires_grad_()
+    gamma = T(gamma0.astype(np.float32), dev).requires_grad_()
+    loss = FPMLoss.apply(O, c, z, geom, gamma, LossContext(plan, cs.grid, leds, T(cs.A, dev)))
+    loss.backward()
+    torch.cuda.synchronize()
+    ref = cs.oracle(cs.O0.astype(np.complex128), c0.astype(np.float64), 0.7, geom0,
+                    gamma0.astype(np.float32).astype(np.float64), leds)
+    assert abs(float(loss) - ref.loss) <= 1e-5 * ref.loss
+    assert rel_l2(H(O.grad), ref.g_O) <= GRAD_TOL
+    g_gamma = H(gamma.grad).astype(np.float64)
+    np.testing.assert_allclose(g_gamma, ref.g_gamma, rtol=1e-4, atol=1e-5 * np.abs(ref.g_gamma).max())
+    P = fo.pupil(cs.mask, cs.zern, c0.astype(np.float64), 0.7, cs.kappa)
+    sub = fo.loss_and_grads_subpixel(cs.O0.astype(np.complex128), P, s, leds,
+                                     cs.A.astype(np.float64), gamma0.astype(np.float32).astype(np.float64))
+    _, _, g_theta = fo.pupil_param_grads(sub.g_P, P, cs.zern, cs.kappa)
+    g_c = H(c.grad).astype(np.float64)
+    for j in range(1, 15):
+        assert abs(g_c[j] - ref.g_coeffs[j]) <= GRAD_TOL * np.sum(np.abs(g_theta * cs.zern[j])), j
+    assert abs(float(H(z.grad)[0]) - ref.g_z) <= GRAD_TOL * np.sum(np.abs(g_theta * cs.kappa))
+    scale = np.zeros(4)
+    for b, led in enumerate(leds):
+        scale += np.abs(J[led].T) @ np.abs(sub.g_shift[b])
+    assert np.all(np.abs(H(geom.grad) - ref.g_geom) <= 1e-4 * scale)
+
+
 def test_loss_grad_without_geometry_matches_the_nearest_path(dev, case):
     say("loss_grad with the plan's integer LED table vs fpm_backward")
     w = case.w

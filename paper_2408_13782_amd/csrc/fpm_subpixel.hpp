@@ -563,14 +563,14 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
   {
     const int j = threadIdx.x & (kPar - 1), lane = threadIdx.x / kPar;
     const int cnt = lane < a.n_rows ? (a.n_rows - lane + 256 / kPar - 1) / (256 / kPar) : 0;
-    red[threadIdx.x] = ordered_sum<32>(a.row_part + (size_t)lane * kSubPar + j, cnt,
+    red[threadIdx.x] = ordered_sum<24>(a.row_part + (size_t)lane * kSubPar + j, cnt,
                                    (256 / kPar) * kSubPar);
   }
   // offset gradients of each slot, from the workgroups that served it
   if ((int)threadIdx.x < a.bt.B) {
     const double* rp = a.row_part + (size_t)xcd_wg(threadIdx.x, 0, a.row_chunks) * kSubPar;
-    const double gy = ordered_sum<32>(rp + kPar, a.row_chunks, kXcds * kSubPar);
-    const double gx = ordered_sum<32>(rp + kPar + 1, a.row_chunks, kXcds * kSubPar);
+    const double gy = ordered_sum<24>(rp + kPar, a.row_chunks, kXcds * kSubPar);
+    const double gx = ordered_sum<24>(rp + kPar + 1, a.row_chunks, kXcds * kSubPar);
     gs[threadIdx.x][0] = gy;
     gs[threadIdx.x][1] = gx;
   }

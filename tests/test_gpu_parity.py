@@ -154,7 +154,7 @@ def _backward_case(dev, w, O, P, leds, A, gamma, with_gP=True):
 
 
 @pytest.mark.parametrize("name,B", [("small", 8), ("small", 3), ("paper", 16), ("paper", 13),
-                                    ("large", 32)])
+                                    ("large", 32), ("large", 64)])
 def test_backward_matches_oracle_at_initial_state(dev, name, B):
     w = inputs.workload(name)
     say(f"backward {name} B={B}")

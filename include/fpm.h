@@ -64,7 +64,8 @@ enum {
   FPM_EINVAL = -1,        /* bad size, null required pointer, B > max_batch ... */
   FPM_ENOMEM = -2,        /* device allocation failed at plan creation */
   FPM_EHIP = -3,          /* a HIP runtime call failed */
-  FPM_EUNSUPPORTED = -4   /* N or M outside the compiled set */
+  FPM_EUNSUPPORTED = -4,  /* N or M outside the compiled set */
+  FPM_ENONFINITE = -5     /* a served solve ended with a non-finite loss (fpm_serve.h) */
 };
 
 typedef struct fpm_plan fpm_plan;

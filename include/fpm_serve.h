@@ -28,6 +28,9 @@
  *  - A request's result depends only on the request: every reduction in the
  *    update is in a fixed order and a slot is used by one request at a time,
  *    so the same request gives bitwise the same result alone or in a mix.
+ *  - A solve whose summed loss is not finite (NaN or infinite measured data,
+ *    a diverging learning rate) completes with status FPM_ENONFINITE; its
+ *    outputs are still written. Other requests are not affected.
  *
  * Footprint of a request (bytes, what admission counts):
  *   state 3 M^2 * 8 (spectrum and the two Adam moments) + N^2 * 8 (pupil)
@@ -77,7 +80,7 @@ typedef struct {
    (steady clock, zero at creation; fpm_server_clock_ms reads it). */
 typedef struct {
   int64_t tag;
-  int32_t status;             /* FPM_OK or the code of the call that failed */
+  int32_t status;             /* FPM_OK, FPM_ENONFINITE, or the code of the call that failed */
   int32_t lane;               /* lane that ran it */
   double t_submit_ms;         /* fpm_server_submit returned */
   double t_admit_ms;          /* a lane took it */

@@ -700,6 +700,7 @@ const char* fpm_strerror(int code) {
     case FPM_ENOMEM: return "out of device memory";
     case FPM_EHIP: return "HIP runtime error";
     case FPM_EUNSUPPORTED: return "unsupported size";
+    case FPM_ENONFINITE: return "non-finite loss";
   }
   return "unknown error";
 }

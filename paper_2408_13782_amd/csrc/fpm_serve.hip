@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <chrono>
+#include <cmath>
 #include <condition_variable>
 #include <cstring>
 #include <exception>
@@ -279,8 +280,12 @@ int run_request(const Job& j, Slot* s, hipStream_t st, hipEvent_t ev) {
   if (r.loss_out && hipMemcpyAsync(r.loss_out, s->loss, sizeof(double), hipMemcpyDeviceToDevice,
                                    st) != hipSuccess)
     return serve_fail(FPM_EHIP, "loss copy failed");
+  double loss = 0.0;   // the summed loss, for the non-finite guard
+  if (hipMemcpyAsync(&loss, s->loss, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
+    return serve_fail(FPM_EHIP, "loss read-back failed");
   if (hipEventRecord(ev, st) != hipSuccess || hipEventSynchronize(ev) != hipSuccess)
     return serve_fail(FPM_EHIP, "waiting for the request failed");
+  if (!std::isfinite(loss)) return serve_fail(FPM_ENONFINITE, "the solve's loss is not finite");
   return FPM_OK;
 }
 

@@ -15,7 +15,13 @@ import numpy as np
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libfpm.so")
 
+# status codes of include/fpm.h
 FPM_OK = 0
+FPM_EINVAL = -1
+FPM_ENOMEM = -2
+FPM_EHIP = -3
+FPM_EUNSUPPORTED = -4
+FPM_ENONFINITE = -5
 N_ZERN = 15
 N_PAR = 16
 
@@ -255,6 +261,37 @@ class State:
         s.loss = self.loss.data_ptr()
         s.t = self.t
         return s
+
+    _SAVED = ("O", "m_O", "v_O", "P", "coeffs", "m_c", "v_c", "z_um", "m_z", "v_z", "g_par",
+              "loss")
+
+    def save(self, path: str, **extra):
+        """Checkpoint: every tensor of the state, the Adam step count t and any
+        caller values (e.g. the schedule position) to an .npz file. Resuming from
+        it (State.load) continues bitwise as if never interrupted."""
+        import torch
+        torch.cuda.synchronize()
+        arrays = {k: getattr(self, k).cpu().numpy() for k in self._SAVED}
+        np.savez(path, t=np.int64(self.t), **arrays,
+                 **{"extra_" + k: np.asarray(v) for k, v in extra.items()})
+
+    @classmethod
+    def load(cls, plan: "Plan", path: str):
+        """(state, extra) from a checkpoint written by save, on the current device."""
+        import torch
+        dev = torch.device("cuda", torch.cuda.current_device())
+        with np.load(path, allow_pickle=False) as f:
+            st = cls(plan, torch.as_tensor(f["O"]).to(dev), P0=torch.as_tensor(f["P"]).to(dev))
+            for k in cls._SAVED:
+                t = getattr(st, k)
+                src = torch.as_tensor(f[k])
+                if tuple(src.shape) != tuple(t.shape) or src.dtype != t.dtype:
+                    raise FpmError(f"checkpoint entry {k} does not fit the plan")
+                t.copy_(src.to(dev))
+            st.t = int(f["t"])
+            extra = {k[len("extra_"):]: f[k] for k in f.files if k.startswith("extra_")}
+        torch.cuda.synchronize()
+        return st, extra
 
 
 class Geometry:

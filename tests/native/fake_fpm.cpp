@@ -1,8 +1,10 @@
 // Stand-ins for the libfpm entry points the tile server calls. A "solve"
 // sleeps 20 us per step, writes its first LED id into O[0].im, the first entry
-// of its plan's LED table into O[1].re and its step count into the loss; the
+// of its plan's LED table into O[1].re and its step count into the loss (NaN
+// when the first measured value is NaN); the
 // largest number of solves in flight and the LED-table rebinds are counted.
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <string>
 #include <thread>
@@ -28,10 +30,11 @@ int fpm_plan_info(const fpm_plan* p, fpm_info* i) { i->device_bytes = 1000 * p->
 int fpm_init_spectrum(fpm_plan*, const float*, fpm_c32* O, void*) { O[0].re = 1; return 0; }
 int fpm_pupil(fpm_plan*, const float*, int32_t, const float*, fpm_c32*, void*) { return 0; }
 std::atomic<int> live{0}, peak{0};
-int fpm_run(fpm_plan* pl, fpm_state* s, const fpm_hparams*, const int32_t* leds, const int32_t* sizes, int32_t n, const float*, const float*, void*) {
+int fpm_run(fpm_plan* pl, fpm_state* s, const fpm_hparams*, const int32_t* leds, const int32_t* sizes, int32_t n, const float*, const float* meas, void*) {
   int l = ++live; int p = peak; while (l > p && !peak.compare_exchange_weak(p, l)) {}
   std::this_thread::sleep_for(std::chrono::microseconds(20 * n));
   s->O[0].im = (float)leds[0]; s->loss[0] = n;
+  if (std::isnan(meas[0])) s->loss[0] = NAN;   // NaN data give a NaN loss
   s->O[1].re = (float)pl->shifts[0];   // the LED table the solve ran with
   --live; return 0;
 }

@@ -9,7 +9,7 @@
 typedef int hipError_t;
 typedef void* hipStream_t;
 typedef void* hipEvent_t;
-enum { hipSuccess = 0, hipMemcpyDeviceToDevice = 3, hipStreamNonBlocking = 1, hipEventBlockingSync = 1, hipEventDisableTiming = 2 };
+enum { hipSuccess = 0, hipMemcpyDeviceToHost = 2, hipMemcpyDeviceToDevice = 3, hipStreamNonBlocking = 1, hipEventBlockingSync = 1, hipEventDisableTiming = 2 };
 inline hipError_t hipGetDevice(int* d) { *d = 0; return 0; }
 inline hipError_t hipSetDevice(int) { return 0; }
 inline hipError_t hipStreamCreateWithFlags(hipStream_t* s, unsigned) { *s = malloc(1); return 0; }

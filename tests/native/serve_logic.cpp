@@ -2,8 +2,10 @@
 // every request completes with its own result, admission is first-in
 // first-out, the footprint budget caps the requests in flight, invalid
 // requests are refused, destroy waits for queued work, idle slots of other
-// shapes are freed when device memory runs out.
+// shapes are freed when device memory runs out, a request whose loss is not
+// finite fails alone.
 #include <atomic>
+#include <cmath>
 #include <cstdio>
 #include <vector>
 
@@ -174,6 +176,37 @@ int main() {
     CHECK(fpm_server_destroy(s2) == FPM_OK);
     CHECK(hip_stub_live().load() == 0);
     hip_stub_alloc_cap() = 0;
+  }
+  // NaN data in one request: that request completes with FPM_ENONFINITE, the
+  // others with FPM_OK
+  {
+    fpm_server_desc two{2, 8 * fp};
+    fpm_server* s3 = nullptr;
+    CHECK(fpm_server_create(&two, &s3) == FPM_OK);
+    std::vector<float> bad_amp(amp);
+    bad_amp[0] = NAN;
+    for (int i = 0; i < 6; ++i) {
+      fpm_request r{};
+      r.desc = d;
+      r.shifts_host = shifts.data();
+      r.meas_amp = i == 3 ? bad_amp.data() : amp.data();
+      r.centre_led = 4;
+      r.leds = leds.data();
+      r.batch_sizes = sizes.data();
+      r.n_steps = 2;
+      r.O_out = outs[i].data();
+      r.loss_out = &loss[i];
+      r.tag = 300 + i;
+      CHECK(fpm_server_submit(s3, &r) == FPM_OK);
+    }
+    CHECK(fpm_server_drain(s3) == FPM_OK);
+    std::vector<fpm_completion> cc(8);
+    int32_t nc = 0;
+    CHECK(fpm_server_poll(s3, cc.data(), 8, &nc, 0) == FPM_OK && nc == 6);
+    for (int i = 0; i < nc; ++i)
+      CHECK(cc[i].status == (cc[i].tag == 303 ? FPM_ENONFINITE : FPM_OK));
+    for (int i = 0; i < 6; ++i) CHECK(i == 3 ? std::isnan(loss[i]) : loss[i] == 2.0);
+    CHECK(fpm_server_destroy(s3) == FPM_OK);
   }
   std::printf("OK\n");
   return 0;

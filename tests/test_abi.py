@@ -54,6 +54,16 @@ def test_error_strings():
     assert lib.fpm_strerror(0) == b"ok"
     assert lib.fpm_strerror(-1) == b"invalid argument"
     assert lib.fpm_strerror(-4) == b"unsupported size"
+    assert lib.fpm_strerror(-5) == b"non-finite loss"
+
+
+def test_status_codes_of_the_binding_match_the_header():
+    src = open(HEADER).read()
+    codes = dict((k, int(v)) for k, v in re.findall(r"\b(FPM_E[A-Z]+|FPM_OK)\s*=\s*(-?\d+)", src))
+    assert len(codes) == 6
+    for name, value in codes.items():
+        assert getattr(fpm, name) == value, name
+        assert fpm.load().fpm_strerror(value) != b"unknown error", name
 
 
 @pytest.mark.parametrize("name", ["small", "paper", "large"])

@@ -634,3 +634,29 @@ def test_edge_cases(dev):
         make_plan(w, bad, 8)
     with pytest.raises(fpm.FpmError):
         fpm.Plan(96, 4, pr.shifts, 8, w.wavelength_um, w.na, w.mag, w.pixel_um)
+
+
+def test_checkpoint_resume_is_bitwise(dev, tmp_path):
+    """A solve stopped after 7 steps, saved, loaded into a fresh state and run
+    on equals the uninterrupted solve bitwise (spectrum, moments, pupil
+    parameters, Adam step count, loss)."""
+    w = inputs.workload("small", learn_zernike=True, learn_z=True)
+    say("checkpoint and resume")
+    pr = oracle_problem(w, seed=3)
+    plan = make_plan(w, pr.shifts, w.batch)
+    hp = problem.hparams(w)
+    A = T(pr.A, dev)
+    sched = problem.flatten_schedule(problem.schedule(inputs.led_permutations(w.n_led, 3, seed=4),
+                                                      w.batch))
+    full = _gpu_state(plan, pr.O0, dev)
+    plan.run(full, hp, *sched.span(0, 14), A)
+    part = _gpu_state(plan, pr.O0, dev)
+    plan.run(part, hp, *sched.span(0, 7), A)
+    part.save(str(tmp_path / "ck.npz"), step=7)
+    resumed, extra = fpm.State.load(plan, str(tmp_path / "ck.npz"))
+    assert int(extra["step"]) == 7 and resumed.t == 7
+    plan.run(resumed, hp, *sched.span(int(extra["step"]), 14), A)
+    torch.cuda.synchronize()
+    assert resumed.t == full.t == 14
+    for name in ("O", "m_O", "v_O", "P", "coeffs", "m_c", "v_c", "z_um", "m_z", "v_z", "loss"):
+        np.testing.assert_array_equal(H(getattr(resumed, name)), H(getattr(full, name)), name)

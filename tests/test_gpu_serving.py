@@ -143,3 +143,29 @@ def test_measure_reports_latency_and_throughput(serving):
         assert 0 < r["p50_ms"] <= r["p99_ms"] <= r["max_ms"]
         assert r["requests_per_s"] > 0
     assert row["sequential"]["max_running"] == 1
+
+
+def test_non_finite_request_fails_alone(serving, tiles):
+    """NaN in one request's measured data: that request completes with
+    FPM_ENONFINITE, the requests around it complete as they would alone."""
+    import copy
+    t = tiles[0]
+    say("a request with NaN data among good ones")
+    bad_tile = copy.copy(t)
+    bad_tile.meas_amp = t.meas_amp.clone()
+    bad_tile.meas_amp[t.centre + 1, 5, 7] = float("nan")
+    torch.cuda.synchronize()
+    outs = [_outputs(t)[0] for _ in range(3)]
+    reqs = [serving.Request(t, seed=11, tag=0, O_out=outs[0]),
+            serving.Request(bad_tile, seed=12, tag=1, O_out=outs[1]),
+            serving.Request(t, seed=13, tag=2, O_out=outs[2])]
+    with serving.Server(lanes=2) as sv:
+        for r in reqs:
+            sv.submit(r)
+        sv.drain()
+        comps = {c.tag: c for c in sv.poll(0)}
+    assert comps[1].status == fpm.FPM_ENONFINITE
+    assert comps[0].status == 0 and comps[2].status == 0
+    for k in (0, 2):
+        st = _direct_solve(t, reqs[k])
+        np.testing.assert_array_equal(outs[k].cpu().numpy(), st.O.cpu().numpy())

@@ -42,10 +42,10 @@ TRAFFIC = {
     ("paper", "cols"): (4453.6 * 2 + 4843.4) * 1024,
     ("paper", "rows_backward"): (4460.8 * 2 + 2450.0) * 1024,
     ("paper", "update"): (7195.0 * 2 + 9658.3) * 1024,
-    ("large", "rows_forward"): (14828.8 * 2 + 39716.4) * 1024,
-    ("large", "cols"): (36173.9 * 2 + 39788.4) * 1024,
-    ("large", "rows_backward"): (34280.1 * 2 + 19665.9) * 1024,
-    ("large", "update"): (45575.6 * 2 + 57625.7) * 1024,
+    ("large", "rows_forward"): (14833.3 * 2 + 39716.4) * 1024,
+    ("large", "cols"): (36173.9 * 2 + 39796.8) * 1024,
+    ("large", "rows_backward"): (34245.7 * 2 + 19665.9) * 1024,
+    ("large", "update"): (47342.1 * 2 + 57625.8) * 1024,
 }
 
 

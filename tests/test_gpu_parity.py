@@ -430,11 +430,11 @@ def test_step_with_zernike_learning_matches_oracle(dev):
 
 def test_batches_above_64_run_in_groups_and_match_oracle(dev):
     """Batches of more than 64 LEDs (the full gradient of Eq. 6 over an 11x11 grid,
-    121 LEDs, and ragged batches of 100 + 21) run as groups of 64 whose gradient sums
+    121 LEDs, and ragged batches of 100 + 21 and 65 + 56) run as groups of 64 whose gradient sums
     are carried between launches: forward, loss and gradients, and a schedule of
     object + Zernike steps against the oracle; the steps are deterministic."""
     w = inputs.workload("small", n_side=11, learn_zernike=True)
-    say("batches above 64 LEDs: 121 (full gradient) and 100 + 21")
+    say("batches above 64 LEDs: 121 (full gradient), 100 + 21, 65 + 56")
     pr = oracle_problem(w, seed=4)
     plan = make_plan(w, pr.shifts, w.n_led)
     assert plan.info.max_batch == 121
@@ -452,10 +452,12 @@ def test_batches_above_64_run_in_groups_and_match_oracle(dev):
     assert rel_l2(gO, ref.g_O) <= GRAD_TOL
     assert rel_l2(gP[m], ref.g_P[m]) <= GRAD_TOL
     assert abs(loss - ref.loss) <= 1e-5 * ref.loss
-    # two epochs of full-gradient steps, then two epochs cut into batches of 100 + 21
-    perms = inputs.led_permutations(w.n_led, 4, seed=6)
-    batches = problem.schedule(perms[:2], w.n_led) + problem.schedule(perms[2:], 100)
-    assert [len(b) for b in batches] == [121, 121, 100, 21, 100, 21]
+    # two epochs of full-gradient steps, two cut into batches of 100 + 21, one
+    # into 65 + 56 (a last group of a single LED)
+    perms = inputs.led_permutations(w.n_led, 5, seed=6)
+    batches = (problem.schedule(perms[:2], w.n_led) + problem.schedule(perms[2:4], 100)
+               + problem.schedule(perms[4:], 65))
+    assert [len(b) for b in batches] == [121, 121, 100, 21, 100, 21, 65, 56]
     sched = problem.flatten_schedule(batches)
     hp = problem.hparams(w)
     outs = []

@@ -8,8 +8,9 @@
  *
  *  - A request is one complete solve: the initial value from one LED's
  *    amplitude (Sec. 2.3), then n_steps random-batch updates (Eq. 13) with the
- *    caller's schedule, exactly as fpm_init_spectrum + fpm_pupil + fpm_run on
- *    a fresh plan and state.
+ *    caller's schedule and loss (amplitude or intensity, Eqs. 4-5), exactly as
+ *    fpm_init_spectrum + fpm_pupil + fpm_plan_set_loss + fpm_run on a fresh
+ *    plan and state.
  *  - Continuous batching: up to n_lanes requests run at the same time, each on
  *    a lane with its own HIP stream, so their kernels overlap on the device.
  *    A request waiting in the queue is admitted as soon as a lane is idle and
@@ -74,6 +75,7 @@ typedef struct {
   float* coeffs_out;          /* DEVICE [15] or NULL: final Zernike coefficients */
   double* loss_out;           /* DEVICE [1] or NULL: loss summed over all steps */
   int64_t tag;                /* caller's id, returned in the completion record */
+  int32_t loss_kind;          /* FPM_LOSS_AMPLITUDE (0, the zero default) or FPM_LOSS_INTENSITY */
 } fpm_request;
 
 /* What happened to one request. Times are ms on the server's clock

@@ -248,6 +248,7 @@ int run_request(const Job& j, Slot* s, hipStream_t st, hipEvent_t ev) {
   if (hipMemsetAsync(s->m_O, 0, 2 * M * M * sizeof(fpm_c32), st) != hipSuccess ||
       hipMemsetAsync(s->small, 0, s->small_bytes, st) != hipSuccess)
     return serve_fail(FPM_EHIP, "hipMemsetAsync failed");
+  if (int rc = fpm_plan_set_loss(s->plan, r.loss_kind)) return serve_fail(rc, fpm_last_error());
   if (int rc = fpm_init_spectrum(s->plan, r.meas_amp + (size_t)r.centre_led * N * N, s->O, st))
     return serve_fail(rc, fpm_last_error());
   if (int rc = fpm_pupil(s->plan, s->coeffs, kZernTerms, s->z, s->P, st))
@@ -467,6 +468,8 @@ int fpm_server_submit(fpm_server* sv, const fpm_request* r) {
     if (r->centre_led < 0 || r->centre_led >= d.n_led)
       return serve_fail(FPM_EINVAL, "centre_led outside [0, n_led)");
     if (r->n_steps < 0) return serve_fail(FPM_EINVAL, "n_steps must be >= 0");
+    if (r->loss_kind != FPM_LOSS_AMPLITUDE && r->loss_kind != FPM_LOSS_INTENSITY)
+      return serve_fail(FPM_EINVAL, "loss_kind must be FPM_LOSS_AMPLITUDE or FPM_LOSS_INTENSITY");
     if (r->n_steps > 0 && (!r->leds || !r->batch_sizes))
       return serve_fail(FPM_EINVAL, "leds and batch_sizes must not be NULL");
     auto job = std::make_unique<Job>();

@@ -36,7 +36,8 @@ class _Request(C.Structure):
     _fields_ = [("desc", fpm._Desc), ("shifts_host", C.c_void_p), ("meas_amp", C.c_void_p),
                 ("centre_led", C.c_int32), ("hp", fpm._HParams), ("leds", C.c_void_p),
                 ("batch_sizes", C.c_void_p), ("n_steps", C.c_int32), ("O_out", C.c_void_p),
-                ("coeffs_out", C.c_void_p), ("loss_out", C.c_void_p), ("tag", C.c_int64)]
+                ("coeffs_out", C.c_void_p), ("loss_out", C.c_void_p), ("tag", C.c_int64),
+                ("loss_kind", C.c_int32)]
 
 
 class _Completion(C.Structure):
@@ -182,8 +183,10 @@ class Request:
     """One solve of a tile: its schedule (seeded), output buffers and C struct."""
 
     def __init__(self, tile: Tile, seed: int, tag: int, O_out=None, coeffs_out=None,
-                 loss_out=None):
+                 loss_out=None, loss: str = "amplitude"):
         w = tile.w
+        if loss not in fpm.Plan.LOSSES:
+            raise fpm.FpmError(f"unknown loss {loss!r}")
         perms = inputs.led_permutations(w.n_led, w.epochs, seed=int(seed))
         sched = problem.flatten_schedule(problem.schedule(perms, w.batch))
         self.tile = tile
@@ -200,7 +203,8 @@ class Request:
                           tile.centre, tile.hp.c(), self.leds.ctypes.data,
                           self.sizes.ctypes.data, int(self.sizes.size), self.O_out.data_ptr(),
                           None if coeffs_out is None else coeffs_out.data_ptr(),
-                          None if loss_out is None else loss_out.data_ptr(), int(tag))
+                          None if loss_out is None else loss_out.data_ptr(), int(tag),
+                          fpm.Plan.LOSSES[loss])
 
 
 def make_tiles(device="cuda", seed: int = 0):

@@ -26,6 +26,7 @@ int fpm_plan_set_shifts(fpm_plan* p, const int32_t* sh, void*) {
   return 0;
 }
 int fpm_plan_destroy(fpm_plan* p) { delete p; return 0; }
+int fpm_plan_set_loss(fpm_plan*, int32_t kind) { return kind == 0 || kind == 1 ? 0 : -1; }
 int fpm_plan_info(const fpm_plan* p, fpm_info* i) { i->device_bytes = 1000 * p->d.n_lr; return 0; }
 int fpm_init_spectrum(fpm_plan*, const float*, fpm_c32* O, void*) { O[0].re = 1; return 0; }
 int fpm_pupil(fpm_plan*, const float*, int32_t, const float*, fpm_c32*, void*) { return 0; }

@@ -60,6 +60,9 @@ int main() {
   bad.centre_led = 99;
   CHECK(fpm_server_submit(sv, &bad) == FPM_EINVAL);
   bad.centre_led = 0;
+  bad.loss_kind = 7;   // neither loss
+  CHECK(fpm_server_submit(sv, &bad) == FPM_EINVAL);
+  bad.loss_kind = 0;
   bad.n_steps = 1;
   bad.leds = leds.data();
   int32_t big_batch = 5;   // > max_batch

@@ -169,3 +169,34 @@ def test_non_finite_request_fails_alone(serving, tiles):
     for k in (0, 2):
         st = _direct_solve(t, reqs[k])
         np.testing.assert_array_equal(outs[k].cpu().numpy(), st.O.cpu().numpy())
+
+
+def test_intensity_loss_request_equals_a_direct_solve(serving, tiles):
+    """A request with the intensity loss (Eq. 4) equals fpm_run with that loss;
+    the next request on the same slot uses the amplitude loss again."""
+    t = tiles[0]
+    say("intensity-loss request, then an amplitude one on the same slot")
+    O_i, _, l_i = _outputs(t)
+    O_a, _, l_a = _outputs(t)
+    reqs = [serving.Request(t, seed=21, tag=0, O_out=O_i, loss_out=l_i, loss="intensity"),
+            serving.Request(t, seed=22, tag=1, O_out=O_a, loss_out=l_a)]
+    with serving.Server(lanes=1) as sv:
+        for r in reqs:
+            sv.submit(r)
+        sv.drain()
+        comps = {c.tag: c for c in sv.poll(0)}
+        assert sv.stats()["slots"] == 1
+    assert comps[0].status == 0 and comps[1].status == 0
+    for req, O_out, l_out, loss in ((reqs[0], O_i, l_i, "intensity"),
+                                    (reqs[1], O_a, l_a, "amplitude")):
+        w = t.w
+        plan = fpm.Plan(w.n_lr, w.upsample, t.shifts, w.batch, w.wavelength_um, w.na, w.mag,
+                        w.pixel_um)
+        plan.set_loss(loss)
+        st = fpm.State(plan, plan.init_spectrum(t.meas_amp[t.centre].contiguous()))
+        plan.run(st, t.hp, req.leds, req.sizes, t.meas_amp)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(O_out.cpu().numpy(), st.O.cpu().numpy())
+        np.testing.assert_array_equal(l_out.cpu().numpy(), st.loss.cpu().numpy())
+    with pytest.raises(fpm.FpmError):
+        serving.Request(t, seed=1, tag=2, loss="l1")

@@ -76,6 +76,16 @@ typedef struct {
   double* loss_out;           /* DEVICE [1] or NULL: loss summed over all steps */
   int64_t tag;                /* caller's id, returned in the completion record */
   int32_t loss_kind;          /* FPM_LOSS_AMPLITUDE (0, the zero default) or FPM_LOSS_INTENSITY */
+  /* Multi-parameter solve (NULL grid: the nearest-pixel solve above). With a
+     HOST grid (copied; n_side^2 == n_led, every batch <= 64 LEDs) the request
+     runs fpm_run_multi instead of fpm_run: sub-pixel offsets from the grid
+     plus the learned LED-array errors (starting from zero), learned with Adam
+     at these rates when learn_geometry, besides the spectrum and the pupil
+     parameters hp asks for. */
+  const fpm_led_grid* grid;
+  double lr_shift_mm, lr_rot_rad, lr_height_mm;
+  int32_t learn_geometry;
+  double* geom_out;           /* DEVICE [4] or NULL: final shift_x, shift_y, rot, dh errors */
 } fpm_request;
 
 /* What happened to one request. Times are ms on the server's clock

@@ -59,15 +59,17 @@ struct Slot {
   float *coeffs = nullptr, *m_c = nullptr, *v_c = nullptr, *z = nullptr, *m_z = nullptr,
         *v_z = nullptr;
   double *g_par = nullptr, *loss = nullptr;
+  double *geom = nullptr, *m_geom = nullptr, *v_geom = nullptr;
   void* small = nullptr;
   size_t small_bytes = 0;
   int64_t footprint = 0;
   bool busy = false;
 };
 
-// Small block: 6 x 16 floats (coeffs, m_c, v_c, z, m_z, v_z), then 16 + 1 doubles.
+// Small block: 6 x 16 floats (coeffs, m_c, v_c, z, m_z, v_z), then 16 + 1
+// doubles (g_par, loss), then 3 x 4 doubles (LED-array geometry and its moments).
 constexpr size_t kSmallFloats = 6 * 16;
-constexpr size_t kSmallBytes = kSmallFloats * sizeof(float) + 17 * sizeof(double);
+constexpr size_t kSmallBytes = kSmallFloats * sizeof(float) + (17 + 12) * sizeof(double);
 
 int64_t state_bytes(const fpm_desc& d) {
   const int64_t M = (int64_t)d.n_lr * d.upsample, N = d.n_lr;
@@ -78,6 +80,8 @@ int64_t data_bytes(const fpm_desc& d) { return (int64_t)d.n_led * d.n_lr * d.n_l
 
 struct Job {
   fpm_request req{};
+  bool multi = false;          // fused multi-parameter solve on `grid`
+  fpm_led_grid grid{};
   ShapeKey key;
   std::vector<int32_t> shifts, leds, sizes;
   int64_t footprint = 0;
@@ -180,6 +184,9 @@ int slot_create(const ShapeKey& key, const std::vector<int32_t>& shifts,
   s->v_z = f + 80;
   s->g_par = reinterpret_cast<double*>(f + kSmallFloats);
   s->loss = s->g_par + 16;
+  s->geom = s->loss + 1;
+  s->m_geom = s->geom + 4;
+  s->v_geom = s->geom + 8;
   s->small_bytes = kSmallBytes;
   s->footprint = state_bytes(key.desc) + info.device_bytes + data_bytes(key.desc);
   out = std::move(s);
@@ -267,7 +274,19 @@ int run_request(const Job& j, Slot* s, hipStream_t st, hipEvent_t ev) {
   state.g_par = s->g_par;
   state.loss = s->loss;
   state.t = 0;
-  if (r.n_steps > 0) {
+  if (r.n_steps > 0 && j.multi) {
+    fpm_geometry geo{};
+    geo.geom = s->geom;
+    geo.m_geom = s->m_geom;
+    geo.v_geom = s->v_geom;
+    geo.lr_shift_mm = r.lr_shift_mm;
+    geo.lr_rot_rad = r.lr_rot_rad;
+    geo.lr_height_mm = r.lr_height_mm;
+    geo.learn = r.learn_geometry;
+    if (int rc = fpm_run_multi(s->plan, &j.grid, &state, &geo, &r.hp, j.leds.data(),
+                               j.sizes.data(), r.n_steps, r.meas_amp, st))
+      return serve_fail(rc, fpm_last_error());
+  } else if (r.n_steps > 0) {
     if (int rc = fpm_run(s->plan, &state, &r.hp, j.leds.data(), j.sizes.data(), r.n_steps,
                          nullptr, r.meas_amp, st))
       return serve_fail(rc, fpm_last_error());
@@ -281,6 +300,9 @@ int run_request(const Job& j, Slot* s, hipStream_t st, hipEvent_t ev) {
   if (r.loss_out && hipMemcpyAsync(r.loss_out, s->loss, sizeof(double), hipMemcpyDeviceToDevice,
                                    st) != hipSuccess)
     return serve_fail(FPM_EHIP, "loss copy failed");
+  if (r.geom_out && hipMemcpyAsync(r.geom_out, s->geom, 4 * sizeof(double),
+                                   hipMemcpyDeviceToDevice, st) != hipSuccess)
+    return serve_fail(FPM_EHIP, "geometry copy failed");
   double loss = 0.0;   // the summed loss, for the non-finite guard
   if (hipMemcpyAsync(&loss, s->loss, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess)
     return serve_fail(FPM_EHIP, "loss read-back failed");
@@ -470,6 +492,8 @@ int fpm_server_submit(fpm_server* sv, const fpm_request* r) {
     if (r->n_steps < 0) return serve_fail(FPM_EINVAL, "n_steps must be >= 0");
     if (r->loss_kind != FPM_LOSS_AMPLITUDE && r->loss_kind != FPM_LOSS_INTENSITY)
       return serve_fail(FPM_EINVAL, "loss_kind must be FPM_LOSS_AMPLITUDE or FPM_LOSS_INTENSITY");
+    if (r->grid && r->grid->n_side * r->grid->n_side != d.n_led)
+      return serve_fail(FPM_EINVAL, "grid->n_side^2 must equal n_led");
     if (r->n_steps > 0 && (!r->leds || !r->batch_sizes))
       return serve_fail(FPM_EINVAL, "leds and batch_sizes must not be NULL");
     auto job = std::make_unique<Job>();
@@ -481,6 +505,8 @@ int fpm_server_submit(fpm_server* sv, const fpm_request* r) {
       const int b = r->batch_sizes[i];
       if (b < 1 || b > d.max_batch)
         return serve_fail(FPM_EINVAL, "batch sizes must be in [1, max_batch]");
+      if (r->grid && b > 64)
+        return serve_fail(FPM_EINVAL, "a multi-parameter request takes at most 64 LEDs per batch");
       total += (size_t)b;
     }
     for (size_t i = 0; i < total; ++i)
@@ -490,7 +516,12 @@ int fpm_server_submit(fpm_server* sv, const fpm_request* r) {
       job->leds.assign(r->leds, r->leds + total);
       job->sizes.assign(r->batch_sizes, r->batch_sizes + r->n_steps);
     }
+    if (r->grid) {
+      job->multi = true;
+      job->grid = *r->grid;
+    }
     // the copies own the host arrays from here on
+    job->req.grid = nullptr;
     job->req.shifts_host = nullptr;
     job->req.leds = nullptr;
     job->req.batch_sizes = nullptr;

@@ -37,7 +37,9 @@ class _Request(C.Structure):
                 ("centre_led", C.c_int32), ("hp", fpm._HParams), ("leds", C.c_void_p),
                 ("batch_sizes", C.c_void_p), ("n_steps", C.c_int32), ("O_out", C.c_void_p),
                 ("coeffs_out", C.c_void_p), ("loss_out", C.c_void_p), ("tag", C.c_int64),
-                ("loss_kind", C.c_int32)]
+                ("loss_kind", C.c_int32), ("grid", C.c_void_p), ("lr_shift_mm", C.c_double),
+                ("lr_rot_rad", C.c_double), ("lr_height_mm", C.c_double),
+                ("learn_geometry", C.c_int32), ("geom_out", C.c_void_p)]
 
 
 class _Completion(C.Structure):
@@ -183,7 +185,11 @@ class Request:
     """One solve of a tile: its schedule (seeded), output buffers and C struct."""
 
     def __init__(self, tile: Tile, seed: int, tag: int, O_out=None, coeffs_out=None,
-                 loss_out=None, loss: str = "amplitude"):
+                 loss_out=None, loss: str = "amplitude", grid=None, geometry_lr=(5e-3, 5e-4, 2e-2),
+                 learn_geometry: bool = True, geom_out=None):
+        """grid (an fpm.LedGrid): the multi-parameter solve (fpm_run_multi) with the
+        LED-array errors learned from zero at geometry_lr (shift mm, rotation rad,
+        height mm) when learn_geometry; geom_out receives them (float64 [4])."""
         w = tile.w
         if loss not in fpm.Plan.LOSSES:
             raise fpm.FpmError(f"unknown loss {loss!r}")
@@ -199,12 +205,19 @@ class Request:
         fpm._need(self.O_out, "O_out", torch.complex64, (w.m_hr, w.m_hr))
         fpm._need(coeffs_out, "coeffs_out", torch.float32, (fpm.N_ZERN,), optional=True)
         fpm._need(loss_out, "loss_out", torch.float64, (1,), optional=True)
+        fpm._need(geom_out, "geom_out", torch.float64, (4,), optional=True)
+        self.geom_out = geom_out
+        self._grid_c = None if grid is None else grid.c()   # copied by the server at submit
         self.c = _Request(tile.desc, tile.shifts.ctypes.data, tile.meas_amp.data_ptr(),
                           tile.centre, tile.hp.c(), self.leds.ctypes.data,
                           self.sizes.ctypes.data, int(self.sizes.size), self.O_out.data_ptr(),
                           None if coeffs_out is None else coeffs_out.data_ptr(),
                           None if loss_out is None else loss_out.data_ptr(), int(tag),
-                          fpm.Plan.LOSSES[loss])
+                          fpm.Plan.LOSSES[loss],
+                          None if grid is None else C.addressof(self._grid_c),
+                          float(geometry_lr[0]), float(geometry_lr[1]), float(geometry_lr[2]),
+                          int(bool(learn_geometry)),
+                          None if geom_out is None else geom_out.data_ptr())
 
 
 def make_tiles(device="cuda", seed: int = 0):

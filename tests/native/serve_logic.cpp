@@ -211,6 +211,36 @@ int main() {
     for (int i = 0; i < 6; ++i) CHECK(i == 3 ? std::isnan(loss[i]) : loss[i] == 2.0);
     CHECK(fpm_server_destroy(s3) == FPM_OK);
   }
+  // a multi-parameter request (with a grid) runs fpm_run_multi and returns its geometry
+  {
+    fpm_server_desc one{1, 8 * fp};
+    fpm_server* s4 = nullptr;
+    CHECK(fpm_server_create(&one, &s4) == FPM_OK);
+    fpm_led_grid g{};
+    g.n_side = 3;
+    std::vector<double> geom_out(4, -1.0);
+    fpm_request r{};
+    r.desc = d;
+    r.shifts_host = shifts.data();
+    r.meas_amp = amp.data();
+    r.centre_led = 4;
+    r.leds = leds.data();
+    r.batch_sizes = sizes.data();
+    r.n_steps = 3;
+    r.O_out = outs[0].data();
+    r.loss_out = &loss[0];
+    r.grid = &g;
+    r.geom_out = geom_out.data();
+    r.tag = 400;
+    CHECK(fpm_server_submit(s4, &r) == FPM_OK);
+    g.n_side = 5;   // the grid was copied at submit
+    fpm_request bad2 = r;
+    bad2.grid = &g;   // 5 x 5 LEDs for a 9-LED table
+    CHECK(fpm_server_submit(s4, &bad2) == FPM_EINVAL);
+    CHECK(fpm_server_drain(s4) == FPM_OK);
+    CHECK(loss[0] == 1003.0 && geom_out[0] == 3.0);
+    CHECK(fpm_server_destroy(s4) == FPM_OK);
+  }
   std::printf("OK\n");
   return 0;
 }

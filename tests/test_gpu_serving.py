@@ -200,3 +200,33 @@ def test_intensity_loss_request_equals_a_direct_solve(serving, tiles):
         np.testing.assert_array_equal(l_out.cpu().numpy(), st.loss.cpu().numpy())
     with pytest.raises(fpm.FpmError):
         serving.Request(t, seed=1, tag=2, loss="l1")
+
+
+def test_multi_parameter_request_equals_a_direct_fused_solve(serving):
+    """A request with an LED grid runs the fused multi-parameter solve (LED-array
+    geometry, Zernikes, defocus learned) and equals fpm_run_multi bitwise,
+    geometry included."""
+    w = inputs.workload("multiparam")
+    say("multi-parameter request (geometry learned)")
+    t = serving.Tile(w, seed=3)
+    grid = fpm.LedGrid(w.n_side, w.pitch_mm, w.height_mm)
+    lr = (w.lr_shift, w.lr_rot, w.lr_height)
+    O_s, _, l_s = _outputs(t)
+    g_s = torch.zeros(4, dtype=torch.float64, device="cuda")
+    req = serving.Request(t, seed=4, tag=0, O_out=O_s, loss_out=l_s, grid=grid,
+                          geometry_lr=lr, geom_out=g_s)
+    with serving.Server(lanes=2) as sv:
+        sv.submit(req)
+        sv.drain()
+        comps = sv.poll(0)
+    assert len(comps) == 1 and comps[0].status == 0
+    plan = fpm.Plan(w.n_lr, w.upsample, t.shifts, w.batch, w.wavelength_um, w.na, w.mag,
+                    w.pixel_um)
+    st = fpm.State(plan, plan.init_spectrum(t.meas_amp[t.centre].contiguous()))
+    geo = fpm.Geometry(lr_shift_mm=lr[0], lr_rot_rad=lr[1], lr_height_mm=lr[2])
+    plan.run_multi(grid, st, geo, t.hp, req.leds, req.sizes, t.meas_amp)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(O_s.cpu().numpy(), st.O.cpu().numpy())
+    np.testing.assert_array_equal(l_s.cpu().numpy(), st.loss.cpu().numpy())
+    np.testing.assert_array_equal(g_s.cpu().numpy(), geo.geom.cpu().numpy())
+    assert np.any(g_s.cpu().numpy() != 0.0)

@@ -91,7 +91,7 @@ typedef struct {
   int32_t n_lr, m_hr, n_led, max_batch;
   int32_t support_px;      /* |S|: pixels of the pupil disk */
   int32_t support_rows;    /* rows of the pupil grid that meet the disk */
-  int32_t adam_tiles;      /* 32 x 32 HR tiles covering the union of windows */
+  int32_t adam_tiles;      /* 32 x 32 HR tiles of the rectangle bounding the union of windows */
   double pupil_radius_px;  /* NA / lambda / dk */
   double dk;               /* spectral pitch, 1/um */
   int64_t device_bytes;    /* device memory the plan holds (its scratch and tables) */
@@ -109,9 +109,10 @@ int fpm_plan_destroy(fpm_plan* plan);
  * Replace the plan's LED table (same n_led; HOST int32 [n_led][2], copied),
  * e.g. for another tile of the field of view, whose illumination angles
  * differ (Sec. 2.1 k_m with the tile centre as the sample point). Windows are
- * validated as in fpm_plan_create (FPM_EINVAL, nothing changed). Waits for
- * `stream`, then enqueues the upload of the new Adam tile list on it; calls
- * on the plan after this one (on that stream) use the new table.
+ * validated as in fpm_plan_create (FPM_EINVAL, nothing changed). Nothing is
+ * uploaded (the table and the Adam tile rectangle travel in the launch
+ * arguments), so launches already enqueued keep the old table and calls on the
+ * plan after this one use the new one; `stream` is not used and may be NULL.
  */
 int fpm_plan_set_shifts(fpm_plan* plan, const int32_t* shifts_host, void* stream);
 

@@ -285,13 +285,22 @@ template <int N> struct RowLds {
   __device__ __forceinline__ static int at(int n) { return n + (n >> 4); }
 };
 
-// Copy the twiddle table into LDS (call at kernel start, before the first
-// transform; the first stage needs no twiddles and its exchange barrier
-// orders these writes before any twiddle read).
-template <int N>
-__device__ __forceinline__ void stage_twiddles(float2* __restrict__ lds_tw,
-                                               const float2* __restrict__ tw) {
-  for (int i = threadIdx.x; i < N; i += blockDim.x) lds_tw[i] = tw[i];
+// Copy the twiddle table into LDS, by a workgroup of exactly kThreads threads
+// (call before the first transform; the first stage needs no twiddles and its
+// exchange barrier orders these writes before any twiddle read). Unrolled and
+// without a branch (threads past the table copy its last entry again, the same
+// value to the same slot), and called after the kernel's first data loads:
+// the twiddle loads then join them in flight, where a loop or a branch would
+// end the scheduling region and the data loads would wait for the twiddles.
+template <int N, int kThreads>
+__device__ __forceinline__ void stage_twiddles_after_loads(float2* __restrict__ lds_tw,
+                                                           const float2* __restrict__ tw) {
+  constexpr int K = (N + kThreads - 1) / kThreads;
+  float2 r[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) r[k] = tw[min((int)threadIdx.x + k * kThreads, N - 1)];
+#pragma unroll
+  for (int k = 0; k < K; ++k) lds_tw[min((int)threadIdx.x + k * kThreads, N - 1)] = r[k];
 }
 
 // Radix plans: stage radices for a transform of length N done by T threads.

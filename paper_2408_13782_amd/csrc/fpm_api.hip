@@ -2,6 +2,8 @@
 // The C ABI is declared in include/fpm.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <climits>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -131,7 +133,9 @@ struct fpm_plan {
   int N = 0, s = 0, M = 0, n_led = 0, max_batch = 0;
   double lambda = 0, na = 0, mag = 0, pixel = 0, dk = 0, radius = 0;
   int ky_lo = 0, ky_hi = -1, nrows = 0, support_px = 0;
-  int n_tiles = 0;
+  int n_tiles = 0;            // tiles of the Adam rectangle
+  int2 tile0 = {0, 0};        // its first tile (row, column), in 32 x 32 HR tiles
+  int tile_cols = 0;          // its width in tiles
   bool hr_ok = false;
   size_t device_bytes = 0;    // everything the plan allocated
   std::vector<int2> shifts_h;
@@ -142,8 +146,6 @@ struct fpm_plan {
   float2* gacc = nullptr;     // [M][M] gradient sums of a batch's earlier groups (max_batch > kMaxSlots)
   float2* gP = nullptr;       // [N][N] pupil-gradient accumulator for fpm_step
   float* kappa_tab = nullptr;  // defocus phase per um at integer |u|^2 <= R^2
-  int2* tiles = nullptr;      // [n_tiles] 32 x 32 HR tiles covered by some window
-  std::vector<int2> tiles_h;  // host copy, the source of fpm_plan_set_shifts' upload
   std::vector<int2> rowext_h; // host copy of rowext
   double* part = nullptr;     // per-workgroup partial sums (loss | Zernike | pupil_grad)
   double* part_loss = nullptr;
@@ -218,7 +220,6 @@ void plan_free(fpm_plan* p) {
   (void)hipFree(p->gacc);
   (void)hipFree(p->gP);
   (void)hipFree(p->kappa_tab);
-  (void)hipFree(p->tiles);
   (void)hipFree(p->part);
   (void)hipFree(p->staging);
   (void)hipFree(p->part_lg);
@@ -279,10 +280,13 @@ Batch batch_of(const fpm_plan* p, const int32_t* leds, int B) {
   return bt;
 }
 
-// Validate an LED table (every window inside the HR grid) and list the 32 x 32
-// HR tiles covered by the pupil disk of some window (Adam runs over these).
-int led_table(const fpm_plan* p, const int32_t* shifts_host, std::vector<int2>& shifts,
-              std::vector<int2>& tiles) {
+// Validate an LED table (every window inside the HR grid) and find the
+// rectangle of 32 x 32 HR tiles that bounds the tiles covered by the pupil disk
+// of some window (Adam runs over this rectangle: outside the disks the
+// gradient and both moments stay zero, so Adam leaves the spectrum there as
+// it is, and a workgroup finds its tile from its index alone).
+int led_table(fpm_plan* p, const int32_t* shifts_host, std::vector<int2>& shifts,
+              int2& tile0, int& tile_rows, int& tile_cols) {
   const int base = p->M / 2 - p->N / 2;
   shifts.assign(p->n_led, make_int2(0, 0));
   for (int i = 0; i < p->n_led; ++i) {
@@ -295,20 +299,25 @@ int led_table(const fpm_plan* p, const int32_t* shifts_host, std::vector<int2>& 
     }
     shifts[i] = make_int2(sr, sc);
   }
-  const int nt = (p->M + 31) / 32;
-  std::vector<uint8_t> cover((size_t)nt * nt, 0);
+  int r0 = INT_MAX, r1 = -1, c0 = INT_MAX, c1 = -1;
   for (int i = 0; i < p->n_led; ++i) {
     const int2 s = shifts[i];
     for (int ky = p->ky_lo; ky <= p->ky_hi; ++ky) {
-      const int row = base + s.x + ky;
-      const int c0 = base + s.y + p->rowext_h[ky].x, c1 = base + s.y + p->rowext_h[ky].y;
-      for (int tc = c0 / 32; tc <= c1 / 32; ++tc) cover[(size_t)(row / 32) * nt + tc] = 1;
+      const int row = (base + s.x + ky) / 32;
+      r0 = std::min(r0, row);
+      r1 = std::max(r1, row);
+      c0 = std::min(c0, (base + s.y + p->rowext_h[ky].x) / 32);
+      c1 = std::max(c1, (base + s.y + p->rowext_h[ky].y) / 32);
     }
   }
-  tiles.clear();
-  for (int tr = 0; tr < nt; ++tr)
-    for (int tc = 0; tc < nt; ++tc)
-      if (cover[(size_t)tr * nt + tc]) tiles.push_back(make_int2(tr, tc));
+  if (r1 < 0) {   // no LED (or no disk row): no tile
+    tile0 = make_int2(0, 0);
+    tile_rows = tile_cols = 0;
+    return FPM_OK;
+  }
+  tile0 = make_int2(r0, c0);
+  tile_rows = r1 - r0 + 1;
+  tile_cols = c1 - c0 + 1;
   return FPM_OK;
 }
 
@@ -317,12 +326,6 @@ size_t tile_capacity(const fpm_plan* p) {
   return nt * nt;
 }
 
-// Synchronous upload of a tile list (plan creation).
-int copy_tiles(fpm_plan* p, const std::vector<int2>& tiles) {
-  if (!tiles.empty())
-    FPM_HIP(hipMemcpy(p->tiles, tiles.data(), tiles.size() * sizeof(int2), hipMemcpyHostToDevice));
-  return FPM_OK;
-}
 
 Disk disk_of(const fpm_plan* p) {
   Disk d;
@@ -756,15 +759,14 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
         ++p->nrows;
       }
     }
-    // LED table and the HR tiles its windows touch
-    std::vector<int2> tiles;
+    // LED table and the rectangle of HR tiles its windows touch
     p->rowext_h = ext;
-    if (int rc = led_table(p, shifts_host, p->shifts_h, tiles)) {
+    int tile_rows = 0;
+    if (int rc = led_table(p, shifts_host, p->shifts_h, p->tile0, tile_rows, p->tile_cols)) {
       delete p;
       return rc;
     }
-    p->n_tiles = (int)tiles.size();
-    p->tiles_h = tiles;
+    p->n_tiles = tile_rows * p->tile_cols;
     p->hr_ok = hr_supported(p->M);
 
     // kappa(|u|^2) = 2 pi (sqrt(1/l^2 - k^2) - 1/l), k^2 = |u|^2 dk^2, cancellation-free form
@@ -782,9 +784,7 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
         (p->max_batch > kMaxSlots &&
          (rc = upload<float2>(&p->device_bytes, &p->gacc, nullptr, (size_t)p->M * p->M))) ||
         (rc = upload<float2>(&p->device_bytes, &p->gP, nullptr, (size_t)p->N * p->N)) ||
-        (rc = upload(&p->device_bytes, &p->kappa_tab, kap.data(), kap.size())) ||
-        (rc = upload<int2>(&p->device_bytes, &p->tiles, nullptr, tile_capacity(p))) ||
-        (rc = copy_tiles(p, tiles))) {
+        (rc = upload(&p->device_bytes, &p->kappa_tab, kap.data(), kap.size()))) {
       plan_free(p);
       return rc;
     }
@@ -840,17 +840,15 @@ int fpm_plan_set_shifts(fpm_plan* p, const int32_t* shifts_host, void* stream) {
   return guarded([&]() -> int {
     FPM_REQUIRE(p && shifts_host, "plan and shifts_host must not be NULL");
     if (int rc = check_device(p)) return rc;
-    std::vector<int2> shifts, tiles;
-    if (int rc = led_table(p, shifts_host, shifts, tiles)) return rc;
-    hipStream_t st = (hipStream_t)stream;
-    // the previous upload from tiles_h must have completed before it is replaced
-    FPM_HIP(hipStreamSynchronize(st));
+    std::vector<int2> shifts;
+    int2 tile0;
+    int tile_rows = 0, tile_cols = 0;
+    if (int rc = led_table(p, shifts_host, shifts, tile0, tile_rows, tile_cols)) return rc;
+    (void)stream;   // nothing is uploaded: the table and the rectangle are launch arguments
     p->shifts_h = std::move(shifts);
-    p->tiles_h = std::move(tiles);
-    p->n_tiles = (int)p->tiles_h.size();
-    if (p->n_tiles > 0)
-      FPM_HIP(hipMemcpyAsync(p->tiles, p->tiles_h.data(), p->tiles_h.size() * sizeof(int2),
-                             hipMemcpyHostToDevice, st));
+    p->tile0 = tile0;
+    p->tile_cols = tile_cols;
+    p->n_tiles = tile_rows * tile_cols;
     return FPM_OK;
   });
 }
@@ -1043,8 +1041,8 @@ int step_launches(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_
     a.bt = batch_of(p, leds + gr.b0, gr.B);
     a.dk = disk_of(p);
     a.n = p->N;
-    a.tiles = p->tiles;
-    a.n_tiles = p->n_tiles;
+    a.tile0 = p->tile0;
+    a.tile_cols = p->tile_cols;
     a.M = p->M;
     a.gacc = reinterpret_cast<float*>(p->gacc);
     a.acc_in = g > 0;

@@ -104,7 +104,7 @@ struct ScalarAdam {
 //  group's launch starts its sums from g_acc (acc_in) and applies Adam. The
 //  additions then happen in batch order, as in a single pass.
 struct UpdateArgs {
-  const int2* tiles; int n_tiles; int M;
+  int2 tile0; int tile_cols; int M;   // the rectangle of tiles: first tile, width
   float* O; float* mO; float* vO;
   float* gacc; int acc_in, acc_out;
   AdamCoef c;
@@ -232,7 +232,9 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
   FPM_PROBE(3, 0);
   const int n_pw = a.pupil ? pupil_wg_slots(N, a.dk.nrows) : 1;
   if ((int)blockIdx.x >= n_pw) {
-    const int2 tl = a.tiles[blockIdx.x - n_pw];
+    const int i = blockIdx.x - n_pw;
+    const int tr = i / a.tile_cols;
+    const int2 tl = make_int2(a.tile0.x + tr, a.tile0.y + (i - tr * a.tile_cols));
     const int r = tl.x * 32 + (threadIdx.x >> 3);
     const int col = tl.y * 32 + (threadIdx.x & 7) * 2;         // complex column
     const size_t f = ((size_t)r * a.M + col) * 2;                // float offset

@@ -410,7 +410,6 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch b
   if (commit && blockIdx.x == 0) commit_scalars(staging, scal, threadIdx.x);
   int b, c;
   if (!xcd_map(blockIdx.x, chunks, bt.B, b, c)) return;
-  stage_twiddles<N>(lds_tw, tw);
   const int line = threadIdx.x / T;
   const int t = threadIdx.x % T;
   const int rr = c * L + line;
@@ -430,6 +429,7 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch b
     ov[m] = orow[kx];
     pvv[m] = prow[kx];
   }
+  stage_twiddles_after_loads<N, kRowThreads>(lds_tw, tw);
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
@@ -464,7 +464,6 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
   if (!kForward) FPM_PROBE(1, 0);
   int b, g;
   const bool live = xcd_map(blockIdx.x, groups, bt.B, b, g);
-  if (live) stage_twiddles<N>(lds_tw, tw);
   const int line = threadIdx.x % L;
   const int t = threadIdx.x / L;
   const int x = g * L + line;
@@ -484,6 +483,7 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
 #pragma unroll
       for (int m = 0; m < E; ++m) a_meas[m] = ab[(size_t)(t + m * T) * N + x];   // prefetch
     }
+    stage_twiddles_after_loads<N, L * T>(lds_tw, tw);
     const float sg = gamma ? sqrtf(gamma[led]) : 1.0f;
     auto lay = [line](int n) { return n * ColStride<N>::value + line; };
     if (!kForward) FPM_PROBE(1, 1);
@@ -572,7 +572,6 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
   FPM_PROBE(2, 0);
   int b, c;
   const bool live = xcd_map(blockIdx.x, chunks, bt.B, b, c);
-  if (live) stage_twiddles<N>(lds_tw, tw);
   const int line = threadIdx.x / T;
   const int t = threadIdx.x % T;
   const int rr = c * L + line;
@@ -602,6 +601,7 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
         kap[m] = kappa_tab[ux * ux + uy * uy];
       }
     }
+    stage_twiddles_after_loads<N, kRowThreads>(lds_tw, tw);
     FPM_PROBE(2, 1);
     RowPlan<N>::template run<-1>(v, t, lds + line * RowLds<N>::kStride, [](int n) { return RowLds<N>::at(n); }, lds_tw);
     FPM_PROBE(2, 2);

@@ -131,7 +131,6 @@ rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Bat
   int b, c;
   if (!xcd_map(blockIdx.x, chunks, bt.B, b, c)) return;
   FPM_PROBE(0, 0);
-  stage_twiddles<N>(lds_tw, tw);
   const int line = threadIdx.x / T, t = threadIdx.x % T;
   const int rr = c * L + line;
   const bool active = rr < dk.nrows;
@@ -143,6 +142,7 @@ rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Bat
     if (clamped && oob) atomicAdd(oob, 1);
     sub_out[b] = sl;   // for the later kernels of the call
   }
+  stage_twiddles_after_loads<N, kRowThreads>(lds_tw, tw);   // in flight with the geometry
   const float2* prow = P + (size_t)ky * N;
   float2 v[E];
 #pragma unroll
@@ -181,7 +181,6 @@ rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
   int b, c;
   const bool live = xcd_map(blockIdx.x, chunks, bt.B, b, c);
   FPM_PROBE(2, 0);
-  if (live) stage_twiddles<N>(lds_tw, tw);
   const int line = threadIdx.x / T, t = threadIdx.x % T;
   const int rr = c * L + line;
   const bool active = rr < dk.nrows;
@@ -197,6 +196,7 @@ rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = xr[t + m * T];
+    stage_twiddles_after_loads<N, kRowThreads>(lds_tw, tw);
     RowPlan<N>::template run<-1>(v, t, lds + line * RowLds<N>::kStride,
                                 [](int n) { return RowLds<N>::at(n); }, lds_tw);
     if (active) {

@@ -96,8 +96,9 @@ struct ScalarAdam {
 //    Zernike/defocus partials of the row pass in a fixed order, applies Adam
 //    to the 16 pupil parameters (all of them compute the same numbers), and
 //    rebuilds its share of the pupil from the new parameters; workgroup 0 of
-//    them stages the new parameter state, adds the gradients to g_par, and
-//    adds the batch loss (summed from the column pass's partials) to *loss.
+//    them stages the new parameter state and adds the gradients to g_par;
+//  the workgroup after them (workgroup 0 without `pupil`): adds the batch
+//    loss (summed from the column pass's partials) to *loss.
 //  Batches of more than kMaxSlots LEDs are processed in groups: for every
 //  group but the last the kernel only accumulates (acc_out: g_acc = the
 //  group's gathered sum, started from g_acc when acc_in, no Adam); the last
@@ -124,11 +125,37 @@ __host__ __device__ constexpr int pupil_rows_per_wg(int n) { return n <= 64 ? 8 
 __host__ __device__ constexpr int pupil_wg_count(int n, int disk_rows) {
   return (disk_rows + pupil_rows_per_wg(n) - 1) / pupil_rows_per_wg(n);
 }
-// Workgroup slots given to them: a multiple of the 8 XCDs, so that HR tile t
-// (workgroup pupil_wg_slots + t) runs on XCD t mod 8 whatever the pupil size;
-// the padding workgroups return at once.
+// Workgroup slots given to them and to the loss workgroup that follows them: a
+// multiple of the 8 XCDs, so that HR tile t (workgroup pupil_wg_slots + t) runs
+// on XCD t mod 8 whatever the pupil size; the padding workgroups return at once.
 __host__ __device__ constexpr int pupil_wg_slots(int n, int disk_rows) {
-  return (pupil_wg_count(n, disk_rows) + 7) / 8 * 8;
+  return (pupil_wg_count(n, disk_rows) + 1 + 7) / 8 * 8;
+}
+
+// The batch loss of a step, by one workgroup of 256 threads: *loss += the sum of
+// the column pass's n partials (thread t adds partials t, t + 256, ... in
+// increasing order, their loads issued kU at a time; then the four waves'
+// totals in order). The partials and *loss are all requested at once: a
+// workgroup of its own does this, so the sum does not wait behind, or delay,
+// the pupil update.
+__device__ __forceinline__ void add_batch_loss(const double* __restrict__ part, int n,
+                                               double* loss) {
+  constexpr int kU = 8;
+  __shared__ double wsum[4];
+  const double prev = *loss;
+  double s = 0.0;
+  for (int i0 = threadIdx.x; i0 < n; i0 += 256 * kU) {
+    double v[kU];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) v[u] = part[min(i0 + u * 256, n - 1)];
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+      if (i0 + u * 256 < n) s += v[u];
+  }
+  s = wave_sum(s);
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) *loss = prev + (((wsum[0] + wsum[1]) + wsum[2]) + wsum[3]);
 }
 
 // Pupil workgroup pw rebuilds P on the disk points of disk rows pw R .. pw R + R - 1
@@ -281,11 +308,16 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     return;
   }
   const int pw = blockIdx.x;
-  if (a.pupil && pw >= pupil_wg_count(N, a.dk.nrows)) return;   // padding
+  const int n_pupil = a.pupil ? pupil_wg_count(N, a.dk.nrows) : 0;
+  if (pw == n_pupil) {   // the loss workgroup
+    if (a.loss) add_batch_loss(a.loss_part, a.n_loss, a.loss);
+    return;
+  }
+  if (pw > n_pupil) return;   // padding
   __shared__ double red[256];
   __shared__ double gsum[kPar];
   __shared__ float next[kScal];
-  if (a.pupil) {
+  {
     // moments of the row pass: thread t sums entry t % 16 of partials t/16, t/16 + 16, ...
     // (independent loads in flight, then a fixed summation order)
     const int j = threadIdx.x & (kPar - 1);
@@ -351,14 +383,6 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     FPM_PROBE(3, 1);
     // rebuild this workgroup's rows of the pupil from the new parameters
     rebuild_pupil_rows<N, false>(pw, a.dk, a.pg, next, a.cur.z != nullptr, a.P);
-  }
-  FPM_PROBE(3, 2);
-  if (pw == 0 && a.loss && threadIdx.x < 64) {
-    double s = 0.0;
-    for (int i = threadIdx.x; i < a.n_loss; i += 64) s += a.loss_part[i];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (threadIdx.x == 0) *a.loss += s;
   }
   FPM_PROBE(3, 3);
 }

@@ -521,7 +521,8 @@ struct MultiUpdateArgs {
 //  pupil workgroups: sum the moment and offset-gradient partials in a fixed
 //    order, Adam on the Zernike coefficients, defocus and geometry (all of
 //    them compute the same numbers, workgroup 0 writes the next parameter
-//    block), rebuild their share of the pupil.
+//    block), rebuild their share of the pupil;
+//  the workgroup after them: adds the batch loss to *loss.
 template <int N>
 __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
   const int n_pw = pupil_wg_slots(N, a.dk.nrows);
@@ -568,7 +569,12 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
     return;
   }
   const int pw = blockIdx.x;
-  if (pw >= pupil_wg_count(N, a.dk.nrows)) return;   // padding
+  const int n_pupil = pupil_wg_count(N, a.dk.nrows);
+  if (pw == n_pupil) {   // the loss workgroup
+    if (a.loss) add_batch_loss(a.loss_part, a.n_loss, a.loss);
+    return;
+  }
+  if (pw > n_pupil) return;   // padding
   FPM_PROBE(3, 0);
   __shared__ double red[256];
   __shared__ double gsum[kPar];
@@ -660,14 +666,6 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
   }
   // rebuild this workgroup's rows of the pupil from the new parameters
   rebuild_pupil_rows<N, true>(pw, a.dk, a.pg, nextc[0], true, a.P);
-  FPM_PROBE(3, 2);
-  if (pw == 0 && a.loss && threadIdx.x < 64) {
-    double s = 0.0;
-    for (int k = threadIdx.x; k < a.n_loss; k += 64) s += a.loss_part[k];
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
-    if (threadIdx.x == 0) *a.loss += s;
-  }
   FPM_PROBE(3, 3);
 }
 

@@ -132,14 +132,14 @@ __host__ __device__ constexpr int pupil_wg_slots(int n, int disk_rows) {
   return (pupil_wg_count(n, disk_rows) + 1 + 7) / 8 * 8;
 }
 
-// The batch loss of a step, by one workgroup of 256 threads: *loss += the sum of
-// the column pass's n partials (thread t adds partials t, t + 256, ... in
-// increasing order, their loads issued kU at a time; then the four waves'
-// totals in order). The partials and *loss are all requested at once: a
-// workgroup of its own does this, so the sum does not wait behind, or delay,
-// the pupil update.
+// The batch loss of a step, by one workgroup of 256 threads (all of them call
+// this): *loss += the sum of the column pass's n partials part[i * stride]
+// (thread t adds partials t, t + 256, ... in increasing order, their loads
+// issued kU at a time; then the four waves' totals in order). The partials and
+// *loss are all requested at once: in the update kernels a workgroup of its
+// own does this, so the sum does not wait behind, or delay, the pupil update.
 __device__ __forceinline__ void add_batch_loss(const double* __restrict__ part, int n,
-                                               double* loss) {
+                                               double* loss, int stride = 1) {
   constexpr int kU = 8;
   __shared__ double wsum[4];
   const double prev = *loss;
@@ -147,7 +147,7 @@ __device__ __forceinline__ void add_batch_loss(const double* __restrict__ part, 
   for (int i0 = threadIdx.x; i0 < n; i0 += 256 * kU) {
     double v[kU];
 #pragma unroll
-    for (int u = 0; u < kU; ++u) v[u] = part[min(i0 + u * 256, n - 1)];
+    for (int u = 0; u < kU; ++u) v[u] = part[(size_t)min(i0 + u * 256, n - 1) * stride];
 #pragma unroll
     for (int u = 0; u < kU; ++u)
       if (i0 + u * 256 < n) s += v[u];
@@ -214,7 +214,7 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
     if (meets) hit |= 1ull << b;
   }
 #ifndef FPM_GATHER_ROUND
-#define FPM_GATHER_ROUND 2
+#define FPM_GATHER_ROUND 4
 #endif
   constexpr int kRound = FPM_GATHER_ROUND;
   while (hit) {
@@ -230,7 +230,13 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
     bool ok[kRound][4];
 #pragma unroll
     for (int u = 0; u < kRound; ++u) {
-      const int b = bs[u] < 0 ? bs[0] : bs[u];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        ok[u][q] = false;
+        val[u][q] = make_float2(0.f, 0.f);
+      }
+      if (bs[u] < 0) continue;   // uniform: no loads for an empty slot
+      const int b = bs[u];
       const int wr = a.bt.win[b].x, wc = a.bt.win[b].y;
       const int ky = r - wr;
       const int kyc = min(max(ky, a.dk.ky_lo), a.dk.ky_hi);
@@ -239,7 +245,7 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int kx = c0 + tile_col(q) - wc;
-        ok[u][q] = bs[u] >= 0 && ky == kyc && kx >= e.x && kx <= e.y;
+        ok[u][q] = ky == kyc && kx >= e.x && kx <= e.y;
         val[u][q] = xr[min(max(kx, e.x), e.y)];
       }
     }

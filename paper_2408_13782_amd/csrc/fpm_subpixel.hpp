@@ -371,6 +371,7 @@ __global__ void __launch_bounds__(256) loss_grad_reduce(ReduceArgs a) {
   __shared__ double gs[kMaxSlots][2];
   __shared__ double ea[kMaxSlots];
   const int tid = threadIdx.x;
+  if (a.loss) add_batch_loss(a.col_part, a.col_wgs, a.loss, 2);   // the whole workgroup
   // pupil moments: thread (j, lane) sums workgroups lane, lane + 16, ...
   {
     const int j = tid & (kPar - 1), lane = tid / kPar;
@@ -398,7 +399,6 @@ __global__ void __launch_bounds__(256) loss_grad_reduce(ReduceArgs a) {
   }
   __syncthreads();
   if (tid == 0) {
-    if (a.loss) *a.loss += ordered_sum<32>(a.col_part, a.col_wgs, 2);   // workgroup order
     if (a.g_geom) {
       double gg[4] = {0.0, 0.0, 0.0, 0.0};
       for (int b = 0; b < a.bt.B; ++b)

@@ -39,9 +39,9 @@ FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, no packe
 # workload's kernels are those of the fused multi-parameter step.
 TRAFFIC = {
     ("paper", "rows_forward"): (1936.1 * 2 + 4788.7) * 1024,
-    ("paper", "cols"): (4453.1 * 2 + 4843.4) * 1024,
-    ("paper", "rows_backward"): (4459.4 * 2 + 2450.0) * 1024,
-    ("paper", "update"): (7224.9 * 2 + 9754.3) * 1024,
+    ("paper", "cols"): (4451.1 * 2 + 4843.4) * 1024,
+    ("paper", "rows_backward"): (4459.8 * 2 + 2450.0) * 1024,
+    ("paper", "update"): (7230.3 * 2 + 9754.3) * 1024,
     ("large", "rows_forward"): (14739.3 * 2 + 39716.4) * 1024,
     ("large", "cols"): (36173.5 * 2 + 39786.6) * 1024,
     ("large", "rows_backward"): (34168.5 * 2 + 19665.9) * 1024,

@@ -341,8 +341,10 @@ template <int N> constexpr int row_lines() { return kRowThreads / RowPlan<N>::T;
 
 struct Grids {
   int slots, row_chunks, col_groups;
+  int sub_bwd_chunks;   // chunks of rows_backward_sub (its own workgroup size)
   int rows() const { return slots * row_chunks; }
   int cols() const { return slots * col_groups; }
+  int sub_bwd_rows() const { return slots * sub_bwd_chunks; }
 };
 
 template <int N>
@@ -351,6 +353,8 @@ Grids grids_of(const fpm_plan* p, int B) {
   g.slots = (B + kXcds - 1) / kXcds * kXcds;
   g.row_chunks = (p->nrows + row_lines<N>() - 1) / row_lines<N>();
   g.col_groups = N / ColLines<N>::value;
+  constexpr int sub_lines = SubBwdThreads<N>::value / RowPlan<N>::T;
+  g.sub_bwd_chunks = (p->nrows + sub_lines - 1) / sub_lines;
   return g;
 }
 
@@ -530,9 +534,9 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
   }
   {
     Timed tm(p, kRowsBackward, st);
-    rows_backward_sub<N><<<g.rows(), kRowThreads, 0, st>>>(p->X, O, p->P_ws, bt, dk, pg, ga,
-                                                           pr->geom, g.row_chunks, row_part,
-                                                           p->kappa_tab, p->twN);
+    rows_backward_sub<N><<<g.sub_bwd_rows(), SubBwdThreads<N>::value, 0, st>>>(
+        p->X, O, p->P_ws, bt, dk, pg, ga, pr->geom, g.sub_bwd_chunks, row_part, p->kappa_tab,
+        p->twN);
   }
   if (gr->g_O) {
     Timed tm(p, kAdamObject, st);
@@ -544,8 +548,8 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
   ra.col_wgs = g.cols();
   ra.col_chunks = g.col_groups;
   ra.row_part = row_part;
-  ra.row_wgs = g.rows();
-  ra.row_chunks = g.row_chunks;
+  ra.row_wgs = g.sub_bwd_rows();
+  ra.row_chunks = g.sub_bwd_chunks;
   ra.sub = p->sub;
   ra.bt = bt;
   ra.gamma = pr->gamma;
@@ -589,9 +593,8 @@ int launch_multi_step(fpm_plan* p, const GeomArgs& ga, fpm_state* s, const fpm_g
   {
     Timed tm(p, kRowsBackward, st);
     for (int r = 0; r < tm.reps; ++r)
-      rows_backward_sub<N><<<g.rows(), kRowThreads, 0, st>>>(p->X, O, P, bt, dk, pg, ga, geom,
-                                                             g.row_chunks, row_part,
-                                                             p->kappa_tab, p->twN);
+      rows_backward_sub<N><<<g.sub_bwd_rows(), SubBwdThreads<N>::value, 0, st>>>(
+          p->X, O, P, bt, dk, pg, ga, geom, g.sub_bwd_chunks, row_part, p->kappa_tab, p->twN);
   }
   const int t = s->t + 1;
   const double b1 = hp->beta1, b2 = hp->beta2;
@@ -615,8 +618,8 @@ int launch_multi_step(fpm_plan* p, const GeomArgs& ga, fpm_state* s, const fpm_g
   a.n_loss = g.cols();
   a.loss = s->loss;
   a.row_part = row_part;
-  a.n_rows = g.rows();
-  a.row_chunks = g.row_chunks;
+  a.n_rows = g.sub_bwd_rows();
+  a.row_chunks = g.sub_bwd_chunks;
   a.cur = cur;
   a.next = next;
   a.sa.learn_c = hp->learn_zernike;

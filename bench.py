@@ -42,10 +42,10 @@ TRAFFIC = {
     ("paper", "cols"): (4451.1 * 2 + 4843.4) * 1024,
     ("paper", "rows_backward"): (4459.8 * 2 + 2450.0) * 1024,
     ("paper", "update"): (7230.3 * 2 + 9754.3) * 1024,
-    ("large", "rows_forward"): (14739.3 * 2 + 39716.4) * 1024,
+    ("large", "rows_forward"): (14736.0 * 2 + 39716.4) * 1024,
     ("large", "cols"): (36173.5 * 2 + 39786.6) * 1024,
-    ("large", "rows_backward"): (34168.5 * 2 + 19665.9) * 1024,
-    ("large", "update"): (47340.0 * 2 + 57625.8) * 1024,
+    ("large", "rows_backward"): (34201.7 * 2 + 19470.9) * 1024,
+    ("large", "update"): (45730.3 * 2 + 57625.7) * 1024,
 }
 
 

@@ -338,11 +338,19 @@ Disk disk_of(const fpm_plan* p) {
 }
 
 template <int N> constexpr int row_lines() { return kRowThreads / RowPlan<N>::T; }
+// the nearest-pixel backward row pass serves as many rows per workgroup as the
+// sub-pixel passes (its workgroups are counted by row_chunks)
+template <int N> constexpr bool bwd_rows_match() { return BwdRow<N>::threads / BwdRow<N>::T == row_lines<N>(); }
+static_assert(bwd_rows_match<64>() && bwd_rows_match<128>() && bwd_rows_match<192>() &&
+              bwd_rows_match<256>() && bwd_rows_match<384>() && bwd_rows_match<512>(),
+              "rows per workgroup of the backward row pass");
 
 struct Grids {
   int slots, row_chunks, col_groups;
+  int fwd_chunks;       // chunks of rows_forward (its own workgroup shape)
   int sub_bwd_chunks;   // chunks of rows_backward_sub (its own workgroup size)
   int rows() const { return slots * row_chunks; }
+  int fwd_rows() const { return slots * fwd_chunks; }
   int cols() const { return slots * col_groups; }
   int sub_bwd_rows() const { return slots * sub_bwd_chunks; }
 };
@@ -352,6 +360,8 @@ Grids grids_of(const fpm_plan* p, int B) {
   Grids g;
   g.slots = (B + kXcds - 1) / kXcds * kXcds;
   g.row_chunks = (p->nrows + row_lines<N>() - 1) / row_lines<N>();
+  constexpr int fwd_lines = FwdRow<N>::threads / FwdRow<N>::T;
+  g.fwd_chunks = (p->nrows + fwd_lines - 1) / fwd_lines;
   g.col_groups = N / ColLines<N>::value;
   constexpr int sub_lines = SubBwdThreads<N>::value / RowPlan<N>::T;
   g.sub_bwd_chunks = (p->nrows + sub_lines - 1) / sub_lines;
@@ -379,7 +389,7 @@ int launch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t
   {
     Timed tm(p, kRowsForward, st);
     for (int r = 0; r < tm.reps; ++r)
-      rows_forward<N><<<gr.rows(), kRowThreads, 0, st>>>(O, P, bt, dk, gr.row_chunks, p->X,
+      rows_forward<N><<<gr.fwd_rows(), FwdRow<N>::threads, 0, st>>>(O, P, bt, dk, gr.fwd_chunks, p->X,
                                                            p->twN, o.commit, p->staging, o.scal);
   }
   {
@@ -394,19 +404,19 @@ int launch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t
     const PupilGeom pg = pupil_geom(p);
     for (int r = 0; r < tm.reps; ++r) switch (o.mode) {
       case kGradO:
-        rows_backward<N, kGradO><<<gr.rows(), kRowThreads, 0, st>>>(
+        rows_backward<N, kGradO><<<gr.rows(), BwdRow<N>::threads, 0, st>>>(
             p->X, O, P, bt, dk, pg, gr.row_chunks, gO, nullptr, nullptr, nullptr, p->twN);
         break;
       case kGradOP:
-        rows_backward<N, kGradOP><<<gr.rows(), kRowThreads, 0, st>>>(
+        rows_backward<N, kGradOP><<<gr.rows(), BwdRow<N>::threads, 0, st>>>(
             p->X, O, P, bt, dk, pg, gr.row_chunks, gO, o.gP, nullptr, nullptr, p->twN);
         break;
       case kPatch:
-        rows_backward<N, kPatch><<<gr.rows(), kRowThreads, 0, st>>>(
+        rows_backward<N, kPatch><<<gr.rows(), BwdRow<N>::threads, 0, st>>>(
             p->X, O, P, bt, dk, pg, gr.row_chunks, nullptr, nullptr, nullptr, nullptr, p->twN);
         break;
       default:
-        rows_backward<N, kPatchZern><<<gr.rows(), kRowThreads, 0, st>>>(
+        rows_backward<N, kPatchZern><<<gr.rows(), BwdRow<N>::threads, 0, st>>>(
             p->X, O, P, bt, dk, pg, gr.row_chunks, nullptr, nullptr, o.zpart, p->kappa_tab,
             p->twN);
         break;
@@ -424,7 +434,7 @@ int launch_forward(fpm_plan* p, const float2* O, const float2* P, const int32_t*
   const Disk dk = disk_of(p);
   {
     Timed tm(p, kRowsForward, st);
-    rows_forward<N><<<gr.rows(), kRowThreads, 0, st>>>(O, P, bt, dk, gr.row_chunks, p->X,
+    rows_forward<N><<<gr.fwd_rows(), FwdRow<N>::threads, 0, st>>>(O, P, bt, dk, gr.fwd_chunks, p->X,
                                                          p->twN, 0, nullptr, ScalarState{});
   }
   {

@@ -348,9 +348,11 @@ static_assert(bwd_rows_match<64>() && bwd_rows_match<128>() && bwd_rows_match<19
 struct Grids {
   int slots, row_chunks, col_groups;
   int fwd_chunks;       // chunks of rows_forward (its own workgroup shape)
+  int sub_fwd_chunks;   // chunks of rows_forward_sub (its own workgroup shape)
   int sub_bwd_chunks;   // chunks of rows_backward_sub (its own workgroup size)
   int rows() const { return slots * row_chunks; }
   int fwd_rows() const { return slots * fwd_chunks; }
+  int sub_fwd_rows() const { return slots * sub_fwd_chunks; }
   int cols() const { return slots * col_groups; }
   int sub_bwd_rows() const { return slots * sub_bwd_chunks; }
 };
@@ -362,6 +364,8 @@ Grids grids_of(const fpm_plan* p, int B) {
   g.row_chunks = (p->nrows + row_lines<N>() - 1) / row_lines<N>();
   constexpr int fwd_lines = FwdRow<N>::threads / FwdRow<N>::T;
   g.fwd_chunks = (p->nrows + fwd_lines - 1) / fwd_lines;
+  constexpr int sub_fwd_lines = SubFwdRow<N>::threads / SubFwdRow<N>::T;
+  g.sub_fwd_chunks = (p->nrows + sub_fwd_lines - 1) / sub_fwd_lines;
   g.col_groups = N / ColLines<N>::value;
   constexpr int sub_lines = SubBwdThreads<N>::value / RowPlan<N>::T;
   g.sub_bwd_chunks = (p->nrows + sub_lines - 1) / sub_lines;
@@ -532,8 +536,8 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
   double* row_part = p->part_lg + (size_t)g.cols() * 2;
   {
     Timed tm(p, kRowsForward, st);
-    rows_forward_sub<N><<<g.rows(), kRowThreads, 0, st>>>(O, p->P_ws, bt, dk, ga, pr->geom,
-                                                          gr->oob, p->sub, g.row_chunks, p->X,
+    rows_forward_sub<N><<<g.sub_fwd_rows(), SubFwdRow<N>::threads, 0, st>>>(
+        O, p->P_ws, bt, dk, ga, pr->geom, gr->oob, p->sub, g.sub_fwd_chunks, p->X,
                                                           p->twN);
   }
   {
@@ -590,8 +594,8 @@ int launch_multi_step(fpm_plan* p, const GeomArgs& ga, fpm_state* s, const fpm_g
   {
     Timed tm(p, kRowsForward, st);
     for (int r = 0; r < tm.reps; ++r)
-      rows_forward_sub<N><<<g.rows(), kRowThreads, 0, st>>>(O, P, bt, dk, ga, geom, p->oob_ws,
-                                                            p->sub, g.row_chunks, p->X, p->twN);
+      rows_forward_sub<N><<<g.sub_fwd_rows(), SubFwdRow<N>::threads, 0, st>>>(
+          O, P, bt, dk, ga, geom, p->oob_ws, p->sub, g.sub_fwd_chunks, p->X, p->twN);
   }
   {
     Timed tm(p, kCols, st);

@@ -675,36 +675,38 @@ int launch_update(fpm_plan* p, const UpdateArgs& a, int grid, hipStream_t st) {
 }
 
 template <int M>
-int launch_hr(fpm_plan* p, HrArgs a, int row_mode, int dir, hipStream_t st) {
+int launch_hr(fpm_plan* p, HrArgs a, int row_mode, int dir, int batch, hipStream_t st) {
   constexpr int Lr = HrRowLines<M>::value;
   constexpr int Lc = HrColLines<M>::value;
   constexpr int T = Plan1D<M>::T;
+  const dim3 gr(M / Lr, batch), gc(M / Lc, batch);
   {
   Timed tm(p, kHrRows, st);
   switch (row_mode) {
-    case kRowFwd: hr_rows<M, kRowFwd><<<M / Lr, Lr * T, 0, st>>>(a, p->twM); break;
-    case kRowInv: hr_rows<M, kRowInv><<<M / Lr, Lr * T, 0, st>>>(a, p->twM); break;
-    case kRowInit: hr_rows<M, kRowInit><<<M / Lr, Lr * T, 0, st>>>(a, p->twM); break;
-    case kRowRefocus: hr_rows<M, kRowRefocus><<<M / Lr, Lr * T, 0, st>>>(a, p->twM); break;
+    case kRowFwd: hr_rows<M, kRowFwd><<<gr, Lr * T, 0, st>>>(a, p->twM); break;
+    case kRowInv: hr_rows<M, kRowInv><<<gr, Lr * T, 0, st>>>(a, p->twM); break;
+    case kRowInit: hr_rows<M, kRowInit><<<gr, Lr * T, 0, st>>>(a, p->twM); break;
+    case kRowRefocus: hr_rows<M, kRowRefocus><<<gr, Lr * T, 0, st>>>(a, p->twM); break;
   }
   }
   Timed tm(p, kHrCols, st);
   if (dir < 0)
-    hr_cols<M, -1><<<M / Lc, Lc * T, 0, st>>>(a.out, p->twM);
+    hr_cols<M, -1><<<gc, Lc * T, 0, st>>>(a.out, p->twM);
   else
-    hr_cols<M, +1><<<M / Lc, Lc * T, 0, st>>>(a.out, p->twM);
+    hr_cols<M, +1><<<gc, Lc * T, 0, st>>>(a.out, p->twM);
   FPM_HIP(hipGetLastError());
   return FPM_OK;
 }
 
-int dispatch_hr(fpm_plan* p, HrArgs a, int row_mode, int dir, hipStream_t st) {
+// batch > 1 only with kRowRefocus (one distance per transform).
+int dispatch_hr(fpm_plan* p, HrArgs a, int row_mode, int dir, hipStream_t st, int batch = 1) {
   switch (p->M) {
-    case 256: return launch_hr<256>(p, a, row_mode, dir, st);
-    case 512: return launch_hr<512>(p, a, row_mode, dir, st);
-    case 768: return launch_hr<768>(p, a, row_mode, dir, st);
-    case 1024: return launch_hr<1024>(p, a, row_mode, dir, st);
-    case 1536: return launch_hr<1536>(p, a, row_mode, dir, st);
-    case 2048: return launch_hr<2048>(p, a, row_mode, dir, st);
+    case 256: return launch_hr<256>(p, a, row_mode, dir, batch, st);
+    case 512: return launch_hr<512>(p, a, row_mode, dir, batch, st);
+    case 768: return launch_hr<768>(p, a, row_mode, dir, batch, st);
+    case 1024: return launch_hr<1024>(p, a, row_mode, dir, batch, st);
+    case 1536: return launch_hr<1536>(p, a, row_mode, dir, batch, st);
+    case 2048: return launch_hr<2048>(p, a, row_mode, dir, batch, st);
   }
   return fail(FPM_EUNSUPPORTED, kHrSizes);
 }
@@ -1255,14 +1257,17 @@ int fpm_refocus(fpm_plan* p, const fpm_c32* O, const float* z_um, int32_t nz, fp
   if (!p->hr_ok) return fail(FPM_EUNSUPPORTED, kHrSizes);
   if (int rc = check_device(p)) return rc;
   if (nz == 0) return FPM_OK;
-  for (int i = 0; i < nz; ++i) {
+  // the distances in batches (grid rows): one row and one column launch each
+  constexpr int kBatch = 1024;
+  for (int i0 = 0; i0 < nz; i0 += kBatch) {
     HrArgs a{};
     a.in = reinterpret_cast<const float2*>(O);
-    a.out = reinterpret_cast<float2*>(out) + (size_t)i * p->M * p->M;
-    a.z_um = z_um + i;
+    a.out = reinterpret_cast<float2*>(out) + (size_t)i0 * p->M * p->M;
+    a.z_um = z_um + i0;
     a.dk2 = p->dk * p->dk;
     a.inv_l = 1.0 / p->lambda;
-    if (int rc = dispatch_hr(p, a, kRowRefocus, +1, (hipStream_t)stream)) return rc;
+    if (int rc = dispatch_hr(p, a, kRowRefocus, +1, (hipStream_t)stream, std::min(kBatch, nz - i0)))
+      return rc;
   }
   return FPM_OK;
 }

@@ -406,13 +406,15 @@ struct HrArgs {
   const float2* in;     // row-pass source (object, spectrum)
   const float* img;     // kRowInit: centre amplitude image [n][n]
   int n, s;             // kRowInit: LR size and upsampling
-  const float* z_um;    // kRowRefocus: device pointer to the distance
+  const float* z_um;    // kRowRefocus: device pointer to the distances, one per grid row y
   double dk2, inv_l;    // kRowRefocus
-  float2* out;          // destination of both passes
+  float2* out;          // destination of both passes; transform y of a batch at out + y M^2
 };
 
 // Forward (DIR -1): rows of o, DFT, fftshift along k_x.
 // Inverse (DIR +1): ifftshift along k_x (times H(z) when refocusing), inverse DFT.
+// A refocusing launch serves a batch of distances: grid row y computes the
+// transform at z_um[y] into out + y M^2 (one launch per pass for the sweep).
 template <int M, int MODE>
 __global__ void __launch_bounds__(HrRowLines<M>::value * Plan1D<M>::T)
 hr_rows(HrArgs a, const float2* __restrict__ tw) {
@@ -423,6 +425,7 @@ hr_rows(HrArgs a, const float2* __restrict__ tw) {
   __shared__ float2 lds[L * RowLds<M>::kStride];
   const int line = threadIdx.x / T, t = threadIdx.x % T;
   const int row = blockIdx.x * L + line;   // grid covers M rows exactly
+  float2* out = a.out + (size_t)blockIdx.y * M * M;
   float2 v[E];
   if constexpr (MODE == kRowFwd) {
 #pragma unroll
@@ -445,6 +448,7 @@ hr_rows(HrArgs a, const float2* __restrict__ tw) {
       v[m] = make_float2(top * (1.f - wy) + bot * wy, 0.f);
     }
   } else {
+    const double z = MODE == kRowRefocus ? (double)a.z_um[blockIdx.y] : 0.0;
 #pragma unroll
     for (int m = 0; m < E; ++m) {
       const int kx = half_shift<M>(t + m * T);
@@ -456,7 +460,7 @@ hr_rows(HrArgs a, const float2* __restrict__ tw) {
           val = make_float2(0.f, 0.f);
         } else {
           double sn, cs;
-          sincos((double)*a.z_um * defocus_kappa(k2, a.inv_l), &sn, &cs);
+          sincos(z * defocus_kappa(k2, a.inv_l), &sn, &cs);
           val = cmul(val, make_float2((float)cs, (float)sn));
         }
       }
@@ -464,7 +468,7 @@ hr_rows(HrArgs a, const float2* __restrict__ tw) {
     }
   }
   Plan1D<M>::template run<DIR>(v, t, lds + line * RowLds<M>::kStride, [](int n) { return RowLds<M>::at(n); }, tw);
-  float2* orow = a.out + (size_t)row * M;
+  float2* orow = out + (size_t)row * M;
   if constexpr (DIR < 0) {
 #pragma unroll
     for (int m = 0; m < E; ++m) orow[half_shift<M>(t + m * T)] = v[m];
@@ -485,6 +489,7 @@ hr_cols(float2* __restrict__ data, const float2* __restrict__ tw) {
   __shared__ float2 lds[M * (L + 1)];
   const int line = threadIdx.x % L, t = threadIdx.x / L;
   const int x = blockIdx.x * L + line;
+  data += (size_t)blockIdx.y * M * M;   // transform y of a batch
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {

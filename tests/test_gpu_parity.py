@@ -589,6 +589,24 @@ def test_refocus_matches_oracle(dev, n_lr):
         assert rel_l2(out[i], want[i]) <= GRAD_TOL
 
 
+def test_refocus_more_distances_than_one_launch_batch(dev):
+    """1030 distances at M = 256: two launch batches of the sweep (1024 and a
+    ragged 6); the first, last and batch-edge distances against the oracle."""
+    w = inputs.workload("small")
+    say("refocus 1030 z at M=256")
+    plan = make_plan(w, oracle_shifts(w) * 0, 1)
+    amp, ph = inputs.truth_object(w.m_hr, seed=10)
+    O = fo.spectrum(fo.transmission(amp, ph)).astype(np.complex64)
+    z = np.linspace(-40.0, 40.0, 1030).astype(np.float32)
+    out = plan.refocus(T(O, dev), T(z, dev))
+    assert tuple(out.shape) == (1030, w.m_hr, w.m_hr)
+    idx = [0, 511, 1023, 1024, 1029]
+    got = H(out[idx])
+    want = fo.refocus(O.astype(np.complex128), z[idx].astype(np.float64), optics_of(w))
+    for k, i in enumerate(idx):
+        assert rel_l2(got[k], want[k]) <= GRAD_TOL, i
+
+
 # ---------------------------------------------------------------------------
 # edge cases and errors
 

@@ -338,8 +338,8 @@ Disk disk_of(const fpm_plan* p) {
 }
 
 template <int N> constexpr int row_lines() { return kRowThreads / RowPlan<N>::T; }
-// the nearest-pixel backward row pass serves as many rows per workgroup as the
-// sub-pixel passes (its workgroups are counted by row_chunks)
+// the nearest-pixel backward row pass is counted by row_chunks, which also
+// sizes the moment-partial buffers
 template <int N> constexpr bool bwd_rows_match() { return BwdRow<N>::threads / BwdRow<N>::T == row_lines<N>(); }
 static_assert(bwd_rows_match<64>() && bwd_rows_match<128>() && bwd_rows_match<192>() &&
               bwd_rows_match<256>() && bwd_rows_match<384>() && bwd_rows_match<512>(),

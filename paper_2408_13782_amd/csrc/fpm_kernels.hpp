@@ -64,14 +64,17 @@ template <> struct RowT<512> { static constexpr int value = FPM_ROW_T512; };
 template <int N> using RowPlan = PlanT<N, RowT<N>::value>;
 
 // The nearest-pixel row passes, each with its own shape. At N = 256, 64
-// threads per row take 0.26 us off the forward pass (two rows per workgroup).
-// The backward pass keeps the common shape: its workgroup count is the number
-// of moment partials that every pupil workgroup of the update sums, and 64
-// threads per row at the same rows per workgroup (256 threads) measured no
-// better.
+// threads per row take 0.26 us off the forward pass (two rows per workgroup);
+// at N = 512, 64 threads per row in both passes take 2.8 us off a step
+// (B = 32). The backward pass keeps the common rows per workgroup (with 64
+// threads per row, in 256-thread workgroups): its workgroup count is the
+// number of moment partials that every pupil workgroup of the update sums. At
+// N = 256 that shape measured no better than 32 threads per row.
 template <int N> struct FwdRow { static constexpr int T = RowT<N>::value, threads = kRowThreads; };
 template <> struct FwdRow<256> { static constexpr int T = 64, threads = kRowThreads; };
+template <> struct FwdRow<512> { static constexpr int T = 64, threads = kRowThreads; };
 template <int N> struct BwdRow { static constexpr int T = RowT<N>::value, threads = kRowThreads; };
+template <> struct BwdRow<512> { static constexpr int T = 64, threads = 2 * kRowThreads; };
 
 #ifndef FPM_COL_LINES256
 #define FPM_COL_LINES256 16

@@ -549,7 +549,7 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
   {
     Timed tm(p, kRowsBackward, st);
     rows_backward_sub<N><<<g.sub_bwd_rows(), SubBwdThreads<N>::value, 0, st>>>(
-        p->X, O, p->P_ws, bt, dk, pg, ga, pr->geom, g.sub_bwd_chunks, row_part, p->kappa_tab,
+        p->X, O, p->P_ws, bt, dk, pg, p->sub, g.sub_bwd_chunks, row_part, p->kappa_tab,
         p->twN);
   }
   if (gr->g_O) {
@@ -608,7 +608,7 @@ int launch_multi_step(fpm_plan* p, const GeomArgs& ga, fpm_state* s, const fpm_g
     Timed tm(p, kRowsBackward, st);
     for (int r = 0; r < tm.reps; ++r)
       rows_backward_sub<N><<<g.sub_bwd_rows(), SubBwdThreads<N>::value, 0, st>>>(
-          p->X, O, P, bt, dk, pg, ga, geom, g.sub_bwd_chunks, row_part, p->kappa_tab, p->twN);
+          p->X, O, P, bt, dk, pg, p->sub, g.sub_bwd_chunks, row_part, p->kappa_tab, p->twN);
   }
   const int t = s->t + 1;
   const double b1 = hp->beta1, b2 = hp->beta2;

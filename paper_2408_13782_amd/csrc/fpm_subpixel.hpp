@@ -181,8 +181,8 @@ template <int N> struct SubBwdThreads { static constexpr int value = N >= 512 ? 
 template <int N, int kThreads = SubBwdThreads<N>::value>
 __global__ void __launch_bounds__(kThreads)
 rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
-                  const float2* __restrict__ P, Batch bt, Disk dk, PupilGeom pg, GeomArgs ga,
-                  const double* __restrict__ geom, int chunks, double* __restrict__ part,
+                  const float2* __restrict__ P, Batch bt, Disk dk, PupilGeom pg,
+                  const SubSlot* __restrict__ stored, int chunks, double* __restrict__ part,
                   const float* __restrict__ kappa_tab, const float2* __restrict__ tw) {
   constexpr int T = RowPlan<N>::T;
   constexpr int E = N / T;
@@ -202,11 +202,14 @@ rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
   if (live) {
     float2* xr = X + ((size_t)b * N + ky) * N;
     const int2 ext = disk_extent<N>(dk, ky);
-    bool clamped;
-    const SubSlot sl = subslot_of(ga, geom, bt, b, &clamped);
     float2 v[E];
 #pragma unroll
     for (int m = 0; m < E; ++m) v[m] = xr[t + m * T];
+    // the slot's offsets as rows_forward_sub derived and stored them (the taps
+    // are read only after the transform, so this load is off the critical path;
+    // deriving them here again cost each workgroup a chain of FP64 operations
+    // before its first load)
+    const SubSlot sl = stored[b];
     stage_twiddles_after_loads<N, kThreads>(lds_tw, tw);
     RowPlan<N>::template run<-1>(v, t, lds + line * RowLds<N>::kStride,
                                 [](int n) { return RowLds<N>::at(n); }, lds_tw);

@@ -2,9 +2,10 @@
 // LED-array geometry, bilinear crop and its adjoint, gradients with respect to
 // the geometry and the LED intensities (paper Sec. 2.1 k_m and Eq. 3; Sec. 2.2).
 //
-// Every kernel derives the offsets of its batch slots itself, in FP64, from
+// The forward row pass derives the offsets of its batch slots, in FP64, from
 // the nominal grid and the current geometry errors (subslot_of), so no launch
-// is spent on them. Launch order of one loss-and-gradient call:
+// is spent on them, and stores them for the later kernels of the call.
+// Launch order of one loss-and-gradient call:
 //   pupil_build        P from the Zernike coefficients and defocus
 //   rows_forward_sub   bilinear crop C_b (4 taps) * P, inverse DFT of disk rows
 //   cols<.., kGamma>   as in the nearest path, plus sum e |psi| per workgroup

@@ -142,24 +142,47 @@ rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Bat
   const bool active = rr < dk.nrows;
   const int ky = dk.ky_lo + (active ? rr : 0);
   const int2 ext = disk_extent<N>(dk, ky);
-  bool clamped;
-  const SubSlot sl = subslot_of(ga, geom, bt, b, &clamped);
-  if (c == 0 && threadIdx.x == 0) {
-    if (clamped && oob) atomicAdd(oob, 1);
-    sub_out[b] = sl;   // for the later kernels of the call
-  }
-  stage_twiddles_after_loads<N, SubFwdRow<N>::threads>(lds_tw, tw);   // in flight with the geometry
+  // The loads that do not depend on the slot's offsets (pupil row, twiddles)
+  // go out first; the first wave then derives the offsets (a chain of FP64
+  // operations that the second wave would only repeat) and shares them
+  // through LDS, and the taps are loaded once they are known.
+  constexpr int kThreads = SubFwdRow<N>::threads;
+  constexpr int K = (N + kThreads - 1) / kThreads;
+  float2 twr[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) twr[k] = tw[min((int)threadIdx.x + k * kThreads, N - 1)];
   const float2* prow = P + (size_t)ky * N;
+  float2 pv[E];
+#pragma unroll
+  for (int m = 0; m < E; ++m) pv[m] = prow[min(max(half_shift<N>(t + m * T), ext.x), ext.y)];
+  __shared__ int4 slot;   // fr, fc and the bits of ay, ax
+  if (threadIdx.x < 64) {
+    bool clamped;
+    const SubSlot s0 = subslot_of(ga, geom, bt, b, &clamped);
+    if (threadIdx.x == 0) {
+      slot = make_int4(s0.fr, s0.fc, __float_as_int(s0.ay), __float_as_int(s0.ax));
+      if (c == 0) {
+        if (clamped && oob) atomicAdd(oob, 1);
+        sub_out[b] = s0;   // for the later kernels of the call
+      }
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) lds_tw[min((int)threadIdx.x + k * kThreads, N - 1)] = twr[k];
+  __syncthreads();
+  const int4 si = slot;
+  const int sfr = si.x, sfc = si.y;
+  const float say = __int_as_float(si.z), sax = __int_as_float(si.w);
   float2 v[E];
 #pragma unroll
   for (int m = 0; m < E; ++m) {
     const int kx0 = half_shift<N>(t + m * T);
     const int kx = min(max(kx0, ext.x), ext.y);
     float2 t00, t01, t10, t11;
-    taps4(O, bt.M, sl.fr + ky, sl.fc + kx, t00, t01, t10, t11);
-    const float2 C = blend(t00, t01, t10, t11, sl.ay, sl.ax);
+    taps4(O, bt.M, sfr + ky, sfc + kx, t00, t01, t10, t11);
+    const float2 C = blend(t00, t01, t10, t11, say, sax);
     const bool in = active && kx0 >= ext.x && kx0 <= ext.y;
-    v[m] = in ? cmul(C, prow[kx]) : make_float2(0.f, 0.f);
+    v[m] = in ? cmul(C, pv[m]) : make_float2(0.f, 0.f);
   }
   PlanT<N, T>::template run<+1>(v, t, lds + line * RowLds<N>::kStride,
                               [](int n) { return RowLds<N>::at(n); }, lds_tw);

@@ -323,7 +323,7 @@ FPM_PLAN(128, 8, 16, 8)
 FPM_PLAN(128, 16, 8, 4, 4)
 FPM_PLAN(128, 32, 4, 4, 4, 2)
 FPM_PLAN(256, 16, 16, 16)
-FPM_PLAN(256, 32, 8, 8, 4)
+FPM_PLAN(256, 32, 8, 4, 8)
 FPM_PLAN(256, 64, 4, 4, 4, 4)
 FPM_PLAN(512, 32, 16, 16, 2)
 FPM_PLAN(512, 64, 8, 8, 8)

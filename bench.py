@@ -38,10 +38,10 @@ FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, no packe
 # the same counter), for the kernel build they were taken on. The large
 # workload's kernels are those of the fused multi-parameter step.
 TRAFFIC = {
-    ("paper", "rows_forward"): (1927.5 * 2 + 4788.7) * 1024,
-    ("paper", "cols"): (4453.1 * 2 + 4843.4) * 1024,
-    ("paper", "rows_backward"): (4454.4 * 2 + 2450.0) * 1024,
-    ("paper", "update"): (7236.1 * 2 + 9754.3) * 1024,
+    ("paper", "rows_forward"): (1920.5 * 2 + 4788.7) * 1024,
+    ("paper", "cols"): (4452.1 * 2 + 4843.4) * 1024,
+    ("paper", "rows_backward"): (4458.4 * 2 + 2450.0) * 1024,
+    ("paper", "update"): (7238.3 * 2 + 9754.3) * 1024,
     ("large", "rows_forward"): (13033.7 * 2 + 39716.4) * 1024,
     ("large", "cols"): (36173.5 * 2 + 39789.6) * 1024,
     ("large", "rows_backward"): (34225.2 * 2 + 19470.9) * 1024,

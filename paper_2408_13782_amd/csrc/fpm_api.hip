@@ -155,7 +155,8 @@ struct fpm_plan {
   double* part_lg = nullptr;  // partials of fpm_loss_grad (column pass | row pass)
   float2* P_ws = nullptr;     // [N][N] pupil built by fpm_loss_grad
   int* oob_ws = nullptr;      // window-clamp counter when the caller passes none
-  SubSlot* sub = nullptr;     // [max_batch] sub-pixel offsets of the current batch
+  SubSlot* sub = nullptr;     // [2][max_batch] sub-pixel offsets of a batch (two steps of
+                              // fpm_run_multi alternate; fpm_loss_grad uses the first)
   MultiParams* mpar = nullptr;  // [2] parameter blocks of fpm_run_multi
   int* tile_flags = nullptr;  // [(M/32)^2] HR tiles with possibly non-zero Adam moments
   unsigned* counters = nullptr;  // completion counter of pupil_grad's reduction
@@ -537,7 +538,7 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
   {
     Timed tm(p, kRowsForward, st);
     rows_forward_sub<N><<<g.sub_fwd_rows(), SubFwdRow<N>::threads, 0, st>>>(
-        O, p->P_ws, bt, dk, ga, pr->geom, gr->oob, p->sub, g.sub_fwd_chunks, p->X,
+        O, p->P_ws, bt, dk, ga, pr->geom, gr->oob, p->sub, nullptr, g.sub_fwd_chunks, p->X,
                                                           p->twN);
   }
   {
@@ -576,12 +577,18 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
   return FPM_OK;
 }
 
+static_assert(sizeof(MultiUpdateArgs) <= 4096, "kernel arguments are limited to 4 KiB");
+
 // One fused multi-parameter step: parameters of this step in block `cur`,
-// the next ones written to `next`.
+// the next ones written to `next`. The batch's slot offsets live in sub_cur:
+// derived there by the forward row pass, or (pre) already by the previous
+// step's update kernel, which likewise derives the next batch's (leds_next,
+// B_next) into sub_next when there is a next step in this call.
 template <int N>
 int launch_multi_step(fpm_plan* p, const GeomArgs& ga, fpm_state* s, const fpm_geometry* geo,
                       const fpm_hparams* hp, const int32_t* leds, int B, const float* A,
-                      MultiParams* cur, MultiParams* next, hipStream_t st) {
+                      MultiParams* cur, MultiParams* next, SubSlot* sub_cur, bool pre,
+                      SubSlot* sub_next, const int32_t* leds_next, int B_next, hipStream_t st) {
   const Grids g = grids_of<N>(p, B);
   const Batch bt = batch_of(p, leds, B);
   const Disk dk = disk_of(p);
@@ -595,7 +602,8 @@ int launch_multi_step(fpm_plan* p, const GeomArgs& ga, fpm_state* s, const fpm_g
     Timed tm(p, kRowsForward, st);
     for (int r = 0; r < tm.reps; ++r)
       rows_forward_sub<N><<<g.sub_fwd_rows(), SubFwdRow<N>::threads, 0, st>>>(
-          O, P, bt, dk, ga, geom, p->oob_ws, p->sub, g.sub_fwd_chunks, p->X, p->twN);
+          O, P, bt, dk, ga, geom, p->oob_ws, sub_cur, pre ? sub_cur : nullptr, g.sub_fwd_chunks,
+          p->X, p->twN);
   }
   {
     Timed tm(p, kCols, st);
@@ -608,7 +616,7 @@ int launch_multi_step(fpm_plan* p, const GeomArgs& ga, fpm_state* s, const fpm_g
     Timed tm(p, kRowsBackward, st);
     for (int r = 0; r < tm.reps; ++r)
       rows_backward_sub<N><<<g.sub_bwd_rows(), SubBwdThreads<N>::value, 0, st>>>(
-          p->X, O, P, bt, dk, pg, p->sub, g.sub_bwd_chunks, row_part, p->kappa_tab, p->twN);
+          p->X, O, P, bt, dk, pg, sub_cur, g.sub_bwd_chunks, row_part, p->kappa_tab, p->twN);
   }
   const int t = s->t + 1;
   const double b1 = hp->beta1, b2 = hp->beta2;
@@ -627,7 +635,10 @@ int launch_multi_step(fpm_plan* p, const GeomArgs& ga, fpm_state* s, const fpm_g
   a.X = p->X;
   a.bt = bt;
   a.dk = dk;
-  a.sub = p->sub;
+  a.sub = sub_cur;
+  a.next_sub = sub_next;
+  if (sub_next) a.bt_next = batch_of(p, leds_next, B_next);
+  a.ga = ga;
   a.loss_part = col_part;
   a.n_loss = g.cols();
   a.loss = s->loss;
@@ -821,7 +832,7 @@ int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** ou
         (rc = upload<float2>(&p->device_bytes, &p->P_ws, nullptr, (size_t)p->N * p->N)) ||
         (rc = upload<int>(&p->device_bytes, &p->oob_ws, nullptr, 1)) ||
         (rc = upload<MultiParams>(&p->device_bytes, &p->mpar, nullptr, 2)) ||
-        (rc = upload<SubSlot>(&p->device_bytes, &p->sub, nullptr, (size_t)p->max_batch)) ||
+        (rc = upload<SubSlot>(&p->device_bytes, &p->sub, nullptr, 2 * (size_t)p->max_batch)) ||
         (rc = upload<int>(&p->device_bytes, &p->tile_flags, nullptr, tile_capacity(p)))) {
       plan_free(p);
       return rc;
@@ -1212,10 +1223,14 @@ int fpm_run_multi(fpm_plan* p, const fpm_led_grid* grid, fpm_state* s, fpm_geome
   for (int i = 0; i < n_steps; ++i) {
     MultiParams* cur = p->mpar + (i & 1);
     MultiParams* next = p->mpar + ((i + 1) & 1);
+    SubSlot* sub_cur = p->sub + (size_t)(i & 1) * p->max_batch;
+    const bool has_next = i + 1 < n_steps;
+    SubSlot* sub_next = has_next ? p->sub + (size_t)((i + 1) & 1) * p->max_batch : nullptr;
     const int B = batch_sizes[i];
     const int rc = with_lr_size(p->N, [&](auto n) {
-      return launch_multi_step<decltype(n)::value>(p, ga, s, geo, hp, leds + off, B, meas_amp,
-                                                   cur, next, st);
+      return launch_multi_step<decltype(n)::value>(
+          p, ga, s, geo, hp, leds + off, B, meas_amp, cur, next, sub_cur, i > 0, sub_next,
+          has_next ? leds + off + B : nullptr, has_next ? batch_sizes[i + 1] : 0, st);
     });
     if (rc) return rc;
     off += (size_t)B;

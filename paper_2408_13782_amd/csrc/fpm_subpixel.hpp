@@ -32,6 +32,7 @@ struct SubSlot {
   int fr, fc;
   float ay, ax;
   double J[8];
+  int clamped;   // the window was clamped into the HR grid
 };
 
 // LED-array geometry (nominal grid plus learned errors) and optics constants.
@@ -127,8 +128,8 @@ template <int N>
 __global__ void __launch_bounds__(SubFwdRow<N>::threads)
 rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Batch bt, Disk dk,
                  GeomArgs ga, const double* __restrict__ geom, int* __restrict__ oob,
-                 SubSlot* __restrict__ sub_out, int chunks, float2* __restrict__ X,
-                 const float2* __restrict__ tw) {
+                 SubSlot* __restrict__ sub_out, const SubSlot* __restrict__ pre, int chunks,
+                 float2* __restrict__ X, const float2* __restrict__ tw) {
   constexpr int T = SubFwdRow<N>::T;
   constexpr int E = N / T;
   constexpr int L = SubFwdRow<N>::threads / T;
@@ -156,13 +157,21 @@ rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Bat
 #pragma unroll
   for (int m = 0; m < E; ++m) pv[m] = prow[min(max(half_shift<N>(t + m * T), ext.x), ext.y)];
   __shared__ int4 slot;   // fr, fc and the bits of ay, ax
-  if (threadIdx.x < 64) {
+  if (pre) {
+    // derived by the previous step's update kernel from the same geometry
+    if (threadIdx.x == 0) {
+      const SubSlot& s0 = pre[b];
+      slot = make_int4(s0.fr, s0.fc, __float_as_int(s0.ay), __float_as_int(s0.ax));
+      if (c == 0 && s0.clamped && oob) atomicAdd(oob, 1);
+    }
+  } else if (threadIdx.x < 64) {
     bool clamped;
-    const SubSlot s0 = subslot_of(ga, geom, bt, b, &clamped);
+    SubSlot s0 = subslot_of(ga, geom, bt, b, &clamped);
     if (threadIdx.x == 0) {
       slot = make_int4(s0.fr, s0.fc, __float_as_int(s0.ay), __float_as_int(s0.ax));
       if (c == 0) {
         if (clamped && oob) atomicAdd(oob, 1);
+        s0.clamped = clamped;
         sub_out[b] = s0;   // for the later kernels of the call
       }
     }
@@ -550,6 +559,8 @@ struct MultiUpdateArgs {
   int learn_geom; double lr_geom[4];
   double* g_par; double* g_geom;      // diagnostics, += (nullable)
   PupilGeom pg; float2* P;
+  // the next step's batch: its slot offsets from the new geometry (nullable)
+  SubSlot* next_sub; Batch bt_next; GeomArgs ga;
 };
 
 // Last launch of a fused multi-parameter step:
@@ -559,7 +570,8 @@ struct MultiUpdateArgs {
 //  pupil workgroups: sum the moment and offset-gradient partials in a fixed
 //    order, Adam on the Zernike coefficients, defocus and geometry (all of
 //    them compute the same numbers, workgroup 0 writes the next parameter
-//    block), rebuild their share of the pupil;
+//    block and, with next_sub, the next step's slot offsets derived from the
+//    new geometry), rebuild their share of the pupil;
 //  the workgroup after them: adds the batch loss to *loss.
 template <int N>
 __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
@@ -700,6 +712,13 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
       a.next->m_g[k] = nextg[1][k];
       a.next->v_g[k] = nextg[2][k];
       if (a.g_geom) a.g_geom[k] += gg[k];
+    }
+    // the next step's forward row pass reads these instead of deriving them
+    if (a.next_sub && i < a.bt_next.B) {
+      bool clamped;
+      SubSlot sl = subslot_of(a.ga, nextg[0], a.bt_next, i, &clamped);
+      sl.clamped = clamped;
+      a.next_sub[i] = sl;
     }
   }
   // rebuild this workgroup's rows of the pupil from the new parameters

@@ -397,8 +397,14 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
 // High-resolution 2-D transforms, split into a row pass and a column pass.
 
 template <int M> struct HrRowLines { static constexpr int value = (128 / Plan1D<M>::T) > 0 ? 128 / Plan1D<M>::T : 1; };
-// columns per workgroup of the HR column pass: M x (L + 1) complex slots of LDS
+// columns per workgroup of the HR column pass: M x HrColStride complex slots of LDS
 template <int M> struct HrColLines { static constexpr int value = M > 1024 ? 8 : 16; };
+// LDS slots between consecutive elements of one column: one padding slot,
+// none at M = 2048 (8 columns of 128 threads), where by a model of 32 banks
+// and 16 lanes per 8-byte access one slot of padding doubles the cycles of
+// the exchanges (the bank-conflict counter read 50 % of the pass's LDS cycles)
+// and none costs 1.25 times the conflict-free cycles.
+template <int M> struct HrColStride { static constexpr int value = HrColLines<M>::value + (M == 2048 ? 0 : 1); };
 
 enum HrRowMode { kRowFwd = 0, kRowInv = 1, kRowInit = 2, kRowRefocus = 3 };
 
@@ -486,7 +492,8 @@ hr_cols(float2* __restrict__ data, const float2* __restrict__ tw) {
   constexpr int T = Plan1D<M>::T;
   constexpr int E = M / T;
   constexpr int L = HrColLines<M>::value;
-  __shared__ float2 lds[M * (L + 1)];
+  constexpr int S = HrColStride<M>::value;
+  __shared__ float2 lds[M * S];
   const int line = threadIdx.x % L, t = threadIdx.x / L;
   const int x = blockIdx.x * L + line;
   data += (size_t)blockIdx.y * M * M;   // transform y of a batch
@@ -496,7 +503,7 @@ hr_cols(float2* __restrict__ data, const float2* __restrict__ tw) {
     const int n = t + m * T;
     v[m] = data[(size_t)(DIR > 0 ? half_shift<M>(n) : n) * M + x];
   }
-  auto lay = [line](int n) { return n * (L + 1) + line; };
+  auto lay = [line](int n) { return n * S + line; };
   Plan1D<M>::template run<DIR>(v, t, lds, lay, tw);
   constexpr float inv = 1.0f / M;
 #pragma unroll

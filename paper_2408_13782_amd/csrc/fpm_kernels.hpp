@@ -316,9 +316,10 @@ __device__ __forceinline__ void row_moment_partials(float (&sv)[6], int row0, co
 // Sum K per-thread values over the workgroup; thread k < K stores total k into
 // part[blockIdx.x * K + k]. Fixed summation order. No ordering with other
 // workgroups is implied.
-template <int K, class V>
+// kWaves: the most waves a workgroup of the caller has (sizes the LDS buffer).
+template <int K, int kWaves = 16, class V>
 __device__ __forceinline__ void block_partials(const V* vals, double* part) {
-  __shared__ double wsum[16][K];
+  __shared__ double wsum[kWaves][K];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int nwaves = (blockDim.x + 63) >> 6;
 #pragma unroll

@@ -288,7 +288,9 @@ rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
       acc[17] = GX;
     }
   }
-  block_partials<kSubPar>(acc, part);
+  // (a buffer for this workgroup's waves only: at N = 512 the pass then fits
+  // four workgroups per CU in LDS instead of three)
+  block_partials<kSubPar, (kThreads + 63) / 64>(acc, part);
   FPM_PROBE(2, 3);
 }
 

@@ -42,10 +42,10 @@ TRAFFIC = {
     ("paper", "cols"): (4452.1 * 2 + 4843.4) * 1024,
     ("paper", "rows_backward"): (4458.4 * 2 + 2450.0) * 1024,
     ("paper", "update"): (7238.3 * 2 + 9754.3) * 1024,
-    ("large", "rows_forward"): (13206.5 * 2 + 39713.7) * 1024,
-    ("large", "cols"): (36173.0 * 2 + 39812.2) * 1024,
-    ("large", "rows_backward"): (34147.9 * 2 + 19470.9) * 1024,
-    ("large", "update"): (45777.9 * 2 + 57628.2) * 1024,
+    ("large", "rows_forward"): (13206.3 * 2 + 39713.7) * 1024,
+    ("large", "cols"): (36173.0 * 2 + 39817.2) * 1024,
+    ("large", "rows_backward"): (33152.6 * 2 + 19470.9) * 1024,
+    ("large", "update"): (45758.7 * 2 + 57628.2) * 1024,
 }
 
 

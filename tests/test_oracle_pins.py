@@ -538,3 +538,115 @@ def test_intensity_and_amplitude_gradients_agree_in_direction_near_the_truth():
     gi = fo.loss_and_grads(O2, P, shifts, [0, 1, 2], A, gamma, loss="intensity").g_O
     cos = np.real(np.vdot(ga, gi)) / (np.linalg.norm(ga) * np.linalg.norm(gi))
     assert cos > 0.5
+
+
+# ---------------------------------------------------------------------------
+# Pupil phase (Eq. 3): its defocus term and its Zernike terms tied to facts
+# outside pupil() itself
+
+
+def test_defocus_pupil_equals_refocused_object_through_the_plain_pupil():
+    """Centre LED: the field through mask exp(i z kappa) equals the field of the
+    object refocused by z (angular spectrum, pinned by the plane-wave test) seen
+    through the plain pupil mask, low-passed and decimated with explicit DFT sums."""
+    opt = small_optics(n=8, s=4)
+    m, n = opt.m_hr, opt.n_lr
+    o = fo.transmission(*inputs.truth_object(m, seed=12))
+    O = fo.spectrum(o)
+    mask = fo.pupil_mask(opt)
+    zern = fo.zernike_basis(opt)
+    kappa = fo.defocus_phase_per_um(opt)
+    for z in (-25.0, 6.5, 40.0):
+        P = fo.pupil(mask, zern, np.zeros(15), z, kappa)
+        got = fo.lr_field(O, P, (0, 0))
+        oz = fo.refocus(O, [z], opt)[0]
+        want = _brute_force_lr_field(oz, mask.astype(complex), (0, 0), opt.upsample)
+        np.testing.assert_allclose(got, want, atol=1e-11 * np.abs(want).max())
+        # the wrong sign of z kappa would not match
+        bad = fo.lr_field(O, fo.pupil(mask, zern, np.zeros(15), -z, kappa), (0, 0))
+        assert np.abs(bad - want).max() > 1e-3 * np.abs(want).max()
+
+
+@pytest.mark.parametrize("j,axis", [(1, 0), (2, 1)])
+@pytest.mark.parametrize("d", [1, -3])
+def test_tilt_zernike_shifts_the_field_by_whole_pixels(j, axis, d):
+    """Z_1 = 2 y/R and Z_2 = 2 x/R (OSA, unit RMS): with c = pi R d / N the pupil
+    carries the phase ramp 2 pi d u / N, which moves the LR field by d pixels
+    along that axis (the DFT shift theorem), so psi_c = roll(psi_0, -d)."""
+    opt = small_optics(n=32, s=4)
+    m, n = opt.m_hr, opt.n_lr
+    O = fo.spectrum(fo.transmission(*inputs.truth_object(m, seed=13)))
+    mask = fo.pupil_mask(opt)
+    zern = fo.zernike_basis(opt)
+    kappa = fo.defocus_phase_per_um(opt)
+    base = np.linspace(-0.3, 0.2, 15)
+    base[1] = base[2] = 0.0
+    c = base.copy()
+    c[j] = math.pi * opt.pupil_radius_px * d / n
+    for shift in [(0, 0), (3, -2)]:
+        psi0 = fo.lr_field(O, fo.pupil(mask, zern, base, 1.5, kappa), shift)
+        psi = fo.lr_field(O, fo.pupil(mask, zern, c, 1.5, kappa), shift)
+        np.testing.assert_allclose(psi, np.roll(psi0, -d, axis=axis),
+                                   atol=1e-12 * np.abs(psi0).max())
+
+
+def test_step_matches_torch_autograd_and_adam():
+    """Three steps of the oracle's step() (object, Zernike 1..14 and defocus
+    learned; piston held) against a torch float64 model: the loss of Eqs. 3 and
+    5 written with torch.fft, its gradients by autograd, and torch.optim.Adam
+    over the three parameter groups with their own learning rates."""
+    torch = pytest.importorskip("torch")
+    opt = small_optics(n=16, s=4)
+    m, n = opt.m_hr, opt.n_lr
+    O0 = fo.spectrum(fo.transmission(*inputs.truth_object(m, seed=14)))
+    mask = fo.pupil_mask(opt)
+    zern = fo.zernike_basis(opt)
+    kappa = fo.defocus_phase_per_um(opt)
+    k = fo.led_wavevectors(opt, 5, 4.0, 90.0)
+    shifts = fo.nearest_shifts(fo.led_shifts(opt, k))
+    c_true = np.linspace(0.1, -0.2, 15)
+    A = fo.forward_amplitudes(fo.spectrum(fo.transmission(*inputs.truth_object(m, seed=15))),
+                              fo.pupil(mask, zern, c_true, 3.0, kappa), shifts, range(25))
+    c0 = np.linspace(-0.05, 0.07, 15)
+    cfg = fo.SolveConfig(lr_object=2e-2, lr_zernike=3e-2, lr_z=0.2, learn_pupil=True,
+                         learn_z=True)
+    batches = [[0, 7, 12, 18], [24, 3, 11, 6], [2, 12, 20, 9]]
+
+    st = fo.init_state(O0, coeffs0=c0, z0=-1.0)
+    for leds in batches:
+        fo.step(st, cfg, mask, zern, kappa, shifts, leds, A)
+
+    tO = torch.tensor(O0, dtype=torch.complex128, requires_grad=True)
+    tc = torch.tensor(c0[1:], dtype=torch.float64, requires_grad=True)
+    tz = torch.tensor([-1.0], dtype=torch.float64, requires_grad=True)
+    piston = torch.tensor(c0[0], dtype=torch.float64)
+    tzern = torch.tensor(zern)
+    tkap = torch.tensor(kappa)
+    tmask = torch.tensor(mask.astype(np.float64))
+    tA = torch.tensor(A)
+    adam = torch.optim.Adam([{"params": [tO], "lr": cfg.lr_object},
+                             {"params": [tc], "lr": cfg.lr_zernike},
+                             {"params": [tz], "lr": cfg.lr_z}])
+    base = m // 2 - n // 2
+    for leds in batches:
+        adam.zero_grad()
+        theta = piston * tzern[0] + torch.tensordot(tc, tzern[1:], dims=1) + tz[0] * tkap
+        P = tmask * torch.exp(1j * theta)
+        loss = torch.zeros((), dtype=torch.float64)
+        for led in leds:
+            r0, c0w = base + int(shifts[led][0]), base + int(shifts[led][1])
+            phi = tO[r0:r0 + n, c0w:c0w + n] * P
+            psi = (n * n / m) * torch.fft.ifft2(torch.fft.ifftshift(phi))
+            loss = loss + torch.sum((torch.abs(psi) - tA[led]) ** 2)
+        loss.backward()
+        adam.step()
+
+    np.testing.assert_allclose(st.O, tO.detach().numpy(), atol=1e-12)
+    np.testing.assert_allclose(st.coeffs[1:], tc.detach().numpy(), atol=1e-12)
+    assert st.coeffs[0] == c0[0]
+    assert abs(st.z_um - float(tz.detach()[0])) <= 1e-12
+    assert st.t == 3
+    # the updates are large enough that a wrong order or learning rate would show
+    assert np.abs(st.O - O0).max() > 2 * cfg.lr_object
+    assert np.median(np.abs(st.coeffs[1:] - c0[1:])) > 0.5 * cfg.lr_zernike
+    assert abs(st.z_um + 1.0) > 0.5 * cfg.lr_z

@@ -10,11 +10,19 @@ data (seeded smooth random object, Poisson noise 1e4 / 1e2 photons for
 bright / dark field). Inputs are resident in HBM before timing starts.
 
 Prints one JSON line (rank 0):
-  value        LED-images per second (fwd + bwd + update), whole job
-  roofline     the dominant kernel: algorithmic work per launch / its mean
-               duration (HIP events on the launch stream around 20 back-to-back
-               launches on a step's operands) vs MI355X peak
+  value        LED-images per second through whole steps (the fwd+bwd chain,
+               Adam on the spectrum, the pupil-parameter update), timed over
+               the K steps; `fwd_bwd` gives the chain alone
+  roofline     the fwd+bwd chain (rows_forward + cols + rows_backward): its
+               algorithmic bytes per batch, (16 |S| + 4 N^2) B, over the sum of
+               the three kernels' mean durations (HIP events on the launch
+               stream around 20 back-to-back launches of each on a step's
+               operands) vs the HBM peak; every kernel's own figures in
+               detail.kernels. `traffic` is what the rocprofv3 counters of
+               profiles/hbm_traffic.md measured, if they were taken on the
+               loaded build (fpm_build_tag), else null
   cpu_baseline the FP64 oracle's steps on the same workload, host cores
+               (scipy.fft worker threads; numpy one thread beside it)
 """
 from __future__ import annotations
 
@@ -33,20 +41,25 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP32_VALU_PEAK_TFLOPS = 78.6   # 256 CU x 64 lanes x 2 (FMA) x 2.4 GHz, no packed FP32
 
 
-# HBM bytes per launch of a kernel from rocprofv3 counters (FETCH_SIZE x 2 +
-# WRITE_SIZE; the factor 2 is what a plain device copy of known size reads on
-# the same counter), for the kernel build they were taken on. The large
-# workload's kernels are those of the fused multi-parameter step.
-TRAFFIC = {
-    ("paper", "rows_forward"): (1920.5 * 2 + 4788.7) * 1024,
-    ("paper", "cols"): (4452.1 * 2 + 4843.4) * 1024,
-    ("paper", "rows_backward"): (4458.4 * 2 + 2450.0) * 1024,
-    ("paper", "update"): (7238.3 * 2 + 9754.3) * 1024,
-    ("large", "rows_forward"): (13206.3 * 2 + 39713.7) * 1024,
-    ("large", "cols"): (36173.0 * 2 + 39817.2) * 1024,
-    ("large", "rows_backward"): (33152.6 * 2 + 19470.9) * 1024,
-    ("large", "update"): (45758.7 * 2 + 57628.2) * 1024,
-}
+def load_traffic(workload: str, build_tag: str):
+    """HBM bytes per launch of each step kernel from the committed rocprofv3
+    counter summary (profiles/hbm_traffic.md: FETCH_SIZE and WRITE_SIZE in KiB per
+    dispatch, with the counts a device copy of known size reads on them), or None
+    if those counters were taken on another build of the library."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.md")
+    try:
+        text = open(path).read()
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        data = json.loads(block)
+    except (OSError, IndexError, ValueError):
+        return None
+    if data.get("build") != build_tag or workload not in data.get("workloads", {}):
+        return None
+    cal = data["calibration"]
+    f_fetch = cal["copy_read_kib"] / cal["fetch_kib"]     # bytes read per FETCH_SIZE unit
+    f_write = cal["copy_written_kib"] / cal["write_kib"]
+    return {k: (v["fetch_kib"] * f_fetch + v["write_kib"] * f_write) * 1024.0
+            for k, v in data["workloads"][workload].items()}
 
 
 def log(msg):
@@ -90,11 +103,31 @@ def kernel_work(plan, B: int):
     }, U
 
 
+def host_cpu() -> dict:
+    """The host's CPU model and the cores this process may run on."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"model": model, "cpu_count": os.cpu_count(), "usable_cores": usable}
+
+
 def cpu_baseline(w, seconds: float):
-    """Time the FP64 oracle's full steps on the same workload (bounded sample).
+    """Time the FP64 oracle's full steps on the same workload (bounded samples).
 
     The oracle builds its own inputs (truth object, measurements through its
     forward model, seeded Poisson noise, initial value); set-up is not timed.
+    Two modes: its 2-D FFTs on scipy.fft with one worker thread per usable core
+    (the reported value), and numpy's single-threaded FFT.
     """
     import numpy as np
     from oracle import fpm_oracle as fo
@@ -115,19 +148,34 @@ def cpu_baseline(w, seconds: float):
     O0 = fo.initial_spectrum(A[centre], w.upsample)
     cfg = fo.SolveConfig(lr_object=w.lr_object, lr_zernike=w.lr_zernike, lr_z=w.lr_z,
                          learn_pupil=w.learn_zernike, learn_z=w.learn_z)
-    st = fo.init_state(O0)
     perms = inputs.led_permutations(w.n_led, 12, seed=0)
     sched = fo.batches_from_permutations(perms, w.batch)
-    n_img, n_steps = 0, 0
-    t0 = time.perf_counter()
-    while n_steps < len(sched) and (time.perf_counter() - t0 < seconds or n_steps < 3):
-        fo.step(st, cfg, mask, zern, kappa, shifts, sched[n_steps], A)
-        n_img += len(sched[n_steps])
-        n_steps += 1
-    dt = time.perf_counter() - t0
-    return {"value": n_img / dt, "unit": "LED-images/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_steps} full FP64 steps ({n_img} LED-images) of the same workload, "
-                      f"numpy single thread, {dt:.1f} s"}
+    host = host_cpu()
+
+    def timed_steps(workers):
+        fo.set_fft_workers(workers)
+        st = fo.init_state(O0)
+        n_img, n_steps = 0, 0
+        t0 = time.perf_counter()
+        while n_steps < len(sched) and (time.perf_counter() - t0 < seconds or n_steps < 3):
+            fo.step(st, cfg, mask, zern, kappa, shifts, sched[n_steps], A)
+            n_img += len(sched[n_steps])
+            n_steps += 1
+        dt = time.perf_counter() - t0
+        fo.set_fft_workers(1)
+        return n_img / dt, n_steps, n_img, dt
+
+    workers = host["usable_cores"]
+    v_mt, s_mt, i_mt, t_mt = timed_steps(workers)
+    v_1, s_1, i_1, t_1 = timed_steps(1)
+    return {"value": v_mt, "unit": "LED-images/s", "cores": workers, "kind": "oracle",
+            "sample": f"{s_mt} full FP64 steps ({i_mt} LED-images) of the same workload, "
+                      f"2-D FFTs on scipy.fft with {workers} worker threads (the rest of the "
+                      f"oracle's numpy arithmetic on one thread), {t_mt:.1f} s",
+            "host": host,
+            "single_thread": {"value": v_1, "unit": "LED-images/s", "cores": 1,
+                              "sample": f"{s_1} full FP64 steps ({i_1} LED-images), numpy.fft, "
+                                        f"one thread, {t_1:.1f} s"}}
 
 
 def _psnr(x, ref) -> float:
@@ -135,14 +183,6 @@ def _psnr(x, ref) -> float:
     mse = float(np.mean((x - ref) ** 2))
     peak = float(np.max(np.abs(ref)))
     return float("inf") if mse == 0 else 10.0 * math.log10(peak * peak / mse)
-
-
-def ring_order(prob) -> "np.ndarray":
-    """LEDs from the centre outwards (by |k|, then by angle): the fixed order of
-    the sequential one-image-per-update baseline (Eq. 7)."""
-    import numpy as np
-    k = prob.k
-    return np.lexsort((np.arctan2(k[:, 0], k[:, 1]), np.round(np.hypot(k[:, 0], k[:, 1]), 9)))
 
 
 def multiparam_rate(w, prob, steps: int) -> dict:
@@ -223,7 +263,7 @@ def batch_sweep(w, batches, epochs: int, log) -> dict:
         if mode != "sequential":
             perms = inputs.led_permutations(w.n_led, epochs, seed=0)
         else:
-            perms = np.tile(ring_order(prob), (epochs, 1)).astype(np.int32)
+            perms = np.tile(inputs.centre_out_order(prob.k), (epochs, 1)).astype(np.int32)
         per_epoch = -(-w.n_led // B)
         sched = problem.flatten_schedule(problem.schedule(perms, B))
         st = fpm.State(plan, O0)
@@ -263,16 +303,22 @@ def main():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="after timing, one device-to-device copy of this size (a kernel of "
                          "known traffic for calibrating HBM counters)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="seconds of oracle steps per CPU-baseline mode")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch-sweep", type=int, nargs="*", default=None,
                     help="instead of the throughput line: quality vs time for these batch "
                          "sizes and the sequential loop (e.g. --batch-sweep 1 8 16 40 0; "
                          "0 = all LEDs, the full gradient)")
     ap.add_argument("--sweep-epochs", type=int, default=30)
-    ap.add_argument("--serving-requests", type=int, default=150,
-                    help="requests of the tile-serving latency measurement at rho = 0.9 "
+    ap.add_argument("--serving-requests", type=int, default=2000,
+                    help="requests per arrival rate of the tile-serving latency measurement "
                          "(0: skip)")
+    ap.add_argument("--serving-rates", type=float, nargs="+", default=[0.5, 0.9, 1.5],
+                    help="arrival rates as multiples of the sequential service rate")
+    ap.add_argument("--no-detail-sweep", dest="sweep_in_detail", action="store_false",
+                    help="skip the reduced batch-size sweep in the line's detail")
+    ap.add_argument("--detail-sweep-epochs", type=int, default=5)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -368,31 +414,35 @@ def main():
     plan.timing_repeat(None, 1)
     log("per-kernel mean us: " + ", ".join(f"{k}={v * 1e3:.2f}" for k, v in timed.items()))
     B = w.batch
-    dominant = max(timed, key=lambda k: timed[k])
-    bytes_, flops = work[dominant]
-    dur_s = timed[dominant] / 1e3
-    ridge = FP32_VALU_PEAK_TFLOPS * 1e12 / (HBM_PEAK_GBS * 1e9)     # flop per byte
-    if flops / bytes_ > ridge:
-        achieved = flops / dur_s / 1e12
-        roof = {"bound": "alu", "achieved": achieved, "peak": FP32_VALU_PEAK_TFLOPS,
-                "unit": "TFLOP/s", "frac": achieved / FP32_VALU_PEAK_TFLOPS,
-                "traffic": TRAFFIC.get((w.name, dominant)), "kernel": dominant,
-                "mean_us": timed[dominant] * 1e3,
-                "hbm_algorithmic_GBs": bytes_ / dur_s / 1e9}
-    else:
-        achieved = bytes_ / dur_s / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": TRAFFIC.get((w.name, dominant)),
-                "kernel": dominant, "mean_us": timed[dominant] * 1e3,
-                "algorithmic_bytes": bytes_}
-    chain_ms = sum(timed.get(k, 0.0) for k in ("rows_forward", "cols", "rows_backward"))
+    traffic = load_traffic(w.name, fpm.build_tag())
+    kernels = {}
+    for k, (bytes_, flops) in work.items():
+        dur_s = timed[k] / 1e3
+        kernels[k] = {"mean_us": timed[k] * 1e3, "algorithmic_bytes": bytes_, "flops": flops,
+                      "hbm_frac": bytes_ / dur_s / 1e9 / HBM_PEAK_GBS,
+                      "valu_frac": flops / dur_s / 1e12 / FP32_VALU_PEAK_TFLOPS,
+                      "traffic": traffic.get(k) if traffic else None}
+    # the headline roofline: the fwd+bwd chain (a3-a7) of one batch
+    chain = ("rows_forward", "cols", "rows_backward")
+    chain_s = sum(timed[k] for k in chain) / 1e3
     S, N = plan.info.support_px, plan.N
     chain_bytes = (16.0 * S + 4.0 * N * N) * B
+    chain_flops = sum(work[k][1] for k in chain)
+    achieved = chain_bytes / chain_s / 1e9
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": sum(traffic[k] for k in chain) if traffic else None,
+            "kernel": "rows_forward + cols + rows_backward (the fwd+bwd chain of one batch)",
+            "mean_us": chain_s * 1e6, "algorithmic_bytes": chain_bytes,
+            "valu_tflops": chain_flops / chain_s / 1e12,
+            "valu_frac": chain_flops / chain_s / 1e12 / FP32_VALU_PEAK_TFLOPS,
+            "build": fpm.build_tag()}
+    fwd_bwd = {"led_images_per_s": B / chain_s, "us_per_batch": chain_s * 1e6,
+               "timing": "sum of the three chain kernels' mean durations (HIP events on the "
+                         "launch stream around 20 back-to-back launches of each)"}
     detail = {
-        "fwd_bwd_us_per_batch": chain_ms * 1e3,
-        "fwd_bwd_led_images_per_s": B / (chain_ms / 1e3),
-        "fwd_bwd_hbm_frac": chain_bytes / (chain_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
-        "per_kernel_mean_us": {k: v * 1e3 for k, v in timed.items()},
+        "kernels": kernels,
+        "step_us_from_kernels": sum(timed.values()) * 1e3,
         "support_px": S, "union_px": U,
     }
     if not w.learn_geometry:
@@ -412,10 +462,14 @@ def main():
     detail["refocus_16z_ms"] = r0.elapsed_time(r1) / 5
     del foc
 
+    metric = ("LED-images fwd+bwd/sec (256²→1024²); HBM roofline %; tile p50/p99 ms"
+              if w.name == "paper" else f"LED-images fwd+bwd/sec ({w.n_lr}²→{w.m_hr}²)")
     result = {
-        "metric": "LED-images fwd+bwd/sec (256²→1024²)" if w.name == "paper" else
-                  f"LED-images fwd+bwd/sec ({w.n_lr}²→{w.m_hr}²)",
-        "value": value, "unit": "LED-images/s", "n_gpus": 1, "steps": args.steps,
+        "metric": metric,
+        "value": value, "unit": "LED-images/s",
+        "value_is": "LED-images through whole random-batch steps (fwd+bwd chain, Adam on the "
+                    "spectrum, pupil-parameter update) per second over the timed steps",
+        "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"{w.name}: {w.n_side}x{w.n_side} LEDs, {w.n_lr}^2 LR -> "
@@ -425,30 +479,46 @@ def main():
                                + (" + LED-array geometry (fused multi-parameter step)"
                                   if w.learn_geometry else ""),
                    "n_led": w.n_led, "n_lr": w.n_lr, "m_hr": w.m_hr, "batch": w.batch},
+        "fwd_bwd": fwd_bwd,
         "roofline": roof,
         "detail": detail,
     }
     if args.serving_requests > 0:
         from paper_2408_13782_amd import serving
-        log(f"tile serving: {args.serving_requests} requests at 0.9 x the sequential rate")
-        sres = serving.measure(rates=(0.9,), n_requests=args.serving_requests, lanes=4,
+        rates = tuple(args.serving_rates)
+        log(f"tile serving: {args.serving_requests} requests at rho = {rates} x the "
+            "sequential rate")
+        sres = serving.measure(rates=rates, n_requests=args.serving_requests, lanes=4,
                                calib_requests=40, log=log)
-        row = sres["rates"][0]
+        rows = []
+        for row in sres["rates"]:
+            rows.append({"rho": row["rho"], "arrival_rate_per_s": row["rate_per_s"],
+                         "p50_ms": row["server"]["p50_ms"], "p99_ms": row["server"]["p99_ms"],
+                         "requests_per_s": row["server"]["requests_per_s"],
+                         "sequential_p50_ms": row["sequential"]["p50_ms"],
+                         "sequential_p99_ms": row["sequential"]["p99_ms"],
+                         "sequential_requests_per_s": row["sequential"]["requests_per_s"]})
         result["serving"] = {
             "workload": "Poisson stream of tile solves, N in {128,192,256,384,512}, "
                         "7x7/11x11/15x15 LEDs, 4x upsampling, 20 epochs of B=16, "
                         "object + Zernike pupil",
-            "requests": args.serving_requests, "rho": row["rho"],
-            "arrival_rate_per_s": row["rate_per_s"], "mu_seq_per_s": sres["mu_seq_per_s"],
-            "lanes": sres["lanes"],
-            "p50_ms": row["server"]["p50_ms"], "p99_ms": row["server"]["p99_ms"],
-            "requests_per_s": row["server"]["requests_per_s"],
-            "sequential_p50_ms": row["sequential"]["p50_ms"],
-            "sequential_p99_ms": row["sequential"]["p99_ms"],
-            "sequential_requests_per_s": row["sequential"]["requests_per_s"],
+            "requests_per_rate": args.serving_requests, "mu_seq_per_s": sres["mu_seq_per_s"],
+            "lanes": sres["lanes"], "sequential": "the same server with one lane (FIFO, one "
+                                                  "request at a time)",
+            "rates": rows,
         }
+    if args.sweep_in_detail:
+        log("reduced batch-size sweep (B = 1, 16, all; sequential order), "
+            f"{args.detail_sweep_epochs} epochs")
+        sw = batch_sweep(w, [1, w.batch, 0], args.detail_sweep_epochs, log)
+        detail["batch_sweep"] = {
+            "epochs": sw["epochs"],
+            "runs": [{"mode": r["mode"], "batch": r["batch"],
+                      "ms_per_epoch": r["ms_per_epoch"],
+                      "amp_psnr_db": r["amp_psnr_db"], "phase_psnr_db": r["phase_psnr_db"]}
+                     for r in sw["runs"]]}
     if not args.no_cpu_baseline:
-        log(f"oracle CPU baseline (~{args.cpu_seconds:.0f} s)")
+        log(f"oracle CPU baseline (~{2 * args.cpu_seconds:.0f} s)")
         result["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
         log("oracle CPU baseline done")
     print(json.dumps(result), flush=True)

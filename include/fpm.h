@@ -128,6 +128,11 @@ int fpm_plan_set_loss(fpm_plan* plan, int32_t kind);
 int fpm_plan_info(const fpm_plan* plan, fpm_info* info);
 const char* fpm_strerror(int code);
 const char* fpm_last_error(void);
+/* Identification of the build: a digest of the library's sources (its HIP,
+ * C++ and C header files), fixed at compile time. Measurements taken on one
+ * build (hardware counters of its kernels) apply to another only if the tags
+ * agree. Static string, never NULL. */
+const char* fpm_build_tag(void);
 
 /* Square LED grid below the sample and its errors (Sec. 2.1; Sec. 2.2). */
 typedef struct {

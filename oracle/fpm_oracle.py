@@ -48,6 +48,30 @@ from dataclasses import dataclass
 
 import numpy as np
 
+# 2-D FFTs: numpy's (one thread) unless set_fft_workers() picks scipy.fft with
+# several worker threads (same transform, used by the CPU-baseline timing only).
+_fft_workers = 1
+
+
+def set_fft_workers(n: int) -> None:
+    """Compute the 2-D FFTs with scipy.fft on n threads (n = 1: numpy.fft)."""
+    global _fft_workers
+    _fft_workers = max(1, int(n))
+
+
+def _fft2(x):
+    if _fft_workers > 1:
+        import scipy.fft
+        return scipy.fft.fft2(x, workers=_fft_workers)
+    return np.fft.fft2(x)
+
+
+def _ifft2(x):
+    if _fft_workers > 1:
+        import scipy.fft
+        return scipy.fft.ifft2(x, workers=_fft_workers)
+    return np.fft.ifft2(x)
+
 # ---------------------------------------------------------------------------
 # Optics and LED geometry (Sec. 2.1: k_m = (sin theta_x / lambda, sin theta_y / lambda))
 # ---------------------------------------------------------------------------
@@ -239,13 +263,13 @@ def transmission(amplitude: np.ndarray, phase: np.ndarray) -> np.ndarray:
 def spectrum(o: np.ndarray) -> np.ndarray:
     """Centred, orthonormally scaled HR spectrum O = fftshift(fft2(o)) / M."""
     m = o.shape[0]
-    return np.fft.fftshift(np.fft.fft2(o)) / m
+    return np.fft.fftshift(_fft2(o)) / m
 
 
 def object_from_spectrum(O: np.ndarray) -> np.ndarray:
     """Inverse of spectrum(): o = ifft2(ifftshift(O)) * M."""
     m = O.shape[0]
-    return np.fft.ifft2(np.fft.ifftshift(O)) * m
+    return _ifft2(np.fft.ifftshift(O)) * m
 
 
 # ---------------------------------------------------------------------------
@@ -276,7 +300,7 @@ def lr_field(O: np.ndarray, P: np.ndarray, shift) -> np.ndarray:
     n = P.shape[0]
     m = O.shape[0]
     phi = crop(O, n, shift) * P
-    return (n * n / m) * np.fft.ifft2(np.fft.ifftshift(phi))
+    return (n * n / m) * _ifft2(np.fft.ifftshift(phi))
 
 
 def forward_amplitudes(O, P, shifts, leds, gamma=None) -> np.ndarray:
@@ -349,7 +373,7 @@ def loss_and_grads(O, P, shifts, leds, meas_amp, gamma=None, loss: str = "amplit
     for b, led in enumerate(leds):
         rows, cols = window_indices(m, n, shifts[led])
         C = O[np.ix_(rows, cols)]
-        psi = (n * n / m) * np.fft.ifft2(np.fft.ifftshift(C * P))
+        psi = (n * n / m) * _ifft2(np.fft.ifftshift(C * P))
         gb = 1.0 if gamma is None else float(gamma[led])
         lb, g_psi, g_gamma[b] = residual(psi, meas_amp[led], gb, loss)
         total += lb
@@ -365,7 +389,7 @@ def field_adjoint(g_psi, P, C, m):
     g_Phi = (1/M) fftshift(fft2(g_psi)); returns (conj(P) g_Phi, conj(C) g_Phi),
     the gradients with respect to the cropped spectrum and the pupil.
     """
-    g_phi = np.fft.fftshift(np.fft.fft2(g_psi)) / m
+    g_phi = np.fft.fftshift(_fft2(g_psi)) / m
     return np.conj(P) * g_phi, np.conj(C) * g_phi
 
 
@@ -446,7 +470,7 @@ def loss_and_grads_subpixel(O, P, shifts, leds, meas_amp, gamma=None,
     total = 0.0
     for b, led in enumerate(leds):
         C, (t00, t01, t10, t11), a, r0, c0 = crop_bilinear(O, n, shifts[led])
-        psi = (n * n / m) * np.fft.ifft2(np.fft.ifftshift(C * P))
+        psi = (n * n / m) * _ifft2(np.fft.ifftshift(C * P))
         gb = 1.0 if gamma is None else float(gamma[led])
         lb, g_psi, g_gamma[b] = residual(psi, meas_amp[led], gb, loss)
         total += lb

@@ -5,6 +5,7 @@ The library is written next to this file; it is loaded by fpm.py.
 """
 from __future__ import annotations
 
+import hashlib
 import os
 import shutil
 import subprocess
@@ -32,6 +33,19 @@ HIPCC_FLAGS = [
 ]
 
 
+def source_tag() -> str:
+    """Digest of every source file of the library (csrc/ and include/), in name
+    order: the tag that fpm_build_tag() returns for a build of these sources."""
+    h = hashlib.sha256()
+    for d in (CSRC, INCLUDE):
+        for name in sorted(os.listdir(d)):
+            if name.endswith((".hip", ".hpp", ".h")):
+                h.update(name.encode())
+                with open(os.path.join(d, name), "rb") as f:
+                    h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def hipcc() -> str:
     exe = shutil.which("hipcc") or "/opt/rocm/bin/hipcc"
     if not os.path.exists(exe):
@@ -41,7 +55,7 @@ def hipcc() -> str:
 
 def build_library(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, "-I", INCLUDE, "-I", CSRC,
+    cmd = [hipcc(), *HIPCC_FLAGS, f'-DFPM_BUILD_TAG="{source_tag()}"', "-I", INCLUDE, "-I", CSRC,
            *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)

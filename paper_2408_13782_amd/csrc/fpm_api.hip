@@ -382,6 +382,7 @@ struct BackwardOut {
   ScalarState scal{};
   double* loss_part = nullptr;  // where the column pass stores its loss partials (with loss)
   double* zpart = nullptr;      // where the row pass stores its moment partials (kPatchZern)
+  float2* X = nullptr;          // row/column scratch; NULL: the plan's
 };
 
 template <int N>
@@ -391,17 +392,18 @@ int launch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t
   const Grids gr = grids_of<N>(p, B);
   const Batch bt = batch_of(p, leds, B);
   const Disk dk = disk_of(p);
+  float2* X = o.X ? o.X : p->X;
   {
     Timed tm(p, kRowsForward, st);
     for (int r = 0; r < tm.reps; ++r)
-      rows_forward<N><<<gr.fwd_rows(), FwdRow<N>::threads, 0, st>>>(O, P, bt, dk, gr.fwd_chunks, p->X,
+      rows_forward<N><<<gr.fwd_rows(), FwdRow<N>::threads, 0, st>>>(O, P, bt, dk, gr.fwd_chunks, X,
                                                            p->twN, o.commit, p->staging, o.scal);
   }
   {
     Timed tm(p, kCols, st);
     for (int r = 0; r < tm.reps; ++r)
       cols<N, false><<<gr.cols(), ColLines<N>::value * ColPlan<N>::T, 0, st>>>(
-          p->X, A, gamma, bt, dk, gr.col_groups, o.loss ? o.loss_part : nullptr, nullptr,
+          X, A, gamma, bt, dk, gr.col_groups, o.loss ? o.loss_part : nullptr, nullptr,
           nullptr, p->twN, 1.0f / p->M);
   }
   {
@@ -410,19 +412,19 @@ int launch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t
     for (int r = 0; r < tm.reps; ++r) switch (o.mode) {
       case kGradO:
         rows_backward<N, kGradO><<<gr.rows(), BwdRow<N>::threads, 0, st>>>(
-            p->X, O, P, bt, dk, pg, gr.row_chunks, gO, nullptr, nullptr, nullptr, p->twN);
+            X, O, P, bt, dk, pg, gr.row_chunks, gO, nullptr, nullptr, nullptr, p->twN);
         break;
       case kGradOP:
         rows_backward<N, kGradOP><<<gr.rows(), BwdRow<N>::threads, 0, st>>>(
-            p->X, O, P, bt, dk, pg, gr.row_chunks, gO, o.gP, nullptr, nullptr, p->twN);
+            X, O, P, bt, dk, pg, gr.row_chunks, gO, o.gP, nullptr, nullptr, p->twN);
         break;
       case kPatch:
         rows_backward<N, kPatch><<<gr.rows(), BwdRow<N>::threads, 0, st>>>(
-            p->X, O, P, bt, dk, pg, gr.row_chunks, nullptr, nullptr, nullptr, nullptr, p->twN);
+            X, O, P, bt, dk, pg, gr.row_chunks, nullptr, nullptr, nullptr, nullptr, p->twN);
         break;
       default:
         rows_backward<N, kPatchZern><<<gr.rows(), BwdRow<N>::threads, 0, st>>>(
-            p->X, O, P, bt, dk, pg, gr.row_chunks, nullptr, nullptr, o.zpart, p->kappa_tab,
+            X, O, P, bt, dk, pg, gr.row_chunks, nullptr, nullptr, o.zpart, p->kappa_tab,
             p->twN);
         break;
     }
@@ -739,6 +741,11 @@ const char* fpm_strerror(int code) {
 }
 
 const char* fpm_last_error(void) { return g_last_error.c_str(); }
+
+#ifndef FPM_BUILD_TAG
+#error "FPM_BUILD_TAG (a digest of the sources) is set by the build"
+#endif
+const char* fpm_build_tag(void) { return FPM_BUILD_TAG; }
 
 int fpm_plan_create(const fpm_desc* d, const int32_t* shifts_host, fpm_plan** out) {
   return guarded([&]() -> int {

@@ -213,10 +213,7 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
                          tile_c0 + 31 < wc + a.dk.ky_lo || tile_c0 > wc + a.dk.ky_hi);
     if (meets) hit |= 1ull << b;
   }
-#ifndef FPM_GATHER_ROUND
-#define FPM_GATHER_ROUND 4
-#endif
-  constexpr int kRound = FPM_GATHER_ROUND;
+  constexpr int kRound = 4;
   while (hit) {
     // kRound slots per round: all loads issued (at addresses clamped into the
     // disk) before the masked, in-order accumulation
@@ -262,7 +259,6 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
 
 template <int N>
 __global__ void __launch_bounds__(256) update(UpdateArgs a) {
-  FPM_PROBE(3, 0);
   const int n_pw = a.pupil ? pupil_wg_slots(N, a.dk.nrows) : 1;
   if ((int)blockIdx.x >= n_pw) {
     const int i = blockIdx.x - n_pw;
@@ -292,7 +288,6 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
       g[2 * h + 1] = make_float2(gi[h].z, gi[h].w);
     }
     gather_gradient<N>(a, r, col, tl.x * 32, tl.y * 32, g);
-    FPM_PROBE(3, 1);
     if (a.acc_out) {
 #pragma unroll
       for (int h = 0; h < 2; ++h)
@@ -309,8 +304,6 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
       store_next4<N>(pm + 8 * h, m[h]);
       store_next4<N>(pv + 8 * h, v[h]);
     }
-    FPM_PROBE(3, 2);
-    FPM_PROBE(3, 3);
     return;
   }
   const int pw = blockIdx.x;
@@ -328,10 +321,7 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     // (independent loads in flight, then a fixed summation order)
     const int j = threadIdx.x & (kPar - 1);
     double sj = 0.0;
-#ifndef FPM_ZPART_UNROLL
-#define FPM_ZPART_UNROLL 24
-#endif
-    constexpr int kStride = 256 / kPar, kUnroll = FPM_ZPART_UNROLL;
+    constexpr int kStride = 256 / kPar, kUnroll = 24;
     for (int i0 = threadIdx.x / kPar; i0 < a.n_zpart; i0 += kStride * kUnroll) {
       double vals[kUnroll];
 #pragma unroll
@@ -386,11 +376,9 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     __syncthreads();
     if (pw == 0 && threadIdx.x < kScal) a.staging[threadIdx.x] = next[threadIdx.x];
     if (pw == 0 && threadIdx.x < kPar && a.g_par) a.g_par[threadIdx.x] += red[threadIdx.x];
-    FPM_PROBE(3, 1);
     // rebuild this workgroup's rows of the pupil from the new parameters
     rebuild_pupil_rows<N, false>(pw, a.dk, a.pg, next, a.cur.z != nullptr, a.P);
   }
-  FPM_PROBE(3, 3);
 }
 
 // ---------------------------------------------------------------------------

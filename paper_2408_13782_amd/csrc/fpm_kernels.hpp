@@ -33,34 +33,17 @@
 #include "fft_line.hpp"
 #include "fpm_optics.hpp"
 
-// Timeline probes for development builds (they compile to nothing here).
-#ifndef FPM_PROBE
-#define FPM_PROBE(kernel, point)
-#endif
-
 namespace fpm {
 
-#ifndef FPM_ROW_THREADS
-#define FPM_ROW_THREADS 128
-#endif
-constexpr int kRowThreads = FPM_ROW_THREADS;   // threads per workgroup in the row passes
+constexpr int kRowThreads = 128;   // threads per workgroup in the row passes
 constexpr int kXcds = 8;
 
 // Threads per row transform in the row passes (more threads per line than
 // the default plan: more waves in flight for the few rows of a batch).
-#ifndef FPM_ROW_T256
-#define FPM_ROW_T256 32
-#endif
-#ifndef FPM_ROW_T512
-#define FPM_ROW_T512 32
-#endif
-#ifndef FPM_ROW_T128
-#define FPM_ROW_T128 32
-#endif
 template <int N> struct RowT { static constexpr int value = DefaultT<N>::value; };
-template <> struct RowT<128> { static constexpr int value = FPM_ROW_T128; };
-template <> struct RowT<256> { static constexpr int value = FPM_ROW_T256; };
-template <> struct RowT<512> { static constexpr int value = FPM_ROW_T512; };
+template <> struct RowT<128> { static constexpr int value = 32; };
+template <> struct RowT<256> { static constexpr int value = 32; };
+template <> struct RowT<512> { static constexpr int value = 32; };
 template <int N> using RowPlan = PlanT<N, RowT<N>::value>;
 
 // The nearest-pixel row passes, each with its own shape. At N = 256, 64
@@ -76,29 +59,16 @@ template <> struct FwdRow<512> { static constexpr int T = 64, threads = kRowThre
 template <int N> struct BwdRow { static constexpr int T = RowT<N>::value, threads = kRowThreads; };
 template <> struct BwdRow<512> { static constexpr int T = 64, threads = 2 * kRowThreads; };
 
-#ifndef FPM_COL_LINES256
-#define FPM_COL_LINES256 16
-#endif
 template <int N> struct ColLines { static constexpr int value = 16; };
-template <> struct ColLines<256> { static constexpr int value = FPM_COL_LINES256; };
 template <> struct ColLines<512> { static constexpr int value = 8; };
 
 // Threads per column transform in the column pass (more threads per column
 // than the row passes: with B = 16 the pass has about one wave per SIMD at 16
 // elements per thread, and more waves hide the LDS and dependency latency).
-#ifndef FPM_COL_T256
-#define FPM_COL_T256 32
-#endif
-#ifndef FPM_COL_T512
-#define FPM_COL_T512 64
-#endif
-#ifndef FPM_COL_T128
-#define FPM_COL_T128 32
-#endif
 template <int N> struct ColT { static constexpr int value = DefaultT<N>::value; };
-template <> struct ColT<128> { static constexpr int value = FPM_COL_T128; };
-template <> struct ColT<256> { static constexpr int value = FPM_COL_T256; };
-template <> struct ColT<512> { static constexpr int value = FPM_COL_T512; };
+template <> struct ColT<128> { static constexpr int value = 32; };
+template <> struct ColT<256> { static constexpr int value = 32; };
+template <> struct ColT<512> { static constexpr int value = 64; };
 template <int N> using ColPlan = PlanT<N, ColT<N>::value>;
 // LDS slots between consecutive elements of one column (padding by radix).
 // N = 512 (8 columns of 64 threads): no padding. By a model of 32 banks and 16
@@ -426,7 +396,6 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch b
   constexpr int L = FwdRow<N>::threads / T;
   __shared__ float2 lds[L * RowLds<N>::kStride];
   __shared__ float2 lds_tw[N];
-  FPM_PROBE(0, 0);
   if (commit && blockIdx.x == 0) commit_scalars(staging, scal, threadIdx.x);
   int b, c;
   if (!xcd_map(blockIdx.x, chunks, bt.B, b, c)) return;
@@ -457,15 +426,12 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch b
     const bool in = active && kx >= ext.x && kx <= ext.y;
     v[m] = in ? cmul(ov[m], pvv[m]) : make_float2(0.f, 0.f);
   }
-  FPM_PROBE(0, 1);
   PlanT<N, T>::template run<+1>(v, t, lds + line * RowLds<N>::kStride, [](int n) { return RowLds<N>::at(n); }, lds_tw);
-  FPM_PROBE(0, 2);
   if (active) {
     float2* xr = X + ((size_t)b * N + ky) * N;
 #pragma unroll
     for (int m = 0; m < E; ++m) store_next<N>(xr + t + m * T, v[m]);
   }
-  FPM_PROBE(0, 3);
 }
 
 // Column pass: inverse DFT along k_y, amplitude loss, residual, forward DFT.
@@ -481,7 +447,6 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
   constexpr int L = ColLines<N>::value;
   __shared__ float2 lds[N * ColStride<N>::value];
   __shared__ float2 lds_tw[N];
-  if (!kForward) FPM_PROBE(1, 0);
   int b, g;
   const bool live = xcd_map(blockIdx.x, groups, bt.B, b, g);
   const int line = threadIdx.x % L;
@@ -506,7 +471,6 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
     stage_twiddles_after_loads<N, L * T>(lds_tw, tw);
     const float sg = gamma ? sqrtf(gamma[led]) : 1.0f;
     auto lay = [line](int n) { return n * ColStride<N>::value + line; };
-    if (!kForward) FPM_PROBE(1, 1);
     ColPlan<N>::template run<+1>(v, t, lds, lay, lds_tw);
     if constexpr (kForward) {
 #pragma unroll
@@ -548,7 +512,6 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
         v[m] = cscale(v[m], k);
       }
       ColPlan<N>::template run<-1>(v, t, lds, lay, lds_tw);
-      FPM_PROBE(1, 2);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int ky = half_shift<N>(t + m * T);
@@ -563,7 +526,6 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
     } else {
       if (loss_part) block_partials<1>(&acc, loss_part);
     }
-    FPM_PROBE(1, 3);
   }
 }
 
@@ -589,7 +551,6 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
   constexpr bool kNeedC = MODE == kGradOP || MODE == kPatchZern;
   __shared__ float2 lds[L * RowLds<N>::kStride];
   __shared__ float2 lds_tw[N];
-  FPM_PROBE(2, 0);
   int b, c;
   const bool live = xcd_map(blockIdx.x, chunks, bt.B, b, c);
   const int line = threadIdx.x / T;
@@ -622,9 +583,7 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
       }
     }
     stage_twiddles_after_loads<N, BwdRow<N>::threads>(lds_tw, tw);
-    FPM_PROBE(2, 1);
     PlanT<N, T>::template run<-1>(v, t, lds + line * RowLds<N>::kStride, [](int n) { return RowLds<N>::at(n); }, lds_tw);
-    FPM_PROBE(2, 2);
     if (active) {
       const float ir = (float)pg.inv_r;
       // row moments S_a = sum g_theta x^a (a <= 4) and sum g_theta kappa
@@ -669,7 +628,6 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
   }
   if constexpr (MODE == kPatchZern)
     row_moment_partials<T, L>(zs, c * L, dk, N / 2, (float)pg.inv_r, zpart);
-  FPM_PROBE(2, 3);
 }
 
 }  // namespace fpm

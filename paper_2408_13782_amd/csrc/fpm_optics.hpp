@@ -73,31 +73,4 @@ struct PupilGeom {
   double inv_l;
 };
 
-// Learned pupil parameters as device pointers (NULL: zero).
-struct PupilParams {
-  const float* coeffs;
-  int n_zern;
-  const float* z_um;
-};
-
-// P(u) = exp(i (sum_j c_j Z_j(u) + z kappa(u))) on the disk, in FP32.
-__device__ __forceinline__ float2 pupil_value(const PupilGeom& g, const PupilParams& pp, int kx,
-                                              int ky) {
-  const float ux = (float)(kx - g.n / 2), uy = (float)(ky - g.n / 2);
-  float th = 0.f;
-  if (pp.coeffs && pp.n_zern > 0) {
-    float z[kZern];
-    const float ir = (float)g.inv_r;
-    zernike15(ux * ir, uy * ir, z);
-#pragma unroll
-    for (int j = 0; j < kZern; ++j)
-      if (j < pp.n_zern) th += pp.coeffs[j] * z[j];
-  }
-  if (pp.z_um)
-    th += pp.z_um[0] * defocus_kappa((ux * ux + uy * uy) * (float)g.dk2, (float)g.inv_l);
-  float s, c;
-  sincosf(th, &s, &c);
-  return make_float2(c, s);
-}
-
 }  // namespace fpm

@@ -137,7 +137,6 @@ rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Bat
   __shared__ float2 lds_tw[N];
   int b, c;
   if (!xcd_map(blockIdx.x, chunks, bt.B, b, c)) return;
-  FPM_PROBE(0, 0);
   const int line = threadIdx.x / T, t = threadIdx.x % T;
   const int rr = c * L + line;
   const bool active = rr < dk.nrows;
@@ -200,7 +199,6 @@ rows_forward_sub(const float2* __restrict__ O, const float2* __restrict__ P, Bat
 #pragma unroll
     for (int m = 0; m < E; ++m) xr[t + m * T] = v[m];
   }
-  FPM_PROBE(0, 3);
 }
 
 constexpr int kSubPar = kPar + 2;   // pupil moments, then dL/ds (row, col)
@@ -224,7 +222,6 @@ rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
   __shared__ float2 lds_tw[N];
   int b, c;
   const bool live = xcd_map(blockIdx.x, chunks, bt.B, b, c);
-  FPM_PROBE(2, 0);
   const int line = threadIdx.x / T, t = threadIdx.x % T;
   const int rr = c * L + line;
   const bool active = rr < dk.nrows;
@@ -291,7 +288,6 @@ rows_backward_sub(float2* __restrict__ X, const float2* __restrict__ O,
   // (a buffer for this workgroup's waves only: at N = 512 the pass then fits
   // four workgroups per CU in LDS instead of three)
   block_partials<kSubPar, (kThreads + 63) / 64>(acc, part);
-  FPM_PROBE(2, 3);
 }
 
 // Window corner and fractional offsets of every batch slot, compact, in LDS,
@@ -589,7 +585,6 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
     const int flagged = a.tile_flags[ti];
     const unsigned long long hit = tile_slots(a.sub, a.bt, a.dk, tr0, tc0, cs);
     if (!hit && !flagged) return;
-    FPM_PROBE(3, 0);
     if (hit && !flagged && threadIdx.x == 0) a.tile_flags[ti] = 1;
     const int r = tr0 + (threadIdx.x >> 3);
     const int c0 = tc0 + (threadIdx.x & 7) * 2;
@@ -606,7 +601,6 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
     }
     float2 g[4];
     gather_bilinear<N>(a.X, a.dk, cs, hit, r, c0, g);
-    FPM_PROBE(3, 1);
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       adam1(o[h].x, m[h].x, v[h].x, g[2 * h].x, a.c);
@@ -617,7 +611,6 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
       store_next4<N>(pm + 8 * h, m[h]);
       store_next4<N>(pv + 8 * h, v[h]);
     }
-    FPM_PROBE(3, 2);
     return;
   }
   const int pw = blockIdx.x;
@@ -627,7 +620,6 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
     return;
   }
   if (pw > n_pupil) return;   // padding
-  FPM_PROBE(3, 0);
   __shared__ double red[256];
   __shared__ double gsum[kPar];
   __shared__ double gs[kMaxSlots][2];
@@ -650,7 +642,6 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
     gs[threadIdx.x][1] = gx;
   }
   __syncthreads();
-  FPM_PROBE(3, 1);
   if (threadIdx.x < kPar) {
     double mom = 0.0;
     for (int k = 0; k < 256 / kPar; ++k) mom += red[k * kPar + threadIdx.x];
@@ -725,7 +716,6 @@ __global__ void __launch_bounds__(256) update_multi(MultiUpdateArgs a) {
   }
   // rebuild this workgroup's rows of the pupil from the new parameters
   rebuild_pupil_rows<N, true>(pw, a.dk, a.pg, nextc[0], true, a.P);
-  FPM_PROBE(3, 3);
 }
 
 }  // namespace fpm

@@ -86,6 +86,7 @@ EXPORTS = {
     "fpm_plan_info": [C.c_void_p, C.POINTER(_Info)],
     "fpm_strerror": [C.c_int],
     "fpm_last_error": [],
+    "fpm_build_tag": [],
     "fpm_led_shifts": [C.POINTER(_Desc), C.POINTER(_Grid), C.c_void_p, C.c_void_p, C.c_void_p],
     "fpm_pupil": [C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p],
     "fpm_forward": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
@@ -128,9 +129,15 @@ def load(path: str = LIB_PATH):
     for name, argtypes in EXPORTS.items():
         fn = getattr(lib, name)
         fn.argtypes = argtypes
-        fn.restype = C.c_char_p if name in ("fpm_strerror", "fpm_last_error") else C.c_int
+        fn.restype = (C.c_char_p if name in ("fpm_strerror", "fpm_last_error", "fpm_build_tag")
+                      else C.c_int)
     _lib = lib
     return lib
+
+
+def build_tag() -> str:
+    """Digest of the sources the loaded library was built from (fpm_build_tag)."""
+    return load().fpm_build_tag().decode()
 
 
 def _check(rc: int):

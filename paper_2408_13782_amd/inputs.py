@@ -187,6 +187,15 @@ def led_permutations(n_led: int, epochs: int, seed: int = 0) -> np.ndarray:
     return np.stack([rng.permutation(n_led) for _ in range(epochs)]).astype(np.int32)
 
 
+def centre_out_order(k: np.ndarray) -> np.ndarray:
+    """The fixed LED order of the sequential one-image-per-update loop (Sec. 3.1,
+    Eq. 7): from the centre outwards by |k_b|, ties by angle. k is float [n_led, 2]
+    in (row, col) order; returns int32 [n_led]."""
+    k = np.asarray(k, np.float64)
+    return np.lexsort((np.arctan2(k[:, 0], k[:, 1]),
+                       np.round(np.hypot(k[:, 0], k[:, 1]), 9))).astype(np.int32)
+
+
 # ---------------------------------------------------------------------------
 # photon noise
 

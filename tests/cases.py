@@ -59,3 +59,21 @@ def rel_l2(a, b) -> float:
     b = np.asarray(b, np.complex128)
     nb = np.linalg.norm(b)
     return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+GRAD_TOL = 2e-5          # per-step gradient bar, relative L2
+GRAD_ELEM_TOL = 1e-4     # elementwise bar, relative to the largest reference entry
+
+
+def assert_grad_close(got, ref, tol: float = GRAD_TOL, elem_tol: float = GRAD_ELEM_TOL):
+    """Gradient parity: relative L2 within tol, and every entry within elem_tol of
+    the largest reference magnitude (an error confined to a few pixels, which the
+    L2 norm over millions of entries would hide, fails the second bound)."""
+    got = np.asarray(got, np.complex128)
+    ref = np.asarray(ref, np.complex128)
+    err = rel_l2(got, ref)
+    assert err <= tol, f"relative L2 {err:.3e} > {tol:.1e}"
+    worst = float(np.abs(got - ref).max())
+    scale = float(np.abs(ref).max())
+    assert worst <= elem_tol * scale, f"max entry error {worst:.3e} > {elem_tol:.0e} x {scale:.3e}"
+    return err

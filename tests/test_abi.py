@@ -98,3 +98,11 @@ def test_product_package_never_reaches_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(from|import)\s+oracle", text, re.M), f
                 assert "fpm_oracle" not in text, f
+
+
+def test_library_build_tag_matches_the_sources():
+    """The in-tree libfpm.so was built from the sources in this tree (its
+    fpm_build_tag is the digest of csrc/ and include/)."""
+    from paper_2408_13782_amd import build
+    tag = fpm.build_tag()
+    assert len(tag) == 16 and tag == build.source_tag()

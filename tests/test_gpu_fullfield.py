@@ -5,7 +5,10 @@ import sys
 import numpy as np
 import pytest
 
-from paper_2408_13782_amd import fpm, inputs
+from oracle import fpm_oracle as fo
+from paper_2408_13782_amd import fpm, inputs, problem
+
+from cases import optics_of, rel_l2
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -83,3 +86,52 @@ def test_tiles_through_the_server_equal_direct_solves_and_stitch(mods):
     for li in range(2):
         q, q0 = fullfield.quality(fields[li], truth), fullfield.quality(init[li], truth)
         assert q["phase_psnr_db"] > q0["phase_psnr_db"] + 1.0, (li, q, q0)
+
+
+@pytest.mark.parametrize("lam", [0.47, 0.63])
+def test_off_axis_colour_tile_matches_oracle(mods, lam):
+    """One corner tile of a 3 x 3 field at the blue and red wavelengths (Sec. 3.3,
+    Sec. 4): its LED table, computed by the library with the tile centre as the
+    sample point, equals the oracle's k_m / dk rounded to the nearest pixel; a
+    plan made with the on-axis table and rebound to the tile's (fpm_plan_set_shifts)
+    runs two epochs of object + Zernike steps that match the oracle's solve."""
+    fullfield, _ = mods
+    w = inputs.workload("small", n_lr=64, n_side=9, wavelength_um=lam, learn_zernike=True)
+    say(f"off-axis tile at {lam} um")
+    field = fullfield.Field(w, tiles=3, overlap=16, wavelengths=(lam,))
+    x_mm, y_mm = field.roi_mm(0, 2)
+    assert x_mm > 0 and y_mm < 0
+    opt = optics_of(w)
+    k = fo.led_wavevectors(opt, w.n_side, w.pitch_mm, w.height_mm, roi_x_mm=x_mm, roi_y_mm=y_mm)
+    shifts = fo.nearest_shifts(fo.led_shifts(opt, k))
+    k0 = fo.led_wavevectors(opt, w.n_side, w.pitch_mm, w.height_mm)
+    shifts0 = fo.nearest_shifts(fo.led_shifts(opt, k0))
+    assert not np.array_equal(shifts, shifts0)
+    np.testing.assert_array_equal(field.tile_shifts(w, 0, 2), shifts)
+    # data from the oracle's forward model at this wavelength (pupil radius NA / lambda)
+    mask, zern, kappa = fo.pupil_mask(opt), fo.zernike_basis(opt), fo.defocus_phase_per_um(opt)
+    amp, ph = inputs.truth_object(w.m_hr, seed=5)
+    O_true = fo.spectrum(fo.transmission(amp, ph))
+    P_true = fo.pupil(mask, zern, np.zeros(15), 4.0, kappa)
+    A = inputs.poisson_amplitudes(fo.forward_intensities(O_true, P_true, shifts, range(w.n_led)),
+                                  np.where(fo.bright_field(opt, k), 1e4, 1e2), seed=5)
+    centre = (w.n_side // 2) * w.n_side + w.n_side // 2
+    O0 = fo.initial_spectrum(A[centre], w.upsample).astype(np.complex64)
+    plan = fpm.Plan(w.n_lr, w.upsample, shifts0, w.batch, w.wavelength_um, w.na, w.mag,
+                    w.pixel_um)
+    plan.set_shifts(shifts)
+    assert plan.info.support_px == int(mask.sum())
+    perms = inputs.led_permutations(w.n_led, 2, seed=6)
+    sched = fo.batches_from_permutations(perms, w.batch)
+    ds = problem.flatten_schedule(problem.schedule(perms, w.batch))
+    st = fpm.State(plan, torch.as_tensor(O0, device="cuda"))
+    plan.run(st, problem.hparams(w), ds.flat, ds.sizes, torch.as_tensor(A, device="cuda"))
+    torch.cuda.synchronize()
+    ost = fo.init_state(O0)
+    cfg = fo.SolveConfig(lr_object=w.lr_object, lr_zernike=w.lr_zernike, learn_pupil=True)
+    losses = fo.solve(ost, cfg, mask, zern, kappa, shifts, sched, A.astype(np.float64))
+    err = rel_l2(st.O.cpu().numpy(), ost.O)
+    say(f"{len(sched)} steps: final object rel err {err:.3e}")
+    assert err <= 1e-3
+    assert abs(float(st.loss.cpu()[0]) - sum(losses)) <= 1e-4 * sum(losses)
+    np.testing.assert_allclose(st.coeffs.cpu().numpy(), ost.coeffs, atol=0.05 * w.lr_zernike)

@@ -10,7 +10,7 @@ import pytest
 from oracle import fpm_oracle as fo
 from paper_2408_13782_amd import fpm, inputs
 
-from cases import optics_of, rel_l2
+from cases import assert_grad_close, optics_of, rel_l2
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -101,7 +101,7 @@ def test_loss_grad_matches_oracle(dev, case):
     ref = case.oracle(O64, c.astype(np.float64), float(z[0]), geom, gamma.astype(np.float64), leds)
     assert int(H(g["oob"])[0]) == 0
     assert abs(float(H(g["loss"])[0]) - ref.loss) <= 1e-5 * ref.loss
-    assert rel_l2(H(g["g_O"]), ref.g_O) <= GRAD_TOL
+    assert_grad_close(H(g["g_O"]), ref.g_O)
     # scalar groups are sums that cancel: measured against the sum of their terms
     P = fo.pupil(case.mask, case.zern, c.astype(np.float64), float(z[0]), case.kappa)
     sub = fo.loss_and_grads_subpixel(O64, P, s, leds, case.A.astype(np.float64),
@@ -145,7 +145,7 @@ def test_autograd_function_takes_batches_above_64_in_groups(dev):
     ref = cs.oracle(cs.O0.astype(np.complex128), c0.astype(np.float64), 0.7, geom0,
                     gamma0.astype(np.float32).astype(np.float64), leds)
     assert abs(float(loss.detach()) - ref.loss) <= 1e-5 * ref.loss
-    assert rel_l2(H(O.grad), ref.g_O) <= GRAD_TOL
+    assert_grad_close(H(O.grad), ref.g_O)
     g_gamma = H(gamma.grad).astype(np.float64)
     np.testing.assert_allclose(g_gamma, ref.g_gamma, rtol=1e-4, atol=1e-5 * np.abs(ref.g_gamma).max())
     P = fo.pupil(cs.mask, cs.zern, c0.astype(np.float64), 0.7, cs.kappa)
@@ -198,7 +198,7 @@ def test_intensity_loss_grad_matches_oracle(dev, case):
                                        w.pitch_mm, w.height_mm, case.mask, case.zern,
                                        case.kappa, loss="intensity")
     assert abs(float(H(g["loss"])[0]) - ref.loss) <= 1e-5 * ref.loss
-    assert rel_l2(H(g["g_O"]), ref.g_O) <= GRAD_TOL
+    assert_grad_close(H(g["g_O"]), ref.g_O)
     np.testing.assert_allclose(H(g["g_gamma"]), ref.g_gamma, rtol=1e-5,
                                atol=1e-6 * np.abs(ref.g_gamma).max())
     assert rel_l2(H(g["g_par"])[1:15], ref.g_coeffs[1:]) <= 1e-4
@@ -523,3 +523,164 @@ def test_fused_multi_step_at_the_large_size_matches_oracle(dev):
     for b, led in enumerate(leds):
         scale += np.abs(J[led].T) @ np.abs(sub.g_shift[b])
     assert np.all(np.abs(H(geo.g) - ref.g_geom) <= 1e-4 * scale)
+
+
+def _torch_adam_reference(case, sched, lrs, c0=None, z0=0.0, geom0=None, O0=None):
+    """The fused run's Adam updates of every group (torch, FP64 on the CPU) driven
+    by the oracle's multi-parameter gradients, one schedule step at a time."""
+    w = case.w
+    O_r = torch.tensor((case.O0 if O0 is None else O0).astype(np.complex128), requires_grad=True)
+    c_r = torch.tensor(np.zeros(15) if c0 is None else np.asarray(c0, np.float64),
+                       requires_grad=True)
+    z_r = torch.tensor([z0], dtype=torch.float64, requires_grad=True)
+    g_r = torch.tensor(np.zeros(4) if geom0 is None else np.asarray(geom0, np.float64),
+                       requires_grad=True)
+    opt = torch.optim.Adam([dict(params=[O_r], lr=lrs[0]), dict(params=[c_r], lr=lrs[1]),
+                            dict(params=[z_r], lr=lrs[2]), dict(params=[g_r], lr=lrs[3])])
+    losses = []
+    for leds in sched:
+        gr = case.oracle(O_r.detach().numpy(), c_r.detach().numpy(), float(z_r.detach()[0]),
+                         g_r.detach().numpy(), None, leds)
+        losses.append(gr.loss)
+        O_r.grad = torch.tensor(gr.g_O)
+        c_r.grad = torch.tensor(gr.g_coeffs)
+        c_r.grad[0] = 0.0
+        z_r.grad = torch.tensor([gr.g_z], dtype=torch.float64)
+        g_r.grad = torch.tensor(gr.g_geom)
+        opt.step()
+    return (O_r.detach().numpy(), c_r.detach().numpy(), z_r.detach().numpy(),
+            g_r.detach().numpy(), losses)
+
+
+@pytest.mark.timeout(300)
+def test_fused_multi_full_solve_matches_oracle(dev, case):
+    """The whole multi-parameter workload through fpm_run_multi: 20 epochs of B = 8
+    on 7x7 LEDs (140 steps; object, Zernikes, defocus and LED-array geometry),
+    against torch Adam driven by the oracle's gradients in the same batch order."""
+    say("fused multi-parameter solve, 140 steps, vs oracle")
+    w = case.w
+    perms = inputs.led_permutations(w.n_led, w.epochs, seed=11)
+    sched = fo.batches_from_permutations(perms, w.batch)
+    assert len(sched) == 140
+    flat = np.concatenate(sched).astype(np.int32)
+    sizes = np.array([len(b) for b in sched], np.int32)
+    plan, st, geo, hp = _multi_setup(case, dev, np.zeros(15), 0.0, np.zeros(4))
+    plan.run_multi(case.grid, st, geo, hp, flat, sizes, T(case.A, dev))
+    torch.cuda.synchronize()
+    assert st.t == 140
+    O_r, c_r, z_r, g_r, losses = _torch_adam_reference(
+        case, sched, (w.lr_object, w.lr_zernike, w.lr_z, 1e-3))
+    o_err = rel_l2(H(st.O), O_r)
+    say(f"final object rel err {o_err:.3e}; Zernike max diff "
+        f"{np.abs(H(st.coeffs) - c_r).max():.2e}, defocus diff {abs(H(st.z_um)[0] - z_r[0]):.2e}, "
+        f"geometry diff {np.abs(H(geo.geom) - g_r).max():.2e}")
+    assert o_err <= 1e-3
+    assert abs(float(H(st.loss)[0]) - sum(losses)) <= 1e-4 * sum(losses)
+    np.testing.assert_allclose(H(st.coeffs), c_r, atol=0.2 * w.lr_zernike)
+    np.testing.assert_allclose(H(st.z_um), z_r, atol=0.2 * w.lr_z)
+    np.testing.assert_allclose(H(geo.geom), g_r, atol=0.2 * 1e-3)
+
+
+class LargeCase(Case):
+    """The large workload (21x21 LEDs, 512^2 -> 2048^2, B = 32): data from the
+    seeded true geometry (nearest-pixel forward model, Poisson noise with dark
+    field at 1e2 photons), solved from the nominal grid."""
+
+    def __init__(self, seed=0):
+        w = inputs.workload("large")
+        opt = optics_of(w)
+        self.w, self.opt = w, opt
+        self.grid = fpm.LedGrid(w.n_side, w.pitch_mm, w.height_mm)
+        self.geom_true = np.array(inputs.true_geometry(w, seed))
+        k = fo.led_wavevectors(opt, w.n_side, w.pitch_mm, w.height_mm, *self.geom_true)
+        shifts_true = fo.nearest_shifts(fo.led_shifts(opt, k))
+        amp, ph = inputs.truth_object(w.m_hr, seed)
+        self.O_true = fo.spectrum(fo.transmission(amp, ph))
+        self.mask = fo.pupil_mask(opt)
+        self.zern = fo.zernike_basis(opt)
+        self.kappa = fo.defocus_phase_per_um(opt)
+        P_true = fo.pupil(self.mask, self.zern, np.zeros(15), inputs.true_defocus(w, seed),
+                          self.kappa)
+        q = np.where(fo.bright_field(opt, k), w.q_bright, w.q_dark)
+        self.A = inputs.poisson_amplitudes(
+            fo.forward_intensities(self.O_true, P_true, shifts_true, range(w.n_led)), q, seed)
+        self.O0 = (self.O_true * 0.9).astype(np.complex64)
+        k0 = fo.led_wavevectors(opt, w.n_side, w.pitch_mm, w.height_mm)
+        self.shifts = fo.nearest_shifts(fo.led_shifts(opt, k0))
+
+    def plan(self, max_batch=32):
+        return super().plan(max_batch)
+
+
+@pytest.mark.timeout(400)
+def test_fused_multi_epoch_at_the_large_size_matches_oracle(dev):
+    """One epoch (14 steps) of the fused multi-parameter solve at 512^2 -> 2048^2,
+    B = 32 (the launch shape the large benchmark times): from the second step on
+    the update kernel derives the next batch's sub-pixel offsets. The spectrum,
+    every scalar group and the loss against torch Adam driven by the oracle's
+    gradients; the first step's spectrum update where its sign is decided."""
+    say("fused multi-parameter epoch, large size (14 steps)")
+    lc = LargeCase()
+    w = lc.w
+    perms = inputs.led_permutations(w.n_led, 1, seed=8)
+    sched = fo.batches_from_permutations(perms, w.batch)
+    assert len(sched) == 14 and len(sched[-1]) == 25
+    c0 = inputs.random_real((15,), seed=9, lo=-0.1, hi=0.1)
+    c0[0] = 0.0
+    geom0 = 0.5 * lc.geom_true
+    z0 = float(np.float32(0.7))
+    lrs = (w.lr_object, w.lr_zernike, w.lr_z, 1e-3)
+    plan = lc.plan()
+    A = T(lc.A, dev)
+    # the first step alone: its update against Adam's first step, lr sign(g)
+    st1 = fpm.State(plan, T(lc.O0, dev), c0, z0)
+    geo1 = fpm.Geometry(geom0, lr_shift_mm=1e-3, lr_rot_rad=1e-3, lr_height_mm=1e-3)
+    hp = fpm.HParams(lr_object=w.lr_object, lr_zernike=w.lr_zernike, lr_z=w.lr_z,
+                     learn_zernike=True, learn_z=True)
+    plan.run_multi(lc.grid, st1, geo1, hp, sched[0], [len(sched[0])], A)
+    torch.cuda.synchronize()
+    ref = lc.oracle(lc.O0.astype(np.complex128), c0.astype(np.float64), z0, geom0, None,
+                    sched[0])
+
+    def ri(z):
+        return np.stack([z.real, z.imag], -1).astype(np.float64)
+
+    O1, gg = ri(H(st1.O)), ri(ref.g_O)
+    want = ri(lc.O0.astype(np.complex128)) - w.lr_object * np.sign(gg)
+    decided = np.abs(gg) > 1e-4 * np.abs(gg).max()
+    diff = np.abs(O1 - want)
+    assert decided.sum() > 0.1 * decided.size
+    assert np.all(diff[decided] <= 1e-6 + 1e-6 * np.abs(want[decided]))
+    assert np.all(diff[~decided] <= 2 * w.lr_object * (1 + 1e-5))
+    # the whole epoch
+    st = fpm.State(plan, T(lc.O0, dev), c0, z0)
+    geo = fpm.Geometry(geom0, lr_shift_mm=1e-3, lr_rot_rad=1e-3, lr_height_mm=1e-3)
+    flat = np.concatenate(sched).astype(np.int32)
+    sizes = np.array([len(b) for b in sched], np.int32)
+    plan.run_multi(lc.grid, st, geo, hp, flat, sizes, A)
+    torch.cuda.synchronize()
+    assert st.t == 14
+    O_r, c_r, z_r, g_r, losses = _torch_adam_reference(lc, sched, lrs, c0, z0, geom0, lc.O0)
+    o_err = rel_l2(H(st.O), O_r)
+    say(f"after one epoch: object rel err {o_err:.3e}, Zernike max diff "
+        f"{np.abs(H(st.coeffs) - c_r).max():.2e}, geometry max diff "
+        f"{np.abs(H(geo.geom) - g_r).max():.2e}")
+    # At this size Adam turns the FP32 rounding of the many near-zero gradient
+    # components (112 674 of 2.9 M below 1e-6 of the largest at the first step)
+    # into whole steps of either sign: the FP64 reference itself, fed gradients
+    # with 1e-6 relative noise, moves 3.6e-3 over these 14 steps. The trajectory
+    # bar is therefore 2e-3 here; the gradient at the GPU's own state (below)
+    # holds the per-step bar.
+    assert o_err <= 2e-3
+    assert abs(float(H(st.loss)[0]) - sum(losses)) <= 1e-5 * sum(losses)
+    # the gradient at the GPU's state after the epoch, every group
+    leds = sched[0]
+    g = plan.loss_grad(lc.grid, st.O, leds, A, coeffs=st.coeffs, z_um=st.z_um, geom=geo.geom)
+    torch.cuda.synchronize()
+    ref = lc.oracle(H(st.O).astype(np.complex128), H(st.coeffs).astype(np.float64),
+                    float(H(st.z_um)[0]), H(geo.geom).astype(np.float64), None, leds)
+    assert abs(float(H(g["loss"])[0]) - ref.loss) <= 1e-5 * ref.loss
+    assert_grad_close(H(g["g_O"]), ref.g_O)
+    np.testing.assert_allclose(H(st.coeffs), c_r, atol=0.2 * w.lr_zernike)
+    np.testing.assert_allclose(H(st.z_um), z_r, atol=0.2 * w.lr_z)
+    np.testing.assert_allclose(H(geo.geom), g_r, atol=0.2 * 1e-3)

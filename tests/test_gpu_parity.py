@@ -16,7 +16,7 @@ import pytest
 from oracle import fpm_oracle as fo
 from paper_2408_13782_amd import fpm, inputs, problem
 
-from cases import oracle_problem, optics_of, rel_l2
+from cases import assert_grad_close, oracle_problem, optics_of, rel_l2
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -60,7 +60,7 @@ def oracle_shifts(w):
 # building blocks
 
 
-@pytest.mark.parametrize("n_lr", [64, 192, 256, 384, 512])
+@pytest.mark.parametrize("n_lr", [64, 128, 192, 256, 384, 512])
 def test_hr_transforms_match_oracle(dev, n_lr):
     w = inputs.workload("small", n_lr=n_lr)
     say(f"hr_transform M={w.m_hr}")
@@ -80,7 +80,7 @@ def test_hr_transforms_match_oracle(dev, n_lr):
     assert rel_l2(H(x), want) <= GRAD_TOL
 
 
-@pytest.mark.parametrize("n_lr", [64, 192, 256])
+@pytest.mark.parametrize("n_lr", [64, 128, 192, 256, 384, 512])
 def test_initial_spectrum_matches_oracle(dev, n_lr):
     w = inputs.workload("small", n_lr=n_lr)
     say(f"init_spectrum N={n_lr}")
@@ -162,7 +162,7 @@ def test_backward_matches_oracle_at_initial_state(dev, name, B):
     P = fo.pupil(pr.mask, pr.zern, np.zeros(15), 0.0, pr.kappa).astype(np.complex64)
     leds = inputs.random_indices(w.n_led, B, seed=11 + B)
     plan, gO, gP, loss, ref = _backward_case(dev, w, pr.O0, P, leds, pr.A, None)
-    assert rel_l2(gO, ref.g_O) <= GRAD_TOL
+    assert_grad_close(gO, ref.g_O)
     m = pr.mask.astype(bool)
     assert rel_l2(gP[m], ref.g_P[m]) <= GRAD_TOL
     assert np.all(gP[~m] == 0)
@@ -189,7 +189,7 @@ def test_backward_with_aberrations_and_gamma(dev):
     leds = inputs.random_indices(w.n_led, 16, seed=1)
     plan, gO, gP, loss, ref = _backward_case(dev, w, O, P, leds, A, gamma)
     m = fo.pupil_mask(opt).astype(bool)
-    assert rel_l2(gO, ref.g_O) <= GRAD_TOL
+    assert_grad_close(gO, ref.g_O)
     assert rel_l2(gP[m], ref.g_P[m]) <= GRAD_TOL
     assert abs(loss - ref.loss) <= 1e-5 * ref.loss
 
@@ -215,7 +215,7 @@ def test_intensity_loss_backward_and_step_match_oracle(dev, name, B):
                             leds, pr.A.astype(np.float64), gamma.astype(np.float64),
                             loss="intensity")
     m = pr.mask.astype(bool)
-    assert rel_l2(H(gO), ref.g_O) <= GRAD_TOL
+    assert_grad_close(H(gO), ref.g_O)
     assert rel_l2(H(gP)[m], ref.g_P[m]) <= GRAD_TOL
     assert abs(float(H(loss)[0]) - ref.loss) <= 1e-5 * ref.loss
     st = fpm.State(plan, T(pr.O0, dev))
@@ -328,7 +328,7 @@ def test_factor_three_sizes_backward_and_step_match_oracle(dev, n_lr, n_side, B)
     plan, gO, gP, loss, ref = _backward_case(dev, w, pr.O0, P.astype(np.complex64), leds, pr.A,
                                              None)
     m = pr.mask.astype(bool)
-    assert rel_l2(gO, ref.g_O) <= GRAD_TOL
+    assert_grad_close(gO, ref.g_O)
     assert rel_l2(gP[m], ref.g_P[m]) <= GRAD_TOL
     assert abs(loss - ref.loss) <= 1e-5 * ref.loss
     st = fpm.State(plan, T(pr.O0, dev), c0, 0.0)
@@ -449,7 +449,7 @@ def test_batches_above_64_run_in_groups_and_match_oracle(dev):
     leds100 = all_leds[:100]
     _, gO, gP, loss, ref = _backward_case(dev, w, pr.O0, H(P), leds100, pr.A, None)
     m = pr.mask.astype(bool)
-    assert rel_l2(gO, ref.g_O) <= GRAD_TOL
+    assert_grad_close(gO, ref.g_O)
     assert rel_l2(gP[m], ref.g_P[m]) <= GRAD_TOL
     assert abs(loss - ref.loss) <= 1e-5 * ref.loss
     # two epochs of full-gradient steps, two cut into batches of 100 + 21, one
@@ -498,7 +498,7 @@ def test_full_gradient_step_at_paper_size_matches_oracle(dev):
     plan, gO, gP, loss, ref = _backward_case(dev, w, pr.O0, P, leds, pr.A, None)
     assert plan.info.max_batch == 225
     m = pr.mask.astype(bool)
-    assert rel_l2(gO, ref.g_O) <= GRAD_TOL
+    assert_grad_close(gO, ref.g_O)
     assert rel_l2(gP[m], ref.g_P[m]) <= GRAD_TOL
     assert abs(loss - ref.loss) <= 1e-5 * ref.loss
     st = _gpu_state(plan, pr.O0, dev)
@@ -527,7 +527,7 @@ def _gradient_at_gpu_state(dev, plan, pr, st, leds, P):
     torch.cuda.synchronize()
     ref = fo.loss_and_grads(H(st.O).astype(np.complex128), H(P).astype(np.complex128),
                             pr.shifts, leds, pr.A.astype(np.float64))
-    return rel_l2(H(gO), ref.g_O)
+    return assert_grad_close(H(gO), ref.g_O)
 
 
 def test_small_solve_matches_oracle(dev):
@@ -640,7 +640,7 @@ def test_edge_cases(dev):
     torch.cuda.synchronize()
     ref = fo.loss_and_grads(pr.O0.astype(np.complex128), H(P).astype(np.complex128), pr.shifts,
                             leds, pr.A.astype(np.float64))
-    assert rel_l2(H(gO), ref.g_O) <= GRAD_TOL
+    assert_grad_close(H(gO), ref.g_O)
     assert abs(float(H(loss)[0]) - ref.loss) <= 1e-5 * ref.loss
     # batch larger than the plan allows
     with pytest.raises(fpm.FpmError):

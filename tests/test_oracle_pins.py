@@ -650,3 +650,18 @@ def test_step_matches_torch_autograd_and_adam():
     assert np.abs(st.O - O0).max() > 2 * cfg.lr_object
     assert np.median(np.abs(st.coeffs[1:] - c0[1:])) > 0.5 * cfg.lr_zernike
     assert abs(st.z_um + 1.0) > 0.5 * cfg.lr_z
+
+
+def test_threaded_fft_mode_gives_the_same_oracle():
+    """The CPU-baseline timing may run the oracle's FFTs on scipy.fft threads: the
+    loss and gradients agree with the default numpy mode to rounding."""
+    pytest.importorskip("scipy")
+    O, P, mask, shifts, A, gamma, _ = _random_problem(seed=31)
+    a = fo.loss_and_grads(O, P, shifts, [0, 2, 4], A, gamma)
+    fo.set_fft_workers(4)
+    try:
+        b = fo.loss_and_grads(O, P, shifts, [0, 2, 4], A, gamma)
+    finally:
+        fo.set_fft_workers(1)
+    assert np.isclose(a.loss, b.loss, rtol=1e-13)
+    np.testing.assert_allclose(b.g_O, a.g_O, atol=1e-13 * np.abs(a.g_O).max())

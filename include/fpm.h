@@ -193,6 +193,26 @@ int fpm_backward(fpm_plan* plan, const fpm_c32* O, const fpm_c32* P, const int32
                  fpm_c32* gP, double* loss, void* stream);
 
 /*
+ * fpm_backward without any device memory of its own: for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation). Same arguments, operation and results as fpm_backward;
+ * the row/column intermediate and the loss partial sums live in a static
+ * device array of the library (16 MiB + 256 KiB on each device the library
+ * runs on, held until the process ends) instead of the plan's scratch.
+ * Limit: min(B, 64) * N * N * 8 bytes <= 16 MiB (e.g. B <= 32 at N = 256,
+ * B <= 8 at N = 512) and the column pass's partial sums within 256 KiB;
+ * a larger batch fails with FPM_EINVAL before anything is enqueued. The call
+ * allocates nothing (its first call on a device looks up the array's device
+ * address once). Every call on one device shares that array and leaves its
+ * contents behind: calls that overlap on one device (several streams or
+ * threads) race and must be ordered by the caller.
+ */
+int fpm_backward_noalloc(fpm_plan* plan, const fpm_c32* O, const fpm_c32* P,
+                         const int32_t* leds, int32_t B, const float* gamma,
+                         const float* meas_amp, fpm_c32* gO, fpm_c32* gP, double* loss,
+                         void* stream);
+
+/*
  * Projection of a pupil gradient onto its phase parameters:
  *   g_theta(u) = Im(gP(u) conj(P(u))),
  *   g_par[j] += sum_u g_theta(u) Z_j(u)  (j < 15),  g_par[15] += sum_u g_theta(u) kappa(u)

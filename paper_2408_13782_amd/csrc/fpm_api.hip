@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstring>
 #include <exception>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -1007,6 +1008,90 @@ int fpm_backward(fpm_plan* p, const fpm_c32* O, const fpm_c32* P, const int32_t*
     if (int rc = launch_update(p, a, 1, st)) return rc;
   }
   return FPM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Scratch of fpm_backward_noalloc, in a file-scope device array instead of the
+// plan's allocations: the row/column intermediate X (kNoAllocXBytes) followed by
+// the column pass's loss partials (kNoAllocPartBytes). Each device the library
+// runs on holds its own copy from module load to process exit; its host-side
+// name is only a stand-in, so host code uses the device address that
+// hipGetSymbolAddress returns, looked up once per device.
+constexpr size_t kNoAllocXBytes = size_t(16) << 20;
+constexpr size_t kNoAllocPartBytes = size_t(256) << 10;
+__device__ __align__(256) unsigned char scratch[kNoAllocXBytes + kNoAllocPartBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch[kMaxDevices] = {};
+
+// Device address of this device's scratch (the current device), or an error.
+int scratch_of(int dev, unsigned char** out) {
+  if (dev < 0 || dev >= kMaxDevices) return fail(FPM_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FPM_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch[dev] = ptr;
+  }
+  *out = static_cast<unsigned char*>(g_scratch[dev]);
+  return FPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fpm_backward_noalloc(fpm_plan* p, const fpm_c32* O, const fpm_c32* P, const int32_t* leds,
+                         int32_t B, const float* gamma, const float* meas_amp, fpm_c32* gO,
+                         fpm_c32* gP, double* loss, void* stream) {
+  return guarded([&]() -> int {
+    FPM_REQUIRE(p && O && P && meas_amp && gO, "plan, O, P, meas_amp and gO must not be NULL");
+    if (int rc = check_batch(p, leds, B)) return rc;
+    if (int rc = check_device(p)) return rc;
+    const size_t x_bytes = (size_t)std::min(B, kMaxSlots) * p->N * p->N * sizeof(float2);
+    const size_t part_bytes = (size_t)cols_grid_of(p, B) * sizeof(double);
+    if (x_bytes > kNoAllocXBytes || part_bytes > kNoAllocPartBytes) {
+      char buf[200];
+      std::snprintf(buf, sizeof buf,
+                    "batch of %d at N = %d needs %zu + %zu bytes of scratch; the allocation-free "
+                    "entry point has %zu + %zu",
+                    B, p->N, x_bytes, part_bytes, kNoAllocXBytes, kNoAllocPartBytes);
+      return fail(FPM_EINVAL, buf);
+    }
+    if (B == 0) return FPM_OK;
+    unsigned char* base = nullptr;
+    if (int rc = scratch_of(p->device, &base)) return rc;
+    double* part = reinterpret_cast<double*>(base + kNoAllocXBytes);
+    BackwardOut o;
+    o.mode = gP ? kGradOP : kGradO;
+    o.gP = reinterpret_cast<float2*>(gP);
+    o.loss = loss != nullptr;
+    o.X = reinterpret_cast<float2*>(base);
+    hipStream_t st = (hipStream_t)stream;
+    for (int g = 0; g < n_groups(B); ++g) {
+      const Group gr = group_of(p, B, g);
+      o.loss_part = part + gr.cols_off;
+      if (int rc = dispatch_backward(p, reinterpret_cast<const float2*>(O),
+                                     reinterpret_cast<const float2*>(P), leds + gr.b0, gr.B,
+                                     gamma, meas_amp, reinterpret_cast<float2*>(gO), o, st))
+        return rc;
+    }
+    if (loss) {   // add the column pass's partials (fixed order)
+      UpdateArgs a{};
+      a.n = p->N;
+      a.loss_part = part;
+      a.n_loss = cols_grid_of(p, B);
+      a.loss = loss;
+      if (int rc = launch_update(p, a, 1, st)) return rc;
+    }
+    return FPM_OK;
+  });
 }
 
 int fpm_pupil_grad(fpm_plan* p, const fpm_c32* gP, const fpm_c32* P, double* g_par,

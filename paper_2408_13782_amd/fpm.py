@@ -93,6 +93,9 @@ EXPORTS = {
                     C.c_void_p, C.c_void_p, C.c_void_p],
     "fpm_backward": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32, C.c_void_p,
                      C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
+    "fpm_backward_noalloc": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_int32,
+                             C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p,
+                             C.c_void_p],
     "fpm_pupil_grad": [C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p, C.c_void_p],
     "fpm_step": [C.c_void_p, C.POINTER(_State), C.POINTER(_HParams), C.c_void_p, C.c_int32,
                  C.c_void_p, C.c_void_p, C.c_void_p],
@@ -438,6 +441,21 @@ class Plan:
         _need(loss, "loss", torch.float64, min_numel=1, optional=True)
         _check(self._lib.fpm_backward(self._h, _ptr(O), _ptr(P), ids.ctypes.data, B, _ptr(gamma),
                                       _ptr(meas_amp), _ptr(gO), _ptr(gP), _ptr(loss), _stream()))
+
+    def backward_noalloc(self, O, P, leds, meas_amp, gO, gP=None, loss=None, gamma=None):
+        """backward() through fpm_backward_noalloc: no device memory of the plan's,
+        a static array of the library instead (see include/fpm.h for its limit)."""
+        import torch
+        self._spectrum(O)
+        self._pupil(P)
+        ids, B = self._leds(leds)
+        self._images(meas_amp, gamma)
+        self._spectrum(gO, "gO")
+        _need(gP, "gP", torch.complex64, (self.N, self.N), optional=True)
+        _need(loss, "loss", torch.float64, min_numel=1, optional=True)
+        _check(self._lib.fpm_backward_noalloc(self._h, _ptr(O), _ptr(P), ids.ctypes.data, B,
+                                              _ptr(gamma), _ptr(meas_amp), _ptr(gO), _ptr(gP),
+                                              _ptr(loss), _stream()))
 
     def pupil_grad(self, gP, P, g_par):
         import torch

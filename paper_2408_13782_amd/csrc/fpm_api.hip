@@ -581,6 +581,7 @@ int launch_loss_grad(fpm_plan* p, const fpm_led_grid* grid, const fpm_params* pr
 }
 
 static_assert(sizeof(MultiUpdateArgs) <= 4096, "kernel arguments are limited to 4 KiB");
+static_assert(sizeof(UpdateArgs) <= 4096, "kernel arguments are limited to 4 KiB");
 
 // One fused multi-parameter step: parameters of this step in block `cur`,
 // the next ones written to `next`. The batch's slot offsets live in sub_cur:
@@ -676,6 +677,32 @@ int launch_multi_step(fpm_plan* p, const GeomArgs& ga, fpm_state* s, const fpm_g
   FPM_HIP(hipGetLastError());
   s->t = t;
   return FPM_OK;
+}
+
+// The batch slots that meet each tile row and tile column of the Adam
+// rectangle (a slot meets a row of tiles when its window's disk rows overlap
+// the row's 32 HR rows; columns alike): a tile's slots are the AND of its row's
+// and its column's masks, the bounding-box test of the window's disk.
+void tile_masks(const fpm_plan* p, UpdateArgs& a) {
+  const int cols = p->tile_cols, rows = cols > 0 ? p->n_tiles / cols : 0;
+  for (int i = 0; i < rows && i < kMaxTileSide; ++i) {
+    const int lo = 32 * (p->tile0.x + i), hi = lo + 31;
+    unsigned long long m = 0ull;
+    for (int b = 0; b < a.bt.B; ++b) {
+      const int wr = a.bt.win[b].x;
+      if (!(hi < wr + p->ky_lo || lo > wr + p->ky_hi)) m |= 1ull << b;
+    }
+    a.hit_row[i] = m;
+  }
+  for (int j = 0; j < cols && j < kMaxTileSide; ++j) {
+    const int lo = 32 * (p->tile0.y + j), hi = lo + 31;
+    unsigned long long m = 0ull;
+    for (int b = 0; b < a.bt.B; ++b) {
+      const int wc = a.bt.win[b].y;
+      if (!(hi < wc + p->ky_lo || lo > wc + p->ky_hi)) m |= 1ull << b;
+    }
+    a.hit_col[j] = m;
+  }
 }
 
 int launch_update(fpm_plan* p, const UpdateArgs& a, int grid, hipStream_t st) {
@@ -1166,6 +1193,7 @@ int step_launches(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_
     a.tile0 = p->tile0;
     a.tile_cols = p->tile_cols;
     a.M = p->M;
+    tile_masks(p, a);
     a.gacc = reinterpret_cast<float*>(p->gacc);
     a.acc_in = g > 0;
     a.acc_out = !last;

@@ -104,6 +104,9 @@ struct ScalarAdam {
 //  group's gathered sum, started from g_acc when acc_in, no Adam); the last
 //  group's launch starts its sums from g_acc (acc_in) and applies Adam. The
 //  additions then happen in batch order, as in a single pass.
+// Tiles per side of the update kernel's rectangle at most (M <= 4096).
+constexpr int kMaxTileSide = 128;
+
 struct UpdateArgs {
   int2 tile0; int tile_cols; int M;   // the rectangle of tiles: first tile, width
   float* O; float* mO; float* vO;
@@ -116,12 +119,20 @@ struct UpdateArgs {
   const double* zpart; int n_zpart;
   ScalarState cur; ScalarAdam sa; double* g_par; float* staging;
   PupilGeom pg; const int2* rowext; float2* P;
+  // batch slots whose window's disk rows (columns) meet tile row (column) i of
+  // the rectangle: a tile's slots are hit_row[row] & hit_col[column]
+  unsigned long long hit_row[kMaxTileSide], hit_col[kMaxTileSide];
 };
 
-// Pupil rows rebuilt per workgroup of the update kernels (about 512 points or
+// Pupil rows rebuilt per workgroup of the update kernels (about 256 points or
 // fewer each). Every pupil workgroup first sums all of the row pass's moment
 // partials, so only rows that hold disk points get a workgroup.
-__host__ __device__ constexpr int pupil_rows_per_wg(int n) { return n <= 64 ? 8 : n <= 128 ? 4 : 2; }
+// One disk row per workgroup up to N = 256 (at most N threads' worth of points,
+// so every thread rebuilds at most one); two above, where the pupil workgroups
+// (summing many more moment partials) are not on the kernel's critical path.
+__host__ __device__ constexpr int pupil_rows_per_wg(int n) {
+  return n <= 64 ? 8 : n <= 128 ? 4 : n <= 256 ? 1 : 2;
+}
 __host__ __device__ constexpr int pupil_wg_count(int n, int disk_rows) {
   return (disk_rows + pupil_rows_per_wg(n) - 1) / pupil_rows_per_wg(n);
 }
@@ -158,6 +169,18 @@ __device__ __forceinline__ void add_batch_loss(const double* __restrict__ part, 
   if (threadIdx.x == 0) *loss = prev + (((wsum[0] + wsum[1]) + wsum[2]) + wsum[3]);
 }
 
+// exp(i th) rounded to complex64: th reduced to [-pi, pi] in FP64 (exact to
+// FP64 rounding for the phases of a pupil), then the FP32 sine and cosine of
+// the reduced angle, whose error (an FP32 ulp) is that of the final rounding;
+// an FP64 sincos costs several times the instructions for the same stored value.
+__device__ __forceinline__ float2 unit_phasor(double th) {
+  constexpr double kTwoPi = 6.283185307179586;
+  const double r = th - kTwoPi * rint(th * (1.0 / kTwoPi));
+  float sn, cs;
+  sincosf((float)r, &sn, &cs);
+  return make_float2(cs, sn);
+}
+
 // Pupil workgroup pw rebuilds P on the disk points of disk rows pw R .. pw R + R - 1
 // (R = pupil_rows_per_wg(N)) from the phase coefficients coef[0..14] (Zernike)
 // and, with `defocus`, coef[15] (z); the workgroup's 256 threads are spread
@@ -178,6 +201,15 @@ __device__ __forceinline__ void rebuild_pupil_rows(int pw, const Disk& dk, const
     first[r] = e.x;
     total += max(e.y - e.x + 1, 0);
   }
+  // the phase as a polynomial in the monomials x^a y^b (a + b <= 4):
+  // sum_j c_j Z_j = sum_k (sum_j c_j kZernMono[j][k]) x^a y^b
+  __shared__ double mono[kMono];
+  if (threadIdx.x < kMono) {
+    double m = 0.0;
+    for (int j = 0; j < kZern; ++j) m += (double)coef[j] * kZernMono[j][threadIdx.x];
+    mono[threadIdx.x] = m;
+  }
+  __syncthreads();
   for (int i = threadIdx.x; i < total; i += 256) {
     if constexpr (kReload) asm volatile("" ::: "memory");
     int r = 0, s0 = 0, x0 = first[0];
@@ -186,15 +218,13 @@ __device__ __forceinline__ void rebuild_pupil_rows(int pw, const Disk& dk, const
       if (i >= start[q]) { r = q; s0 = start[q]; x0 = first[q]; }
     const int ky = dk.ky_lo + r0 + r, kx = x0 + (i - s0);
     const double ux = kx - N / 2, uy = ky - N / 2;
-    double z[kZern];
-    zernike15(ux * pg.inv_r, uy * pg.inv_r, z);
-    double th = 0.0;
-#pragma unroll
-    for (int q = 0; q < kZern; ++q) th += (double)coef[q] * z[q];
+    const double x = ux * pg.inv_r, y = uy * pg.inv_r;
+    const double x2 = x * x, y2 = y * y, xy = x * y;
+    double th = mono[0] + mono[1] * x + mono[2] * y + mono[3] * x2 + mono[4] * xy + mono[5] * y2;
+    th += (mono[6] * x + mono[7] * y) * x2 + (mono[8] * x + mono[9] * y) * y2;
+    th += (mono[10] * x2 + mono[11] * xy + mono[12] * y2) * x2 + (mono[13] * xy + mono[14] * y2) * y2;
     if (defocus) th += (double)coef[kZern] * defocus_kappa((ux * ux + uy * uy) * pg.dk2, pg.inv_l);
-    double sn, cs;
-    sincos(th, &sn, &cs);
-    P[(size_t)ky * N + kx] = make_float2((float)cs, (float)sn);
+    P[(size_t)ky * N + kx] = unit_phasor(th);
   }
 }
 
@@ -203,26 +233,25 @@ __device__ __forceinline__ void rebuild_pupil_rows(int pw, const Disk& dk, const
 // disk covers them.
 // g holds the running sums on entry (zero, or the earlier groups' sums).
 template <int N>
-__device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int c0, int tile_r0,
-                                                int tile_c0, float2 (&g)[4]) {
-  // slots whose disk bounding box meets this 32 x 32 tile (uniform over the workgroup)
-  unsigned long long hit = 0ull;
-  for (int b = 0; b < a.bt.B; ++b) {
-    const int wr = a.bt.win[b].x, wc = a.bt.win[b].y;
-    const bool meets = !(tile_r0 + 31 < wr + a.dk.ky_lo || tile_r0 > wr + a.dk.ky_hi ||
-                         tile_c0 + 31 < wc + a.dk.ky_lo || tile_c0 > wc + a.dk.ky_hi);
-    if (meets) hit |= 1ull << b;
-  }
+__device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int c0, int tr, int tc,
+                                                float2 (&g)[4]) {
+  // slots whose disk bounding box meets this 32 x 32 tile (uniform over the
+  // workgroup), from the per-row and per-column masks of the launch
+  unsigned long long hit = a.hit_row[tr] & a.hit_col[tc];
   constexpr int kRound = 4;
   while (hit) {
-    // kRound slots per round: all loads issued (at addresses clamped into the
-    // disk) before the masked, in-order accumulation
+    // kRound slots per round: their windows read together, then all loads
+    // issued (at addresses clamped into the disk) before the masked, in-order
+    // accumulation
     int bs[kRound];
+    int2 wv[kRound];
 #pragma unroll
     for (int u = 0; u < kRound; ++u) {
       bs[u] = hit ? __ffsll((long long)hit) - 1 : -1;
       if (hit) hit &= hit - 1;
     }
+#pragma unroll
+    for (int u = 0; u < kRound; ++u) wv[u] = a.bt.win[bs[u] < 0 ? bs[0] : bs[u]];
     float2 val[kRound][4];
     bool ok[kRound][4];
 #pragma unroll
@@ -234,7 +263,7 @@ __device__ __forceinline__ void gather_gradient(const UpdateArgs& a, int r, int 
       }
       if (bs[u] < 0) continue;   // uniform: no loads for an empty slot
       const int b = bs[u];
-      const int wr = a.bt.win[b].x, wc = a.bt.win[b].y;
+      const int wr = wv[u].x, wc = wv[u].y;
       const int ky = r - wr;
       const int kyc = min(max(ky, a.dk.ky_lo), a.dk.ky_hi);
       const int2 e = disk_extent<N>(a.dk, kyc);
@@ -287,7 +316,7 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
       g[2 * h] = make_float2(gi[h].x, gi[h].y);
       g[2 * h + 1] = make_float2(gi[h].z, gi[h].w);
     }
-    gather_gradient<N>(a, r, col, tl.x * 32, tl.y * 32, g);
+    gather_gradient<N>(a, r, col, tr, i - tr * a.tile_cols, g);
     if (a.acc_out) {
 #pragma unroll
       for (int h = 0; h < 2; ++h)
@@ -321,7 +350,8 @@ __global__ void __launch_bounds__(256) update(UpdateArgs a) {
     // (independent loads in flight, then a fixed summation order)
     const int j = threadIdx.x & (kPar - 1);
     double sj = 0.0;
-    constexpr int kStride = 256 / kPar, kUnroll = 24;
+    // 40 loads per thread in flight: all 640 partials of a batch of 16 at N = 256
+    constexpr int kStride = 256 / kPar, kUnroll = 40;
     for (int i0 = threadIdx.x / kPar; i0 < a.n_zpart; i0 += kStride * kUnroll) {
       double vals[kUnroll];
 #pragma unroll

@@ -189,9 +189,12 @@ __device__ __forceinline__ int2 disk_extent(const Disk& dk, int ky) {
   const int uy = ky - N / 2;
   const int q = dk.r2i - uy * uy;
   if (q < 0) return make_int2(N, -1);
-  int h = (int)sqrtf((float)q);
-  while (h * h > q) --h;
-  while ((h + 1) * (h + 1) <= q) ++h;
+  // floor(sqrt(q)): sqrt(q + 1/2) is never an integer and lies far enough from
+  // one (at least 1/(4 sqrt(q + 1))) for a float square root to truncate to the
+  // exact value for q < 2^22; the two selects keep it exact without loops
+  int h = (int)sqrtf((float)q + 0.5f);
+  h -= h * h > q ? 1 : 0;
+  h += (h + 1) * (h + 1) <= q ? 1 : 0;
   return make_int2(N / 2 - h, N / 2 + h);
 }
 

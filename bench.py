@@ -91,6 +91,11 @@ def kernel_work(plan, B: int):
     be non-zero; with a learned geometry, U at the plan's table)."""
     N, S, rows = plan.N, plan.info.support_px, plan.info.support_rows
     U = union_support_px(plan)
+    if plan.info.fused_chain:
+        # the loss and its adjoint in one launch (crop, both 2-D transforms of the
+        # disk rows and all columns, the patch write): the chain's bytes and flops
+        chain = (16.0 * S * B + 4.0 * N * N * B, (2 * rows + 2 * N) * fft_flops(N) * B)
+        return {"chain_fused": chain, "update": (48.0 * U + 8.0 * S * B, 0.0)}, U
     return {
         # crop: read the spectrum on the pupil disk; 'rows' inverse DFTs of length N
         "rows_forward": (8.0 * S * B, rows * fft_flops(N) * B),
@@ -423,7 +428,8 @@ def main():
                       "valu_frac": flops / dur_s / 1e12 / FP32_VALU_PEAK_TFLOPS,
                       "traffic": traffic.get(k) if traffic else None}
     # the headline roofline: the fwd+bwd chain (a3-a7) of one batch
-    chain = ("rows_forward", "cols", "rows_backward")
+    chain = (("chain_fused",) if plan.info.fused_chain
+             else ("rows_forward", "cols", "rows_backward"))
     chain_s = sum(timed[k] for k in chain) / 1e3
     S, N = plan.info.support_px, plan.N
     chain_bytes = (16.0 * S + 4.0 * N * N) * B
@@ -432,13 +438,13 @@ def main():
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
             "traffic": sum(traffic[k] for k in chain) if traffic else None,
-            "kernel": "rows_forward + cols + rows_backward (the fwd+bwd chain of one batch)",
+            "kernel": " + ".join(chain) + " (the fwd+bwd chain of one batch)",
             "mean_us": chain_s * 1e6, "algorithmic_bytes": chain_bytes,
             "valu_tflops": chain_flops / chain_s / 1e12,
             "valu_frac": chain_flops / chain_s / 1e12 / FP32_VALU_PEAK_TFLOPS,
             "build": fpm.build_tag()}
     fwd_bwd = {"led_images_per_s": B / chain_s, "us_per_batch": chain_s * 1e6,
-               "timing": "sum of the three chain kernels' mean durations (HIP events on the "
+               "timing": "sum of the chain kernels' mean durations (HIP events on the "
                          "launch stream around 20 back-to-back launches of each)"}
     detail = {
         "kernels": kernels,

@@ -95,6 +95,9 @@ typedef struct {
   double pupil_radius_px;  /* NA / lambda / dk */
   double dk;               /* spectral pitch, 1/um */
   int64_t device_bytes;    /* device memory the plan holds (its scratch and tables) */
+  int32_t fused_chain;     /* 1: a step runs the loss and its adjoint as one launch
+                              (N = 64: the image stays in one CU's LDS), then the
+                              update; 0: three passes (rows, columns, rows), then the update */
 } fpm_info;
 
 /*

@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libfpm.so")
 
 SOURCES = ["fpm_api.hip", "fpm_serve.hip"]
-HEADERS = ["fft_line.hpp", "fpm_kernels.hpp", "fpm_aux.hpp", "fpm_subpixel.hpp"]
+HEADERS = ["fft_line.hpp", "fpm_kernels.hpp", "fpm_aux.hpp", "fpm_subpixel.hpp", "fpm_fused.hpp"]
 
 # Packed FP32 instructions are disabled on purpose (some of their forms have given
 # unreliable results on this target).

@@ -16,6 +16,7 @@
 
 #include "fpm.h"
 #include "fpm_aux.hpp"
+#include "fpm_fused.hpp"
 #include "fpm_kernels.hpp"
 #include "fpm_subpixel.hpp"
 
@@ -115,10 +116,11 @@ int upload(size_t* total, T** dst, const T* src, size_t count) {
 
 enum Kind {
   kPupilBuild, kRowsForward, kCols, kRowsBackward, kPupilGrad, kAdamObject, kAdamScalars,
-  kHrRows, kHrCols, kKinds
+  kHrRows, kHrCols, kChainFused, kKinds
 };
 const char* const kKindNames[kKinds] = {"pupil_build", "rows_forward", "cols", "rows_backward",
-                                        "pupil_grad", "update", "commit", "hr_rows", "hr_cols"};
+                                        "pupil_grad", "update", "commit", "hr_rows", "hr_cols",
+                                        "chain_fused"};
 constexpr size_t kMaxTimed = 65536;
 
 struct TimedLaunch {
@@ -452,6 +454,36 @@ int launch_forward(fpm_plan* p, const float2* O, const float2* P, const int32_t*
   }
   FPM_HIP(hipGetLastError());
   return FPM_OK;
+}
+
+// The step's loss and adjoint in one launch (chain_fused) where an N x N image
+// fits one CU's LDS: one workgroup per slot, one loss partial and one set of
+// moment partials per slot.
+bool fused_chain(const fpm_plan* p) { return p->N == 64; }
+
+template <int N>
+int launch_fused(fpm_plan* p, const float2* O, const float2* P, const int32_t* leds, int B,
+                 const float* gamma, const float* A, const BackwardOut& o, hipStream_t st) {
+  if constexpr (!FusedSupported<N>::value) {
+    return fail(FPM_EUNSUPPORTED, "the single-launch chain serves N = 64");
+  } else {
+    const Batch bt = batch_of(p, leds, B);
+    const Disk dk = disk_of(p);
+    const PupilGeom pg = pupil_geom(p);
+    Timed tm(p, kChainFused, st);
+    for (int r = 0; r < tm.reps; ++r) {
+      if (o.mode == kPatchZern)
+        chain_fused<N, kPatchZern><<<B, Fused<N>::threads, 0, st>>>(
+            O, P, A, gamma, bt, dk, pg, p->X, p->twN, p->kappa_tab, o.loss_part, o.zpart,
+            1.0f / p->M, o.commit, p->staging, o.scal);
+      else
+        chain_fused<N, kPatch><<<B, Fused<N>::threads, 0, st>>>(
+            O, P, A, gamma, bt, dk, pg, p->X, p->twN, p->kappa_tab, o.loss_part, nullptr,
+            1.0f / p->M, o.commit, p->staging, o.scal);
+    }
+    FPM_HIP(hipGetLastError());
+    return FPM_OK;
+  }
 }
 
 int dispatch_backward(fpm_plan* p, const float2* O, const float2* P, const int32_t* leds, int B,
@@ -938,6 +970,7 @@ int fpm_plan_info(const fpm_plan* p, fpm_info* info) {
   info->pupil_radius_px = p->radius;
   info->dk = p->dk;
   info->device_bytes = (int64_t)p->device_bytes;
+  info->fused_chain = fused_chain(p) ? 1 : 0;
   return FPM_OK;
 }
 
@@ -1171,6 +1204,7 @@ int step_launches(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_
   const double b1 = hp->beta1, b2 = hp->beta2;
   const double bc1 = 1.0 - std::pow(b1, t), bc2 = 1.0 - std::pow(b2, t);
   float2* P = reinterpret_cast<float2*>(s->P);
+  const bool fused = fused_chain(p);
   const int G = n_groups(B);
   for (int g = 0; g < G; ++g) {
     const Group gr = group_of(p, B, g);
@@ -1180,11 +1214,21 @@ int step_launches(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_
     o.loss = s->loss != nullptr;
     o.commit = commit && g == 0;
     o.scal = scalar_state_of(s);
-    o.loss_part = p->part_loss + gr.cols_off;
-    o.zpart = p->part_z + (size_t)gr.rows_off * kPar;
-    if (int rc = dispatch_backward(p, reinterpret_cast<const float2*>(s->O), P, leds + gr.b0,
-                                   gr.B, gamma, meas_amp, nullptr, o, st))
-      return rc;
+    if (fused) {
+      o.loss_part = p->part_loss + gr.b0;
+      o.zpart = p->part_z + (size_t)gr.b0 * kPar;
+      if (int rc = with_lr_size(p->N, [&](auto n) {
+            return launch_fused<decltype(n)::value>(p, reinterpret_cast<const float2*>(s->O), P,
+                                                    leds + gr.b0, gr.B, gamma, meas_amp, o, st);
+          }))
+        return rc;
+    } else {
+      o.loss_part = p->part_loss + gr.cols_off;
+      o.zpart = p->part_z + (size_t)gr.rows_off * kPar;
+      if (int rc = dispatch_backward(p, reinterpret_cast<const float2*>(s->O), P, leds + gr.b0,
+                                     gr.B, gamma, meas_amp, nullptr, o, st))
+        return rc;
+    }
     UpdateArgs a{};
     a.X = p->X;
     a.bt = batch_of(p, leds + gr.b0, gr.B);
@@ -1207,11 +1251,11 @@ int step_launches(fpm_plan* p, fpm_state* s, const fpm_hparams* hp, const int32_
       a.c.step_size = (float)(hp->lr_object / bc1);
       a.c.sqrt_bc2 = (float)std::sqrt(bc2);
       a.loss_part = p->part_loss;
-      a.n_loss = cols_grid_of(p, B);
+      a.n_loss = fused ? B : cols_grid_of(p, B);
       a.loss = s->loss;
       a.pupil = learn_p;
       a.zpart = p->part_z;
-      a.n_zpart = rows_grid_of(p, B);
+      a.n_zpart = fused ? B : rows_grid_of(p, B);
       a.cur = o.scal;
       a.sa.learn_c = learn_c;
       a.sa.learn_z = learn_z;

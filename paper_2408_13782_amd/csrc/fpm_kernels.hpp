@@ -437,6 +437,37 @@ rows_forward(const float2* __restrict__ O, const float2* __restrict__ P, Batch b
   }
 }
 
+// The loss term of one pixel and the factor that turns the inverse DFT's output
+// v = M psi into the residual's input to the forward DFT (Eqs. 4-5). Both 1/M
+// scalings (of psi and of the residual's forward transform, which is linear)
+// are folded into the factor. acc += e^2; with kGamma, acc_ea += the pixel's
+// term of dL/dgamma (e |psi| for the amplitude loss, e |psi|^2 for intensity).
+template <bool kGamma>
+__device__ __forceinline__ float residual_factor(float2 v, float a_meas, float sg, int intensity,
+                                                 float inv_m, float& acc, float& acc_ea) {
+  const float inv_m2 = inv_m * inv_m, m_side = 1.f / inv_m;
+  const float qv = v.x * v.x + v.y * v.y;   // M^2 |psi|^2
+  if (intensity) {
+    // e = gamma |psi|^2 - A^2, g_psi = 4 gamma e psi; dL/dgamma = 2 sum e |psi|^2
+    const float q = qv * inv_m2;
+    const float e = sg * sg * q - a_meas * a_meas;
+    acc += e * e;
+    if constexpr (kGamma) acc_ea += e * q;
+    return 4.f * sg * sg * e * inv_m2;
+  }
+  // e = sqrt(gamma) |psi| - A and g_psi = 2 sqrt(gamma) e psi/|psi|
+  //   = 2 sqrt(gamma) (sqrt(gamma) - A/|psi|) psi, with 1/|psi| from one
+  // reciprocal square root (1 ulp) instead of a square root and a division;
+  // where |psi|^2 is below the normal range, 1/|psi| is taken as 0 (then
+  // e = -A and g_psi vanishes with psi)
+  const float rv = qv >= FLT_MIN ? __builtin_amdgcn_rsqf(qv) : 0.f;   // 1/(M |psi|)
+  const float a = qv * rv * inv_m;
+  const float e = sg * a - a_meas;
+  acc += e * e;
+  if constexpr (kGamma) acc_ea += e * a;
+  return 2.f * sg * (sg - a_meas * rv * m_side) * inv_m2;
+}
+
 // Column pass: inverse DFT along k_y, amplitude loss, residual, forward DFT.
 // kForward: write amplitudes (and fields) instead of the residual transform.
 template <int N, bool kForward, bool kGamma = false>
@@ -485,35 +516,10 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
         if (field_out) field_out[o] = psi;
       }
     } else {
-      // v = M psi here. Both 1/M scalings (of psi and of the residual's forward
-      // transform, which is linear) are folded into one factor k on v.
-      const float inv_m2 = inv_m * inv_m, m_side = 1.f / inv_m;
 #pragma unroll
-      for (int m = 0; m < E; ++m) {
-        const float qv = v[m].x * v[m].x + v[m].y * v[m].y;   // M^2 |psi|^2
-        float k;
-        if (bt.intensity) {
-          // e = gamma |psi|^2 - A^2, g_psi = 4 gamma e psi; dL/dgamma = 2 sum e |psi|^2
-          const float q = qv * inv_m2;
-          const float e = sg * sg * q - a_meas[m] * a_meas[m];
-          acc += e * e;
-          if constexpr (kGamma) acc_ea += e * q;
-          k = 4.f * sg * sg * e * inv_m2;
-        } else {
-          // e = sqrt(gamma) |psi| - A and g_psi = 2 sqrt(gamma) e psi/|psi|
-          //   = 2 sqrt(gamma) (sqrt(gamma) - A/|psi|) psi, with 1/|psi| from one
-          // reciprocal square root (1 ulp) instead of a square root and a division;
-          // where |psi|^2 is below the normal range, 1/|psi| is taken as 0 (then
-          // e = -A and g_psi vanishes with psi)
-          const float rv = qv >= FLT_MIN ? __builtin_amdgcn_rsqf(qv) : 0.f;   // 1/(M |psi|)
-          const float a = qv * rv * inv_m;
-          const float e = sg * a - a_meas[m];
-          acc += e * e;
-          if constexpr (kGamma) acc_ea += e * a;
-          k = 2.f * sg * (sg - a_meas[m] * rv * m_side) * inv_m2;
-        }
-        v[m] = cscale(v[m], k);
-      }
+      for (int m = 0; m < E; ++m)
+        v[m] = cscale(v[m], residual_factor<kGamma>(v[m], a_meas[m], sg, bt.intensity, inv_m, acc,
+                                                    acc_ea));
       ColPlan<N>::template run<-1>(v, t, lds, lay, lds_tw);
 #pragma unroll
       for (int m = 0; m < E; ++m) {
@@ -530,6 +536,22 @@ cols(float2* __restrict__ X, const float* __restrict__ A, const float* __restric
       if (loss_part) block_partials<1>(&acc, loss_part);
     }
   }
+}
+
+// One disk pixel's share of the Zernike/defocus moments: with g_P = conj(C) g_Phi
+// and g_theta = Im(g_P conj(P)) (P = mask exp(i theta)), the row sums
+// S = (sum g_theta x^a for a = 0..4, sum g_theta kappa), x = u_x / R.
+__device__ __forceinline__ void add_row_moments(float2 g, float2 p, float2 c, float xx, float kap,
+                                                float (&S)[6]) {
+  const float2 gp = cmulc(c, g);                  // conj(C) g_Phi
+  const float gth = gp.y * p.x - gp.x * p.y;      // Im(g_P conj(P))
+  const float gx = gth * xx, gx2 = gx * xx, gx3 = gx2 * xx;
+  S[0] += gth;
+  S[1] += gx;
+  S[2] += gx2;
+  S[3] += gx3;
+  S[4] += gx3 * xx;
+  S[5] += gth * kap;
 }
 
 // kGradO: g_O scatter-added with atomics; kGradOP: and g_P; kPatch: conj(P) g_Phi
@@ -589,8 +611,6 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
     PlanT<N, T>::template run<-1>(v, t, lds + line * RowLds<N>::kStride, [](int n) { return RowLds<N>::at(n); }, lds_tw);
     if (active) {
       const float ir = (float)pg.inv_r;
-      // row moments S_a = sum g_theta x^a (a <= 4) and sum g_theta kappa
-      float S0 = 0.f, S1 = 0.f, S2 = 0.f, S3 = 0.f, S4 = 0.f, SK = 0.f;
 #pragma unroll
       for (int m = 0; m < E; ++m) {
         const int kx = half_shift<N>(t + m * T);
@@ -605,27 +625,9 @@ rows_backward(float2* __restrict__ X, const float2* __restrict__ O,
           if constexpr (MODE == kGradOP) {
             atomic_add_c(gP + (size_t)ky * N + kx, cmulc(cv[m], g));
           } else if constexpr (MODE == kPatchZern) {
-            const float2 gp = cmulc(cv[m], g);                  // conj(C) g_Phi
-            const float gth = gp.y * p.x - gp.x * p.y;          // Im(g_P conj(P))
-            const int ux = kx - N / 2;
-            const float xx = (float)ux * ir;
-            const float gx = gth * xx, gx2 = gx * xx, gx3 = gx2 * xx;
-            S0 += gth;
-            S1 += gx;
-            S2 += gx2;
-            S3 += gx3;
-            S4 += gx3 * xx;
-            SK += gth * kap[m];
+            add_row_moments(g, p, cv[m], (float)(kx - N / 2) * ir, kap[m], zs);
           }
         }
-      }
-      if constexpr (MODE == kPatchZern) {
-        zs[0] = S0;
-        zs[1] = S1;
-        zs[2] = S2;
-        zs[3] = S3;
-        zs[4] = S4;
-        zs[5] = SK;
       }
     }
   }

@@ -41,7 +41,7 @@ class _Info(C.Structure):
                 ("max_batch", C.c_int32), ("support_px", C.c_int32),
                 ("support_rows", C.c_int32), ("adam_tiles", C.c_int32),
                 ("pupil_radius_px", C.c_double), ("dk", C.c_double),
-                ("device_bytes", C.c_int64)]
+                ("device_bytes", C.c_int64), ("fused_chain", C.c_int32)]
 
 
 class _Grid(C.Structure):

@@ -314,10 +314,12 @@ def test_step_pupil_parameter_gradients_match_oracle(dev):
     assert np.abs(H(st.P) - P1).max() <= 2e-6
 
 
-@pytest.mark.parametrize("n_lr,n_side,B", [(192, 11, 16), (384, 7, 13)])
+@pytest.mark.parametrize("n_lr,n_side,B", [(128, 11, 16), (128, 9, 5), (192, 11, 16),
+                                           (384, 7, 13)])
 def test_factor_three_sizes_backward_and_step_match_oracle(dev, n_lr, n_side, B):
-    """LR sizes 3 * 2^k (radix-12 transforms, HR 768 / 1536): gradients, loss and one
-    object + Zernike step against the oracle."""
+    """LR sizes 128 (whose step runs the loss and adjoint as one launch, the image
+    in LDS) and 3 * 2^k (radix-12 transforms, HR 768 / 1536): gradients, loss and
+    one object + Zernike step against the oracle."""
     w = inputs.workload("small", n_lr=n_lr, n_side=n_side, learn_zernike=True)
     say(f"factor-3 size N={n_lr} grid {n_side}x{n_side} B={B}")
     pr = oracle_problem(w, seed=2)

@@ -247,6 +247,47 @@ def multiparam_rate(w, prob, steps: int) -> dict:
             "fused_led_images_per_s": n_img / (ms_f / 1e3), "fused_ms_per_step": ms_f / steps}
 
 
+def chain_by_batch(w, batches=(16, 64)) -> list:
+    """The fwd+bwd chain's time per batch at several batch sizes on the same
+    workload shape (plans of their own, 6 steps per kernel bracket of 20
+    back-to-back launches): how much of the batch-of-16 time is the fixed cost
+    of the launches and their dependent latencies."""
+    import torch
+    from paper_2408_13782_amd import fpm, inputs, problem
+    from dataclasses import replace
+    out = []
+    for B in batches:
+        wb = replace(w, batch=B)
+        prob = problem.make_plan(wb)
+        problem.simulate(prob, seed=0)
+        plan = prob.plan
+        st = fpm.State(plan, problem.initial_spectrum(prob))
+        hp = problem.hparams(wb)
+        full = [b for b in problem.schedule(
+            inputs.led_permutations(wb.n_led, -(-40 // wb.steps_per_epoch()) + 1, seed=0), B)
+            if len(b) == B]                      # whole batches only
+        sched = problem.flatten_schedule(full)
+        plan.run(st, hp, *sched.span(0, 10), prob.meas_amp)
+        kinds = (("chain_fused",) if plan.info.fused_chain
+                 else ("rows_forward", "cols", "rows_backward"))
+        us = 0.0
+        for i, kind in enumerate(kinds):
+            plan.timing_repeat(kind, 20)
+            plan.timing(True)
+            plan.run(st, hp, *sched.span(10 + 6 * i, 16 + 6 * i), prob.meas_amp)
+            torch.cuda.synchronize()
+            plan.timing(False)
+            kt = plan.timing_collect()
+            us += 1e3 * kt[kind][0] / kt[kind][1]
+        plan.timing_repeat(None, 1)
+        S, N = plan.info.support_px, plan.N
+        alg = (16.0 * S + 4.0 * N * N) * B
+        out.append({"batch": B, "chain_us": us, "led_images_per_s": B / (us * 1e-6),
+                    "hbm_frac": alg / (us * 1e-6) / 1e9 / HBM_PEAK_GBS})
+        del prob, plan, st
+    return out
+
+
 def batch_sweep(w, batches, epochs: int, log) -> dict:
     """Random batches of several sizes (Eqs. 13-14) and the sequential fixed-order
     loop (Eq. 7) on the same synthetic data: quality of the object after each
@@ -452,6 +493,10 @@ def main():
         "support_px": S, "union_px": U,
     }
     if not w.learn_geometry:
+        detail["fwd_bwd_by_batch"] = chain_by_batch(w, (16, 64))
+        log("fwd+bwd chain by batch: " + ", ".join(
+            f"B={r['batch']}: {r['chain_us']:.1f} us ({r['hbm_frac'] * 100:.1f} % of HBM)"
+            for r in detail["fwd_bwd_by_batch"]))
         detail["multiparam"] = multiparam_rate(w, prob, 100)
         log(f"multi-parameter paths: fused {detail['multiparam']['fused_led_images_per_s']:.4g}, "
             f"autograd {detail['multiparam']['led_images_per_s']:.4g} LED-images/s")

@@ -77,3 +77,44 @@ def assert_grad_close(got, ref, tol: float = GRAD_TOL, elem_tol: float = GRAD_EL
     scale = float(np.abs(ref).max())
     assert worst <= elem_tol * scale, f"max entry error {worst:.3e} > {elem_tol:.0e} x {scale:.3e}"
     return err
+
+
+def subpixel_term_sums(O, P, shifts, leds, A, gamma=None, loss: str = "amplitude"):
+    """Per LED of a batch in the oracle's sub-pixel model (fractional offsets
+    `shifts`), the sums of the magnitudes of the terms that make up dL/ds (row,
+    column) and dL/dgamma: S[b] = (sum_u |Re(conj(g_C) dC/ds_row)|, same for the
+    column) and G[b] = the sum of the magnitudes of the per-pixel terms of
+    dL_b/dgamma. Those gradients are sums that cancel, so a float32 result is
+    judged against these sums (its rounding is a fraction of them), not against
+    its own size."""
+    n, m = P.shape[0], O.shape[0]
+    S = np.zeros((len(leds), 2))
+    G = np.zeros(len(leds))
+    for b, led in enumerate(leds):
+        C, (t00, t01, t10, t11), a, _, _ = fo.crop_bilinear(O, n, shifts[led])
+        psi = (n * n / m) * np.fft.ifft2(np.fft.ifftshift(C * P))
+        gb = 1.0 if gamma is None else float(gamma[led])
+        _, g_psi, _ = fo.residual(psi, A[led], gb, loss)
+        g_C, _ = fo.field_adjoint(g_psi, P, C, m)
+        dC_dy = (1 - a[1]) * (t10 - t00) + a[1] * (t11 - t01)
+        dC_dx = (1 - a[0]) * (t01 - t00) + a[0] * (t11 - t10)
+        S[b, 0] = np.abs(np.real(np.conj(g_C) * dC_dy)).sum()
+        S[b, 1] = np.abs(np.real(np.conj(g_C) * dC_dx)).sum()
+        mag = np.abs(psi)
+        amp = np.asarray(A[led], np.float64)
+        if loss == "amplitude":
+            e = np.sqrt(gb) * mag - amp
+            G[b] = np.sum(np.abs(e) * mag) / np.sqrt(gb)
+        else:
+            e = gb * mag * mag - amp * amp
+            G[b] = 2.0 * np.sum(np.abs(e) * mag * mag)
+    return S, G
+
+
+def geometry_term_scale(J, leds, S):
+    """sum_b |ds_b/dgeom|^T S[b]: the magnitude of every term of the geometry
+    gradient sum_b (ds_b/dgeom)^T dL/ds_b, per geometry parameter."""
+    scale = np.zeros(J.shape[-1])
+    for b, led in enumerate(leds):
+        scale += np.abs(J[led].T) @ S[b]
+    return scale

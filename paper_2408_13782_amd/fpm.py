@@ -491,6 +491,37 @@ class Plan:
                                  _stream()))
         state.t = cs.t
 
+    def prepare_run(self, state: State, hp: HParams, leds_flat, batch_sizes, meas_amp,
+                    gamma=None):
+        """fpm_run with its batches, images and hyper-parameters checked and
+        marshalled once: the returned callable issues the run (the same batches
+        each time, continuing from the state's step count) on the stream that is
+        current now, reading the state's tensors at each call. For runs issued
+        from Python in a loop, whose argument checks would otherwise precede
+        every call."""
+        sizes = np.ascontiguousarray(np.asarray(batch_sizes, np.int32))
+        ids, n = self._leds(leds_flat)
+        if int(sizes.sum()) > n:
+            raise FpmError("batch sizes exceed the number of LED ids")
+        self._images(meas_amp, gamma)
+        self._spectrum(state.O)
+        self._pupil(state.P)
+        cs = state.c()
+        hc = hp.c()
+        lib = self._lib
+        args = (self._h, C.byref(cs), C.byref(hc), ids.ctypes.data, sizes.ctypes.data,
+                int(sizes.size), _ptr(gamma), _ptr(meas_amp), _stream())
+        held = (ids, sizes, meas_amp, gamma, hp)
+
+        def go():
+            self._spectrum(state.O)
+            self._pupil(state.P)
+            state.c()
+            _check(lib.fpm_run(*args))
+            state.t = cs.t
+        go.held = held
+        return go
+
     def run_multi(self, grid: LedGrid, state: State, geometry: Geometry, hp: HParams, leds_flat,
                   batch_sizes, meas_amp):
         """Fused multi-parameter updates (fpm_run_multi): spectrum, Zernikes, defocus and

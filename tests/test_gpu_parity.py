@@ -396,6 +396,33 @@ def test_step_is_deterministic(dev):
         np.testing.assert_array_equal(a, b)
 
 
+def test_prepared_run_equals_run(dev):
+    """Plan.prepare_run: two calls of the prepared run (the same four batches
+    twice, the step count carried on) equal two calls of Plan.run, bitwise."""
+    w = inputs.workload("small", learn_zernike=True)
+    say("prepared run against run")
+    pr = oracle_problem(w, seed=2)
+    plan = make_plan(w, pr.shifts, w.batch)
+    ds = problem.flatten_schedule(problem.schedule(inputs.led_permutations(w.n_led, 1, seed=4),
+                                                   w.batch)[:4])
+    A = T(pr.A, dev)
+    hp = problem.hparams(w)
+    outs = []
+    for prepared in (False, True):
+        st = fpm.State(plan, T(pr.O0, dev))
+        go = plan.prepare_run(st, hp, ds.flat, ds.sizes, A) if prepared else None
+        for _ in range(2):
+            if prepared:
+                go()
+            else:
+                plan.run(st, hp, ds.flat, ds.sizes, A)
+        torch.cuda.synchronize()
+        assert st.t == 8
+        outs.append([H(t).copy() for t in (st.O, st.m_O, st.v_O, st.P, st.coeffs, st.loss)])
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
+
+
 def test_defocus_only_step_accepts_null_zernike_arrays(dev):
     """With only the defocus learned, the Zernike arrays of the state may be NULL
     (they stand for zeros): two steps give bitwise what zero arrays give."""

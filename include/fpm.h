@@ -206,7 +206,8 @@ int fpm_backward(fpm_plan* plan, const fpm_c32* O, const fpm_c32* P, const int32
  * B <= 8 at N = 512) and the column pass's partial sums within 256 KiB;
  * a larger batch fails with FPM_EINVAL before anything is enqueued. The call
  * allocates nothing (its first call on a device looks up the array's device
- * address once). Every call on one device shares that array and leaves its
+ * address once) and is not recorded by fpm_timing, whose events are created
+ * on demand. Every call on one device shares that array and leaves its
  * contents behind: calls that overlap on one device (several streams or
  * threads) race and must be ordered by the caller.
  */

@@ -186,6 +186,10 @@ hipEvent_t pool_event(fpm_plan* p) {
 // Brackets one launch with events when the plan's timing is on. With a repeat
 // set for this kind (fpm_timing_repeat), the launch site issues the kernel
 // `reps` times back to back inside the bracket.
+// Set while fpm_backward_noalloc runs on this thread: its launches are not
+// timed, since recording creates events and grows the record on demand.
+thread_local bool g_untimed = false;
+
 struct Timed {
   fpm_plan* p;
   int kind;
@@ -193,6 +197,7 @@ struct Timed {
   hipEvent_t start = nullptr;
   int reps = 1;
   Timed(fpm_plan* plan, int k, hipStream_t s) : p(plan), kind(k), st(s) {
+    if (g_untimed) return;
     if (p->timing && p->repeat_kind == k) reps = p->repeat_n;
     if (p->timing && p->timed.size() < kMaxTimed) {
       start = pool_event(p);
@@ -1127,6 +1132,10 @@ int fpm_backward_noalloc(fpm_plan* p, const fpm_c32* O, const fpm_c32* P, const 
     if (B == 0) return FPM_OK;
     unsigned char* base = nullptr;
     if (int rc = scratch_of(p->device, &base)) return rc;
+    struct Untimed {   // no timing events: they would be created on demand
+      Untimed() { g_untimed = true; }
+      ~Untimed() { g_untimed = false; }
+    } untimed;
     double* part = reinterpret_cast<double*>(base + kNoAllocXBytes);
     BackwardOut o;
     o.mode = gP ? kGradOP : kGradO;

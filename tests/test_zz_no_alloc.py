@@ -114,3 +114,32 @@ def test_noalloc_backward_refuses_batches_beyond_its_scratch(dev):
     backward_noalloc(plan, O, P, inputs.random_indices(w.n_led, 32, seed=1), A, gO, None, loss)
     torch.cuda.synchronize()
     assert float(H(loss)[0]) > 0.0
+
+
+def test_noalloc_backward_is_not_timed(dev):
+    """With the plan's timing on (fpm_timing), fpm_backward records its launches
+    while the allocation-free entry point records none (recording would create
+    events), and its results are unchanged."""
+    w = inputs.workload("small")
+    say("fpm_backward_noalloc under fpm_timing")
+    pr = oracle_problem(w, seed=3)
+    plan = fpm.Plan(w.n_lr, w.upsample, pr.shifts, 8, w.wavelength_um, w.na, w.mag, w.pixel_um)
+    O, A = T(pr.O0), T(pr.A)
+    P = plan.pupil()
+    leds = inputs.random_indices(w.n_led, 8, seed=6)
+    outs = []
+    for timed in (False, True):
+        gO = torch.zeros((w.m_hr, w.m_hr), dtype=torch.complex64, device=dev)
+        loss = torch.zeros(1, dtype=torch.float64, device=dev)
+        plan.timing(timed)
+        backward_noalloc(plan, O, P, leds, A, gO, None, loss)
+        torch.cuda.synchronize()
+        if timed:
+            assert plan.timing_collect() == {}
+            plan.backward(O, P, leds, A, torch.zeros_like(gO), None,
+                          torch.zeros_like(loss))
+            torch.cuda.synchronize()
+            assert len(plan.timing_collect()) > 0
+            plan.timing(False)
+        outs.append(H(loss).copy())
+    np.testing.assert_array_equal(outs[0], outs[1])

@@ -256,16 +256,16 @@ def chain_by_batch(w, batches=(16, 64)) -> list:
     from paper_2408_13782_amd import fpm, inputs, problem
     from dataclasses import replace
     out = []
-    for B in batches:
+    for B in [b for b in batches if b <= w.n_led]:   # a batch of at most every LED
         wb = replace(w, batch=B)
         prob = problem.make_plan(wb)
         problem.simulate(prob, seed=0)
         plan = prob.plan
         st = fpm.State(plan, problem.initial_spectrum(prob))
         hp = problem.hparams(wb)
-        full = [b for b in problem.schedule(
-            inputs.led_permutations(wb.n_led, -(-40 // wb.steps_per_epoch()) + 1, seed=0), B)
-            if len(b) == B]                      # whole batches only
+        epochs = -(-40 // (wb.n_led // B))        # 40 whole batches: 10 + 6 per kernel kind
+        full = [b for b in problem.schedule(inputs.led_permutations(wb.n_led, epochs, seed=0), B)
+                if len(b) == B]                      # whole batches only
         sched = problem.flatten_schedule(full)
         plan.run(st, hp, *sched.span(0, 10), prob.meas_amp)
         kinds = (("chain_fused",) if plan.info.fused_chain

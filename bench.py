@@ -363,7 +363,8 @@ def main():
     ap.add_argument("--serving-rates", type=float, nargs="+", default=[0.5, 0.9, 1.5],
                     help="arrival rates as multiples of the sequential service rate")
     ap.add_argument("--no-detail-sweep", dest="sweep_in_detail", action="store_false",
-                    help="skip the reduced batch-size sweep in the line's detail")
+                    help="skip the batch-size legs of the line's detail (the reduced "
+                         "sweep and the chain at batches of 16 and 64)")
     ap.add_argument("--detail-sweep-epochs", type=int, default=5)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -500,10 +501,11 @@ def main():
         "support_px": S, "union_px": U,
     }
     if not w.learn_geometry:
-        detail["fwd_bwd_by_batch"] = chain_by_batch(w, (16, 64))
-        log("fwd+bwd chain by batch: " + ", ".join(
-            f"B={r['batch']}: {r['chain_us']:.1f} us ({r['hbm_frac'] * 100:.1f} % of HBM)"
-            for r in detail["fwd_bwd_by_batch"]))
+        if args.sweep_in_detail:
+            detail["fwd_bwd_by_batch"] = chain_by_batch(w, (16, 64))
+            log("fwd+bwd chain by batch: " + ", ".join(
+                f"B={r['batch']}: {r['chain_us']:.1f} us ({r['hbm_frac'] * 100:.1f} % of HBM)"
+                for r in detail["fwd_bwd_by_batch"]))
         detail["multiparam"] = multiparam_rate(w, prob, 100)
         log(f"multi-parameter paths: fused {detail['multiparam']['fused_led_images_per_s']:.4g}, "
             f"autograd {detail['multiparam']['led_images_per_s']:.4g} LED-images/s")

@@ -591,6 +591,47 @@ def _gradient_at_gpu_state(dev, plan, pr, st, leds, P):
     return assert_grad_close(H(gO), ref.g_O)
 
 
+def test_intensity_loss_solve_with_pupil_learning_matches_oracle(dev):
+    """Two epochs of fpm_run (14 steps of B = 8, 7x7 LEDs, 64^2 -> 256^2) with the
+    intensity loss (Eq. 4), fixed LED intensities gamma, and the object,
+    Zernike coefficients and defocus all learned, against the oracle's solve
+    of the same schedule and configuration."""
+    w = inputs.workload("small", learn_zernike=True, learn_z=True)
+    say("intensity-loss solve with Zernike and defocus learning, 14 steps")
+    pr = oracle_problem(w, seed=5)
+    perms = inputs.led_permutations(w.n_led, 2, seed=8)
+    sched = fo.batches_from_permutations(perms, w.batch)
+    assert len(sched) == 14
+    gamma = inputs.random_real((w.n_led,), seed=9, lo=0.8, hi=1.2)
+    plan = make_plan(w, pr.shifts, w.batch)
+    plan.set_loss("intensity")
+    st = fpm.State(plan, T(pr.O0, dev), np.zeros(15), 0.0)
+    hp = problem.hparams(w)
+    assert hp.learn_zernike and hp.learn_z
+    ds = problem.flatten_schedule(problem.schedule(perms, w.batch))
+    plan.run(st, hp, ds.flat, ds.sizes, T(pr.A, dev), T(gamma.astype(np.float32), dev))
+    torch.cuda.synchronize()
+    ost = fo.init_state(pr.O0)
+    cfg = fo.SolveConfig(lr_object=w.lr_object, lr_zernike=w.lr_zernike, lr_z=w.lr_z,
+                         learn_pupil=True, learn_z=True, loss="intensity")
+    losses = fo.solve(ost, cfg, pr.mask, pr.zern, pr.kappa, pr.shifts, sched,
+                      pr.A.astype(np.float64), gamma.astype(np.float32).astype(np.float64))
+    err = rel_l2(H(st.O), ost.O)
+    c_err = float(np.abs(H(st.coeffs).astype(np.float64) - ost.coeffs).max())
+    z_err = abs(float(H(st.z_um)[0]) - ost.z_um)
+    say(f"final object rel err {err:.3e}, max Zernike diff {c_err:.2e} rad, "
+        f"defocus diff {z_err:.2e} um")
+    assert st.t == 14
+    assert err <= OBJ_TOL
+    assert c_err <= 1e-3 * w.lr_zernike
+    assert z_err <= 1e-3 * w.lr_z
+    assert abs(float(H(st.loss)[0]) - sum(losses)) <= 1e-5 * sum(losses)
+    # the pupil left in the state is the one of the learned parameters
+    P1 = fo.pupil(pr.mask, pr.zern, H(st.coeffs).astype(np.float64), float(H(st.z_um)[0]),
+                  pr.kappa)
+    assert np.abs(H(st.P) - P1).max() <= 2e-6
+
+
 def test_small_solve_matches_oracle(dev):
     """Full small workload: 7x7 LEDs, 64^2 -> 256^2, B = 8, 20 epochs (140 steps)."""
     w = inputs.workload("small")

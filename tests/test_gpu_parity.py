@@ -341,9 +341,8 @@ def test_step_pupil_parameter_gradients_match_oracle(dev):
 @pytest.mark.parametrize("n_lr,n_side,B", [(128, 11, 16), (128, 9, 5), (192, 11, 16),
                                            (384, 7, 13)])
 def test_factor_three_sizes_backward_and_step_match_oracle(dev, n_lr, n_side, B):
-    """LR sizes 128 (whose step runs the loss and adjoint as one launch, the image
-    in LDS) and 3 * 2^k (radix-12 transforms, HR 768 / 1536): gradients, loss and
-    one object + Zernike step against the oracle."""
+    """LR size 128 and the sizes 3 * 2^k (radix-12 transforms, HR 768 / 1536):
+    gradients, loss and one object + Zernike step against the oracle."""
     w = inputs.workload("small", n_lr=n_lr, n_side=n_side, learn_zernike=True)
     say(f"factor-3 size N={n_lr} grid {n_side}x{n_side} B={B}")
     pr = oracle_problem(w, seed=2)
@@ -589,6 +588,35 @@ def _gradient_at_gpu_state(dev, plan, pr, st, leds, P):
     ref = fo.loss_and_grads(H(st.O).astype(np.complex128), H(P).astype(np.complex128),
                             pr.shifts, leds, pr.A.astype(np.float64))
     return assert_grad_close(H(gO), ref.g_O)
+
+
+@pytest.mark.parametrize("n_lr,n_side,B", [(128, 9, 16), (384, 7, 13)])
+def test_short_solves_at_other_sizes_match_oracle(dev, n_lr, n_side, B):
+    """Two epochs of object + Zernike steps through fpm_run at LR sizes 128 and
+    384 (HR 512 and 1536, the latter with radix-12 transforms) against the
+    oracle's solve of the same schedule: final object within 1e-3, the Zernike
+    coefficients within 1e-3 of their learning rate."""
+    w = inputs.workload("small", n_lr=n_lr, n_side=n_side, batch=B, learn_zernike=True)
+    say(f"short solve N={n_lr} grid {n_side}x{n_side} B={B}")
+    pr = oracle_problem(w, seed=6)
+    perms = inputs.led_permutations(w.n_led, 2, seed=n_lr)
+    sched = fo.batches_from_permutations(perms, B)
+    plan = make_plan(w, pr.shifts, B)
+    st = fpm.State(plan, T(pr.O0, dev), np.zeros(15), 0.0)
+    ds = problem.flatten_schedule(problem.schedule(perms, B))
+    plan.run(st, problem.hparams(w), ds.flat, ds.sizes, T(pr.A, dev))
+    torch.cuda.synchronize()
+    ost = fo.init_state(pr.O0)
+    cfg = fo.SolveConfig(lr_object=w.lr_object, lr_zernike=w.lr_zernike, learn_pupil=True)
+    losses = fo.solve(ost, cfg, pr.mask, pr.zern, pr.kappa, pr.shifts, sched,
+                      pr.A.astype(np.float64))
+    err = rel_l2(H(st.O), ost.O)
+    c_err = float(np.abs(H(st.coeffs).astype(np.float64) - ost.coeffs).max())
+    say(f"{len(sched)} steps: final object rel err {err:.3e}, max Zernike diff {c_err:.2e} rad")
+    assert st.t == len(sched)
+    assert err <= OBJ_TOL
+    assert c_err <= 1e-3 * w.lr_zernike
+    assert abs(float(H(st.loss)[0]) - sum(losses)) <= 1e-5 * sum(losses)
 
 
 def test_intensity_loss_solve_with_pupil_learning_matches_oracle(dev):

@@ -190,6 +190,34 @@ def _psnr(x, ref) -> float:
     return float("inf") if mse == 0 else 10.0 * math.log10(peak * peak / mse)
 
 
+def full_solves(w, prob, hp, warm: int = 2, timed: int = 5) -> dict:
+    """The whole solve of the workload (every epoch's random batches, Eqs.
+    13-14) from its initial spectrum, `warm` untimed then `timed` timed runs
+    (HIP events around each, inputs resident): the median and every time."""
+    import numpy as np
+    import torch
+    from paper_2408_13782_amd import fpm, inputs, problem
+    plan = prob.plan
+    sched = problem.flatten_schedule(problem.schedule(
+        inputs.led_permutations(w.n_led, w.epochs, seed=0), w.batch))
+    n_img = int(sched.sizes.sum())
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    times = []
+    for r in range(warm + timed):
+        st = fpm.State(plan, problem.initial_spectrum(prob))
+        go = plan.prepare_run(st, hp, sched.flat, sched.sizes, prob.meas_amp)
+        torch.cuda.synchronize()
+        e0.record()
+        go()
+        e1.record()
+        torch.cuda.synchronize()
+        if r >= warm:
+            times.append(e0.elapsed_time(e1))
+    med = float(np.median(times))
+    return {"steps": int(sched.sizes.size), "led_images": n_img, "ms_median": med,
+            "ms_all": times, "led_images_per_s": n_img / (med / 1e3)}
+
+
 def multiparam_rate(w, prob, steps: int) -> dict:
     """Throughput of the multi-parameter path on the same workload: fpm_loss_grad
     through the autograd function (object, Zernikes, defocus, LED-array
@@ -501,6 +529,10 @@ def main():
         "support_px": S, "union_px": U,
     }
     if not w.learn_geometry:
+        detail["full_solve"] = full_solves(w, prob, hp)
+        fs = detail["full_solve"]
+        log(f"whole solve ({fs['steps']} steps, {fs['led_images']} LED-images): median of 5 "
+            f"{fs['ms_median']:.2f} ms, {fs['led_images_per_s']:.4g} LED-images/s")
         if args.sweep_in_detail:
             detail["fwd_bwd_by_batch"] = chain_by_batch(w, (16, 64))
             log("fwd+bwd chain by batch: " + ", ".join(
